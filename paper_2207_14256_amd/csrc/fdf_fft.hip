@@ -1,0 +1,534 @@
+// Potential grids and power spectra: Fourier stage + 3-D Stockham FFTs (gfx950).
+//
+// Inverse direction (grid build, sec. 2.1 "potential grids"): delta_0(k) is
+// multiplied by the transfer functions and i k_a, then transformed by three
+// LDS-resident passes:
+//   X pass  : strided C2C along x, fused with the Fourier-stage multipliers;
+//             one block = NB consecutive z-columns of one y row, all x;
+//   Y pass  : strided C2C along y, in place;
+//   Z pass  : contiguous C2R along z through a half-length complex FFT,
+//             writing all slots of a cell together (packed [G^3][nslot]).
+// Forward direction (P(k), sec. 4): Z pass R2C, Y pass, then an X pass that
+// bins Re(A conj B) into log-spaced |k| bins directly from LDS.
+//
+// Half-complex intermediates keep only n_z in [0, G/2): every Nyquist mode
+// of delta_0 is zero, and the spectrum bins stop below k_N, so the n_z = G/2
+// plane is never needed.
+//
+// Stockham stage (radix R, Ns = product of earlier radices), for butterfly j:
+//   v_r = in[j + r N/R] * W_{Ns R}^{r (j mod Ns)},  v = DFT_R(v),
+//   out[(j/Ns) Ns R + (j mod Ns) + r Ns] = v_r.
+#include <type_traits>
+
+#include "fdf_device.h"
+#include "fdf_internal.h"
+
+namespace fdf {
+namespace {
+
+// ------------------------------------------------------------ butterflies --
+template <bool INV, typename R>
+__device__ __forceinline__ void bfly2(cplx<R>* v) {
+  cplx<R> a = cadd(v[0], v[1]), b = csub(v[0], v[1]);
+  v[0] = a; v[1] = b;
+}
+
+template <bool INV, typename R>
+__device__ __forceinline__ void bfly4(cplx<R>& v0, cplx<R>& v1, cplx<R>& v2, cplx<R>& v3) {
+  cplx<R> a0 = cadd(v0, v2), a1 = csub(v0, v2), a2 = cadd(v1, v3), a3 = csub(v1, v3);
+  v0 = cadd(a0, a2);
+  v2 = csub(a0, a2);
+  if (INV) {  // X1 = a1 + i a3, X3 = a1 - i a3
+    v1 = {a1.x - a3.y, a1.y + a3.x};
+    v3 = {a1.x + a3.y, a1.y - a3.x};
+  } else {    // X1 = a1 - i a3, X3 = a1 + i a3
+    v1 = {a1.x + a3.y, a1.y - a3.x};
+    v3 = {a1.x - a3.y, a1.y + a3.x};
+  }
+}
+
+template <bool INV, typename R>
+__device__ __forceinline__ void bfly8(cplx<R>* v) {
+  const R c = (R)0.70710678118654752440084436210484903928;
+  cplx<R> e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+  cplx<R> o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+  bfly4<INV>(e0, e1, e2, e3);
+  bfly4<INV>(o0, o1, o2, o3);
+  cplx<R> t1, t2, t3;
+  if (INV) {  // W8^s = e^{+i pi s/4}
+    t1 = {c * (o1.x - o1.y), c * (o1.x + o1.y)};
+    t2 = {-o2.y, o2.x};
+    t3 = {-c * (o3.x + o3.y), c * (o3.x - o3.y)};
+  } else {    // W8^s = e^{-i pi s/4}
+    t1 = {c * (o1.x + o1.y), c * (o1.y - o1.x)};
+    t2 = {o2.y, -o2.x};
+    t3 = {c * (o3.y - o3.x), -c * (o3.x + o3.y)};
+  }
+  v[0] = cadd(e0, o0); v[4] = csub(e0, o0);
+  v[1] = cadd(e1, t1); v[5] = csub(e1, t1);
+  v[2] = cadd(e2, t2); v[6] = csub(e2, t2);
+  v[3] = cadd(e3, t3); v[7] = csub(e3, t3);
+}
+
+template <int RAD, bool INV, typename R>
+__device__ __forceinline__ void bfly(cplx<R>* v) {
+  if constexpr (RAD == 8) bfly8<INV>(v);
+  else if constexpr (RAD == 4) bfly4<INV>(v[0], v[1], v[2], v[3]);
+  else bfly2<INV>(v);
+}
+
+// ------------------------------------------------------------ LDS stages --
+// buf holds NB lines of length N with element n of line b at buf[n*NB + b].
+// tw is the global table e^{-2 pi i m / G}; the length-N root of unity
+// W_N^m is tw[m * TWS] with TWS = G / N.
+template <typename R, int N, int NB, int NT, bool INV, int NS, int RAD, int TWS>
+__device__ __forceinline__ void fft_stage(cplx<R>* buf, const cplx<R>* __restrict__ tw) {
+  constexpr int NBF = NB * (N / RAD);
+  constexpr int PER = (NBF + NT - 1) / NT;
+  cplx<R> v[PER][RAD];
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int p = 0; p < PER; ++p) {
+    const int t = tid + p * NT;
+    if (NBF % NT == 0 || t < NBF) {
+      const int b = t % NB, j = t / NB;
+#pragma unroll
+      for (int r = 0; r < RAD; ++r) v[p][r] = buf[(j + r * (N / RAD)) * NB + b];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int p = 0; p < PER; ++p) {
+    const int t = tid + p * NT;
+    if (NBF % NT == 0 || t < NBF) {
+      const int b = t % NB, j = t / NB;
+      const int k = j % NS;
+      if (NS > 1) {
+#pragma unroll
+        for (int r = 1; r < RAD; ++r) {
+          cplx<R> w = tw[(r * k * (N / (NS * RAD))) * TWS];
+          v[p][r] = INV ? cmulc(v[p][r], w) : cmul(v[p][r], w);
+        }
+      }
+      bfly<RAD, INV>(v[p]);
+      const int base = (j / NS) * NS * RAD + k;
+#pragma unroll
+      for (int r = 0; r < RAD; ++r) buf[(base + r * NS) * NB + b] = v[p][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename R, int N, int NB, int NT, bool INV, int TWS, int NS = 1>
+__device__ __forceinline__ void fft_lines(cplx<R>* buf, const cplx<R>* __restrict__ tw) {
+  if constexpr (NS < N) {
+    constexpr int REM = N / NS;
+    constexpr int RAD = REM >= 8 ? 8 : REM;
+    fft_stage<R, N, NB, NT, INV, NS, RAD, TWS>(buf, tw);
+    fft_lines<R, N, NB, NT, INV, TWS, NS * RAD>(buf, tw);
+  }
+}
+
+// ---------------------------------------------------------- block shapes --
+template <typename R, int G> struct Shape {
+  static constexpr int CS = (int)sizeof(cplx<R>);
+  static constexpr int NB0 = 65536 / (G * CS);
+  static constexpr int NB = NB0 > 16 ? 16 : (NB0 < 1 ? 1 : NB0);     // columns per strided block
+  static constexpr int NBC = NB > G / 2 ? G / 2 : NB;
+  static constexpr int NBX = NBC / 2 > 0 ? NBC / 2 : 1;             // X pass keeps delta_0 in registers
+  static constexpr int NT = 256;
+  static constexpr int M = G / 2;
+  static constexpr int NL0 = 1024 / G;
+  static constexpr int NL1 = NL0 > 16 ? 16 : (NL0 < 1 ? 1 : NL0);
+  static constexpr int NL = NL1 > G ? G : NL1;                        // lines per contiguous block
+};
+
+__device__ __forceinline__ int signed_index(int i, int G) { return i < G / 2 ? i : i - G; }
+
+// Fourier-stage multiplier of one slot at wave numbers (nx, ny, nz).
+__device__ __forceinline__ void slot_multiplier(int kind, int nx, int ny, int nz, double kf,
+                                                const Transfer& tr, double& re, double& im) {
+  re = 0.0; im = 0.0;
+  const double k2 = kf * kf * (double)(nx * nx + ny * ny + nz * nz);
+  if (k2 == 0.0 || kind == SK_ZERO) return;
+  const double tphi = tr.c_phi / k2;
+  if (kind == SK_PHIDOT) { re = tr.c_phidot / k2; return; }
+  double t = tphi;
+  if (kind == SK_DX_PSI || kind == SK_DY_PSI || kind == SK_DZ_PSI || kind == SK_PSI)
+    t = tphi * (1.0 - tr.slip_amp * exp(-sqrt(k2) / tr.slip_k));
+  if (kind == SK_PSI) { re = t; return; }
+  int n = (kind == SK_DX_PSI || kind == SK_DX_PHI) ? nx
+        : (kind == SK_DY_PSI || kind == SK_DY_PHI) ? ny : nz;
+  im = kf * (double)n * t;   // i k_a T
+}
+
+// ------------------------------------------------------------------ X pass --
+template <typename R, int G>
+__global__ void __launch_bounds__(256) k_xpass_inverse(GridBuildArgs a) {
+  using S = Shape<R, G>;
+  constexpr int NB = S::NBX, NT = S::NT, M = S::M;
+  constexpr int PER = (G * NB + NT - 1) / NT;
+  __shared__ cplx<R> buf[G * NB];
+  const int nzb = M / NB;
+  const int iy = blockIdx.x / nzb, iz0 = (blockIdx.x % nzb) * NB;
+  const cplx<R>* __restrict__ din = (const cplx<R>*)a.delta_k;
+  const cplx<R>* __restrict__ tw = (const cplx<R>*)a.twiddle;
+  cplx<R>* scr = (cplx<R>*)a.scratch;
+  const size_t plane = (size_t)G * G * M;
+  cplx<R> d[PER];
+#pragma unroll
+  for (int p = 0; p < PER; ++p) {
+    const int e = threadIdx.x + p * NT;
+    if ((G * NB) % NT == 0 || e < G * NB) {
+      const int ix = e / NB, b = e % NB;
+      d[p] = din[((size_t)ix * G + iy) * M + iz0 + b];
+    }
+  }
+  const int ny = signed_index(iy, G);
+  for (int f = 0; f < a.nfft; ++f) {
+    const int kind = a.kind[f];
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+      const int e = threadIdx.x + p * NT;
+      if ((G * NB) % NT == 0 || e < G * NB) {
+        const int ix = e / NB, b = e % NB;
+        double re, im;
+        slot_multiplier(kind, signed_index(ix, G), ny, iz0 + b, a.kf, a.tr, re, im);
+        const double dx = (double)d[p].x, dy = (double)d[p].y;
+        buf[ix * NB + b] = {(R)(re * dx - im * dy), (R)(re * dy + im * dx)};
+      }
+    }
+    __syncthreads();
+    fft_lines<R, G, NB, NT, true, 1>(buf, tw);
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+      const int e = threadIdx.x + p * NT;
+      if ((G * NB) % NT == 0 || e < G * NB) {
+        const int ix = e / NB, b = e % NB;
+        scr[f * plane + ((size_t)ix * G + iy) * M + iz0 + b] = buf[ix * NB + b];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------- Y pass (either direction) --
+// blocks over (field h, ix, z-column block); lines along y; in place.
+template <typename R, int G, bool INV>
+__global__ void __launch_bounds__(256) k_ypass(cplx<R>* scr, const cplx<R>* __restrict__ tw) {
+  using S = Shape<R, G>;
+  constexpr int NB = S::NBC, NT = S::NT, M = S::M;
+  constexpr int PER = (G * NB + NT - 1) / NT;
+  __shared__ cplx<R> buf[G * NB];
+  const int nzb = M / NB;
+  const int blk = blockIdx.x;
+  const int izb = blk % nzb, ix = (blk / nzb) % G, f = blk / (nzb * G);
+  const int iz0 = izb * NB;
+  cplx<R>* base = scr + (size_t)f * G * G * M + (size_t)ix * G * M + iz0;
+#pragma unroll
+  for (int p = 0; p < PER; ++p) {
+    const int e = threadIdx.x + p * NT;
+    if ((G * NB) % NT == 0 || e < G * NB) {
+      const int iy = e / NB, b = e % NB;
+      buf[iy * NB + b] = base[(size_t)iy * M + b];
+    }
+  }
+  __syncthreads();
+  fft_lines<R, G, NB, NT, INV, 1>(buf, tw);
+#pragma unroll
+  for (int p = 0; p < PER; ++p) {
+    const int e = threadIdx.x + p * NT;
+    if ((G * NB) % NT == 0 || e < G * NB) {
+      const int iy = e / NB, b = e % NB;
+      base[(size_t)iy * M + b] = buf[iy * NB + b];
+    }
+  }
+}
+
+// ------------------------------------------------ Z pass: C2R + slot packing --
+template <int NSLOT, int OT, typename R>
+__device__ __forceinline__ void store_cell(void* out, size_t cell, const R* vals);
+
+template <> __device__ __forceinline__ void store_cell<8, GT_BF16, float>(void* out, size_t cell, const float* v) {
+  uint4 w;
+  w.x = f32_to_bf16_bits(v[0]) | (f32_to_bf16_bits(v[1]) << 16);
+  w.y = f32_to_bf16_bits(v[2]) | (f32_to_bf16_bits(v[3]) << 16);
+  w.z = f32_to_bf16_bits(v[4]) | (f32_to_bf16_bits(v[5]) << 16);
+  w.w = f32_to_bf16_bits(v[6]) | (f32_to_bf16_bits(v[7]) << 16);
+  ((uint4*)out)[cell] = w;
+}
+template <> __device__ __forceinline__ void store_cell<4, GT_BF16, float>(void* out, size_t cell, const float* v) {
+  uint2 w;
+  w.x = f32_to_bf16_bits(v[0]) | (f32_to_bf16_bits(v[1]) << 16);
+  w.y = f32_to_bf16_bits(v[2]) | (f32_to_bf16_bits(v[3]) << 16);
+  ((uint2*)out)[cell] = w;
+}
+template <> __device__ __forceinline__ void store_cell<4, GT_F32, float>(void* out, size_t cell, const float* v) {
+  ((float4*)out)[cell] = make_float4(v[0], v[1], v[2], v[3]);
+}
+template <> __device__ __forceinline__ void store_cell<8, GT_F32, float>(void* out, size_t cell, const float* v) {
+  ((float4*)out)[2 * cell] = make_float4(v[0], v[1], v[2], v[3]);
+  ((float4*)out)[2 * cell + 1] = make_float4(v[4], v[5], v[6], v[7]);
+}
+template <> __device__ __forceinline__ void store_cell<4, GT_F64, double>(void* out, size_t cell, const double* v) {
+  double2* o = (double2*)out + 2 * cell;
+  o[0] = make_double2(v[0], v[1]);
+  o[1] = make_double2(v[2], v[3]);
+}
+template <> __device__ __forceinline__ void store_cell<8, GT_F64, double>(void* out, size_t cell, const double* v) {
+  double2* o = (double2*)out + 4 * cell;
+  o[0] = make_double2(v[0], v[1]);
+  o[1] = make_double2(v[2], v[3]);
+  o[2] = make_double2(v[4], v[5]);
+  o[3] = make_double2(v[6], v[7]);
+}
+
+// blocks over (ix, y-line block of NL lines)
+template <typename R, int G, int NSLOT, int OT>
+__global__ void __launch_bounds__(256) k_zpass_c2r(GridBuildArgs a) {
+  using S = Shape<R, G>;
+  constexpr int NL = S::NL, NT = S::NT, M = S::M;
+  constexpr int PER = (M * NL + NT - 1) / NT;
+  __shared__ cplx<R> buf[M * NL];
+  __shared__ R stage[NL * G * NSLOT];
+  const int nyb = G / NL;
+  const int ix = blockIdx.x / nyb, iy0 = (blockIdx.x % nyb) * NL;
+  const cplx<R>* __restrict__ tw = (const cplx<R>*)a.twiddle;
+  const cplx<R>* scr = (const cplx<R>*)a.scratch;
+  const size_t plane = (size_t)G * G * M;
+  for (int e = threadIdx.x; e < NL * G * NSLOT; e += NT) stage[e] = (R)0;
+  for (int f = 0; f < a.nfft; ++f) {
+    const int slot = a.slot[f];
+    cplx<R> x[PER];
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {   // coalesced: consecutive threads, consecutive k
+      const int e = threadIdx.x + p * NT;
+      if ((M * NL) % NT == 0 || e < M * NL) {
+        const int line = e / M, k = e % M;
+        x[p] = scr[f * plane + ((size_t)ix * G + iy0 + line) * M + k];
+      }
+    }
+    __syncthreads();   // previous field's results have left buf
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+      const int e = threadIdx.x + p * NT;
+      if ((M * NL) % NT == 0 || e < M * NL) {
+        const int line = e / M, k = e % M;
+        buf[k * NL + line] = x[p];
+      }
+    }
+    __syncthreads();
+    // Z[k] = (X[k] + conj X[M-k]) + i e^{2 pi i k/G} (X[k] - conj X[M-k]), X[M] = 0
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+      const int e = threadIdx.x + p * NT;
+      if ((M * NL) % NT == 0 || e < M * NL) {
+        const int line = e / M, k = e % M;
+        cplx<R> xk = x[p];
+        cplx<R> xm = k ? buf[(M - k) * NL + line] : cplx<R>{(R)0, (R)0};
+        cplx<R> s = {xk.x + xm.x, xk.y - xm.y};          // X[k] + conj X[M-k]
+        cplx<R> d = {xk.x - xm.x, xk.y + xm.y};          // X[k] - conj X[M-k]
+        cplx<R> w = tw[k];                               // e^{-2 pi i k/G}
+        cplx<R> wd = cmulc(d, w);                        // d e^{+2 pi i k/G}
+        x[p] = {s.x - wd.y, s.y + wd.x};                 // s + i wd
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+      const int e = threadIdx.x + p * NT;
+      if ((M * NL) % NT == 0 || e < M * NL) {
+        const int line = e / M, k = e % M;
+        buf[k * NL + line] = x[p];
+      }
+    }
+    __syncthreads();
+    fft_lines<R, M, NL, NT, true, 2>(buf, tw);
+    for (int e = threadIdx.x; e < M * NL; e += NT) {
+      const int line = e / M, m = e % M;
+      cplx<R> z = buf[m * NL + line];
+      stage[(line * G + 2 * m) * NSLOT + slot] = z.x;
+      stage[(line * G + 2 * m + 1) * NSLOT + slot] = z.y;
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < NL * G; e += NT) {
+    const int line = e / G, iz = e % G;
+    const size_t cell = ((size_t)ix * G + iy0 + line) * G + iz;
+    store_cell<NSLOT, OT, R>(a.out, cell, &stage[e * NSLOT]);
+  }
+}
+
+// ---------------------------------------------------- forward Z pass: R2C --
+// blocks over (half h, ix, y-line block)
+template <typename R, int G>
+__global__ void __launch_bounds__(256) k_zpass_r2c(PkArgs a) {
+  using S = Shape<R, G>;
+  constexpr int NL = S::NL, NT = S::NT, M = S::M;
+  constexpr int PER = (M * NL + NT - 1) / NT;
+  __shared__ cplx<R> buf[M * NL];
+  const int nyb = G / NL;
+  const int blk = blockIdx.x;
+  const int h = blk / (G * nyb);
+  const int ix = (blk / nyb) % G, iy0 = (blk % nyb) * NL;
+  const cplx<R>* __restrict__ tw = (const cplx<R>*)a.twiddle;
+  const cplx<R>* src = (const cplx<R>*)(h ? a.grid_b : a.grid_a);   // reals read in pairs
+  cplx<R>* dst = (cplx<R>*)a.scratch + (size_t)h * G * G * M;
+  for (int e = threadIdx.x; e < M * NL; e += NT) {
+    const int line = e / M, m = e % M;
+    buf[m * NL + line] = src[((size_t)ix * G + iy0 + line) * M + m];   // z[m] = x[2m] + i x[2m+1]
+  }
+  __syncthreads();
+  fft_lines<R, M, NL, NT, false, 2>(buf, tw);
+  // X[k] = (Z[k] + conj Z[M-k])/2 - (i/2) e^{-2 pi i k/G} (Z[k] - conj Z[M-k]),  Z[M] = Z[0]
+  cplx<R> x[PER];
+#pragma unroll
+  for (int p = 0; p < PER; ++p) {
+    const int e = threadIdx.x + p * NT;
+    if ((M * NL) % NT == 0 || e < M * NL) {
+      const int line = e / M, k = e % M;
+      cplx<R> zk = buf[k * NL + line];
+      cplx<R> zm = buf[((M - k) % M) * NL + line];
+      cplx<R> s = {zk.x + zm.x, zk.y - zm.y};
+      cplx<R> d = {zk.x - zm.x, zk.y + zm.y};
+      cplx<R> wd = cmul(d, tw[k]);                     // d e^{-2 pi i k/G}
+      x[p] = {(R)0.5 * (s.x + wd.y), (R)0.5 * (s.y - wd.x)};   // s/2 - (i/2) wd
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < PER; ++p) {
+    const int e = threadIdx.x + p * NT;
+    if ((M * NL) % NT == 0 || e < M * NL) {
+      const int line = e / M, k = e % M;
+      dst[((size_t)ix * G + iy0 + line) * M + k] = x[p];
+    }
+  }
+}
+
+// --------------------------------------------- forward X pass + log binning --
+template <typename R, int G>
+__global__ void __launch_bounds__(256) k_xpass_bin(PkArgs a) {
+  using S = Shape<R, G>;
+  constexpr int NB0 = S::NBC / 2 > 0 ? S::NBC / 2 : 1;
+  constexpr int NB = NB0, NT = S::NT, M = S::M;
+  __shared__ cplx<R> bufa[G * NB];
+  __shared__ cplx<R> bufb[G * NB];
+  __shared__ double hist[3 * 256];
+  const int nzb = M / NB;
+  const int iy = blockIdx.x / nzb, iz0 = (blockIdx.x % nzb) * NB;
+  const cplx<R>* __restrict__ tw = (const cplx<R>*)a.twiddle;
+  const cplx<R>* scr = (const cplx<R>*)a.scratch;
+  const size_t plane = (size_t)G * G * M;
+  for (int e = threadIdx.x; e < 3 * a.nbins; e += NT) hist[e] = 0.0;
+  for (int e = threadIdx.x; e < G * NB; e += NT) {
+    const int ix = e / NB, b = e % NB;
+    const size_t gi = ((size_t)ix * G + iy) * M + iz0 + b;
+    bufa[ix * NB + b] = scr[gi];
+    if (!a.auto_mode) bufb[ix * NB + b] = scr[plane + gi];
+  }
+  __syncthreads();
+  fft_lines<R, G, NB, NT, false, 1>(bufa, tw);
+  if (!a.auto_mode) fft_lines<R, G, NB, NT, false, 1>(bufb, tw);
+  const cplx<R>* bb = a.auto_mode ? bufa : bufb;
+  const double norm = a.volume / ((double)G * G * G * (double)G * G * G);
+  const double log2h = (double)(31 - __clz(G / 2));
+  const int ny = signed_index(iy, G);
+  for (int e = threadIdx.x; e < G * NB; e += NT) {
+    const int ix = e / NB, b = e % NB;
+    const int nx = signed_index(ix, G), nz = iz0 + b;
+    const long n2 = (long)nx * nx + (long)ny * ny + (long)nz * nz;
+    if (n2 == 0) continue;
+    const int bin = (int)floor((double)a.nbins * log2((double)n2) / (2.0 * log2h));
+    if (bin >= a.nbins) continue;
+    const cplx<R> A = bufa[ix * NB + b], B = bb[ix * NB + b];
+    const double p = norm * ((double)A.x * (double)B.x + (double)A.y * (double)B.y);
+    const double w = nz == 0 ? 1.0 : 2.0;
+    atomicAdd(&hist[bin], w);
+    atomicAdd(&hist[a.nbins + bin], w * a.kf * sqrt((double)n2));
+    atomicAdd(&hist[2 * a.nbins + bin], w * p);
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 3 * a.nbins; e += NT)
+    if (hist[e] != 0.0) atomicAdd(&a.bins[e], hist[e]);
+}
+
+// --------------------------------------------------------------- dispatch --
+template <typename R, int G>
+void build_grids_g(const GridBuildArgs& a, hipStream_t s) {
+  using S = Shape<R, G>;
+  const int nzb = S::M / S::NBC;
+  hipLaunchKernelGGL((k_xpass_inverse<R, G>), dim3(G * (S::M / S::NBX)), dim3(S::NT), 0, s, a);
+  hipLaunchKernelGGL((k_ypass<R, G, true>), dim3(a.nfft * G * nzb), dim3(S::NT), 0, s,
+                     (cplx<R>*)a.scratch, (const cplx<R>*)a.twiddle);
+  const int nyb = G / S::NL;
+  const dim3 zg(G * nyb);
+  if constexpr (std::is_same<R, float>::value) {
+    if (a.out_type == GT_BF16) {
+      if (a.nslot == 8) hipLaunchKernelGGL((k_zpass_c2r<R, G, 8, GT_BF16>), zg, dim3(S::NT), 0, s, a);
+      else hipLaunchKernelGGL((k_zpass_c2r<R, G, 4, GT_BF16>), zg, dim3(S::NT), 0, s, a);
+    } else {
+      if (a.nslot == 8) hipLaunchKernelGGL((k_zpass_c2r<R, G, 8, GT_F32>), zg, dim3(S::NT), 0, s, a);
+      else hipLaunchKernelGGL((k_zpass_c2r<R, G, 4, GT_F32>), zg, dim3(S::NT), 0, s, a);
+    }
+  } else {
+    if (a.nslot == 8) hipLaunchKernelGGL((k_zpass_c2r<R, G, 8, GT_F64>), zg, dim3(S::NT), 0, s, a);
+    else hipLaunchKernelGGL((k_zpass_c2r<R, G, 4, GT_F64>), zg, dim3(S::NT), 0, s, a);
+  }
+}
+
+template <typename R, int G>
+void power_spectrum_g(const PkArgs& a, hipStream_t s) {
+  using S = Shape<R, G>;
+  const int halves = a.auto_mode ? 1 : 2;
+  const int nyb = G / S::NL;
+  hipLaunchKernelGGL((k_zpass_r2c<R, G>), dim3(halves * G * nyb), dim3(S::NT), 0, s, a);
+  const int nzb = S::M / S::NBC;
+  hipLaunchKernelGGL((k_ypass<R, G, false>), dim3(halves * G * nzb), dim3(S::NT), 0, s,
+                     (cplx<R>*)a.scratch, (const cplx<R>*)a.twiddle);
+  constexpr int NBb = S::NBC / 2 > 0 ? S::NBC / 2 : 1;
+  hipLaunchKernelGGL((k_xpass_bin<R, G>), dim3(G * (S::M / NBb)), dim3(S::NT), 0, s, a);
+}
+
+template <typename R>
+void build_grids_r(const GridBuildArgs& a, hipStream_t s) {
+  switch (a.G) {
+    case 8: build_grids_g<R, 8>(a, s); break;
+    case 16: build_grids_g<R, 16>(a, s); break;
+    case 32: build_grids_g<R, 32>(a, s); break;
+    case 64: build_grids_g<R, 64>(a, s); break;
+    case 128: build_grids_g<R, 128>(a, s); break;
+    case 256: build_grids_g<R, 256>(a, s); break;
+    case 512: build_grids_g<R, 512>(a, s); break;
+    case 1024: build_grids_g<R, 1024>(a, s); break;
+    default: break;
+  }
+}
+
+template <typename R>
+void power_spectrum_r(const PkArgs& a, hipStream_t s) {
+  switch (a.G) {
+    case 8: power_spectrum_g<R, 8>(a, s); break;
+    case 16: power_spectrum_g<R, 16>(a, s); break;
+    case 32: power_spectrum_g<R, 32>(a, s); break;
+    case 64: power_spectrum_g<R, 64>(a, s); break;
+    case 128: power_spectrum_g<R, 128>(a, s); break;
+    case 256: power_spectrum_g<R, 256>(a, s); break;
+    case 512: power_spectrum_g<R, 512>(a, s); break;
+    case 1024: power_spectrum_g<R, 1024>(a, s); break;
+    default: break;
+  }
+}
+
+}  // namespace
+
+void launch_build_grids(const GridBuildArgs& a, hipStream_t s) {
+  if (a.fp64) build_grids_r<double>(a, s);
+  else build_grids_r<float>(a, s);
+}
+
+void launch_power_spectrum(const PkArgs& a, hipStream_t s) {
+  if (a.fp64) power_spectrum_r<double>(a, s);
+  else power_spectrum_r<float>(a, s);
+}
+
+}  // namespace fdf

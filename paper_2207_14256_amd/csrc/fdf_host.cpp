@@ -1,0 +1,1016 @@
+// Host runtime and C ABI of the FastDF push (see include/fastdf.h).
+//
+// Host work is FP64 bookkeeping: configuration checks, the constant-Delta-log-a
+// schedule with its conformal-time integrals (sec. 3.3), the sigma_8
+// normalisation of the seeded field, <eps>(a) for the density estimator
+// (sec. 2.2), carving the caller's workspace, and enqueuing kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/fastdf.h"
+#include "fdf_internal.h"
+
+using namespace fdf;
+
+namespace {
+
+constexpr double kCkms = 299792.458;          // speed of light [km/s]
+constexpr double kBoltzmannEvK = 8.617333262e-5;
+constexpr double kTnuKelvin = 1.95;           // present neutrino temperature (sec. 2)
+constexpr double kPi = 3.14159265358979323846;
+constexpr int kMaxBins = 256;
+constexpr size_t kAlign = 256;
+
+double t_nu_ev() { return kTnuKelvin * kBoltzmannEvK; }
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// ---------------------------------------------------------------- quadrature --
+struct GaussLegendre {
+  double x[16], w[16];
+  GaussLegendre() {
+    // nodes of P_16 by Newton's method on the Legendre recurrence
+    const int n = 16;
+    for (int i = 0; i < n; ++i) {
+      long double z = cosl(kPi * (i + 0.75L) / (n + 0.5L)), pp = 0;
+      for (int it = 0; it < 100; ++it) {
+        long double p1 = 1, p2 = 0;
+        for (int j = 1; j <= n; ++j) {
+          long double p3 = p2;
+          p2 = p1;
+          p1 = ((2 * j - 1) * z * p2 - (j - 1) * p3) / j;
+        }
+        pp = n * (z * p1 - p2) / (z * z - 1);
+        long double dz = p1 / pp;
+        z -= dz;
+        if (fabsl(dz) < 1e-19L) break;
+      }
+      x[i] = (double)z;
+      w[i] = (double)(2 / ((1 - z * z) * pp * pp));
+    }
+  }
+  template <class F> double integrate(F f, double lo, double hi, int panels) const {
+    long double sum = 0;
+    const double h = (hi - lo) / panels;
+    for (int p = 0; p < panels; ++p) {
+      const double c = lo + (p + 0.5) * h, r = 0.5 * h;
+      for (int i = 0; i < 16; ++i) sum += (long double)w[i] * r * f(c + r * x[i]);
+    }
+    return (double)sum;
+  }
+};
+const GaussLegendre& gl16() { static GaussLegendre g; return g; }
+
+struct Cosmo {
+  double h, om, orad, ol;
+  double H0() const { return 100.0 * h / kCkms; }
+  double H(double a) const { return H0() * std::sqrt(orad / (a * a * a * a) + om / (a * a * a) + ol); }
+};
+
+// Delta tau = int_{ln a0}^{ln a1} dln a / (a H)  (sec. 3.3, step sizes)
+double dtau(const Cosmo& c, double lna0, double lna1) {
+  const int panels = std::max(1, (int)std::ceil(std::fabs(lna1 - lna0) / 0.02));
+  return gl16().integrate([&](double l) { const double a = std::exp(l); return 1.0 / (a * c.H(a)); },
+                          lna0, lna1, panels);
+}
+
+// tau(a) from a = 0 (the integrand vanishes like a^(1/2) or a as a -> 0)
+double conformal_time(const Cosmo& c, double a) {
+  const double l1 = std::log(a), l0 = l1 - 80.0;
+  return dtau(c, l0, l1);
+}
+
+double bbks(double k, double gamma, double h) {
+  const double q = k / (gamma * h);
+  if (q <= 0) return 1.0;
+  const double b = 16.1 * q, cc = 5.46 * q, d = 6.71 * q;
+  const double poly = 1.0 + 3.89 * q + b * b + cc * cc * cc + (d * d) * (d * d);
+  return std::log1p(2.34 * q) / (2.34 * q) * std::pow(poly, -0.25);
+}
+
+double tophat(double x) {
+  if (std::fabs(x) < 0.1) {
+    const double x2 = x * x;
+    return 1.0 - x2 / 10.0 + x2 * x2 / 280.0 - x2 * x2 * x2 / 15120.0 + x2 * x2 * x2 * x2 / 1330560.0;
+  }
+  return 3.0 * (std::sin(x) - x * std::cos(x)) / (x * x * x);
+}
+
+// A with sigma(8 Mpc/h) = sigma8 for P = A k^ns T_BBKS^2
+double power_amplitude(double sigma8, double ns, double gamma, double h) {
+  const double R = 8.0 / h;
+  auto f_lnk = [&](double l) {
+    const double k = std::exp(l), t = bbks(k, gamma, h), w = tophat(k * R);
+    return k * k * k * std::pow(k, ns) * t * t * w * w;
+  };
+  auto f_k = [&](double k) {
+    const double t = bbks(k, gamma, h), w = tophat(k * R);
+    return k * k * std::pow(k, ns) * t * t * w * w;
+  };
+  double s2 = gl16().integrate(f_lnk, std::log(1e-7), 0.0, 400);
+  s2 += gl16().integrate(f_k, 1.0, 1000.0, 20000);
+  s2 /= 2.0 * kPi * kPi;
+  return sigma8 * sigma8 / s2;
+}
+
+// <eps>(a) = int q^2 sqrt(q^2 + m^2 a^2) fbar / int q^2 fbar  (eq. rho_def normalisation)
+double mean_energy(double m, double a) {
+  const double T = t_nu_ev(), ma = m * a;
+  auto num = [&](double x) { return x * x * std::sqrt(x * x * T * T + ma * ma) / (1.0 + std::exp(x)); };
+  auto den = [&](double x) { return x * x / (1.0 + std::exp(x)); };
+  return gl16().integrate(num, 0.0, 200.0, 800) / gl16().integrate(den, 0.0, 200.0, 800);
+}
+
+// Radiation-to-matter potential factor g(a) = (10/9) Phi(y)/Phi(0), y = a/a_eq,
+// Phi(y)/Phi(0) = 1 - y (s^2 + 4 s + 5) / (10 (s+1)^4), s = sqrt(1+y)
+// (Kodama-Sasaki super-horizon solution without cancellation), and dg/da.
+void radmat_factor(double a, double om, double orad, double* g, double* dg) {
+  const double aeq = orad / om, y = a / aeq, s = std::sqrt(1.0 + y);
+  const double num = y + 6.0 + 4.0 * s, den = std::pow(s + 1.0, 4);
+  const double hfun = y * num / den;
+  const double dnum = 1.0 + 2.0 / s, dden = 4.0 * std::pow(s + 1.0, 3) / (2.0 * s);
+  const double dh = (num + y * dnum) / den - y * num * dden / (den * den);
+  *g = (10.0 / 9.0) * (1.0 - hfun / 10.0);
+  *dg = -(1.0 / 9.0) * dh / aeq;
+}
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+int ilog2(int v) { int r = 0; while ((1 << r) < v) ++r; return r; }
+
+// ----------------------------------------------------------------- layout --
+struct Layout {
+  size_t twiddle_d, twiddle_f, seg, bins, scratch, dens, fields, parts, total;
+  size_t field_dk_bytes, field_grid_bytes, scratch_bytes, dens_bytes, parts_bytes;
+  int nslot;
+};
+
+int slots_for(const fdf_config& c) { return c.slip_amp != 0.0 ? 8 : 4; }
+size_t real_bytes(const fdf_config& c) { return c.precision == FDF_PREC_FP64 ? 8 : 4; }
+size_t slot_bytes(const fdf_config& c) { return c.precision == FDF_PREC_FP64 ? 8 : 2; }
+size_t particle_bytes(const fdf_config& c) { return c.precision == FDF_PREC_FP64 ? 76 : 52; }
+int arrays_per_species(const fdf_config& c) { return c.precision == FDF_PREC_FP64 ? 10 : 13; }
+
+Layout plan(const fdf_config& c) {
+  Layout L{};
+  const size_t G = (size_t)c.grid_n, rb = real_bytes(c), cb = 2 * rb;
+  L.nslot = slots_for(c);
+  L.field_dk_bytes = align_up(G * G * (G / 2) * cb);
+  L.field_grid_bytes = align_up(G * G * G * (size_t)L.nslot * slot_bytes(c));
+  L.scratch_bytes = align_up(7 * G * G * (G / 2) * cb);
+  L.dens_bytes = align_up(4 * G * G * G * rb);   // two halves, or a 4-slot pre-IC grid
+  const int copies = c.sort_every > 0 ? 2 : 1;
+  L.parts_bytes = align_up((size_t)c.max_particles * particle_bytes(c) * copies +
+                           (size_t)c.max_species * arrays_per_species(c) * copies * kAlign);
+  size_t off = 0;
+  L.twiddle_d = off; off += align_up(G * 16);
+  L.twiddle_f = off; off += align_up(G * 8);
+  L.seg = off; off += align_up((size_t)c.max_species * sizeof(Segment));
+  L.bins = off; off += align_up(3 * kMaxBins * sizeof(double));
+  L.scratch = off; off += L.scratch_bytes;
+  L.dens = off; off += L.dens_bytes;
+  L.fields = off; off += (size_t)c.max_fields * (L.field_dk_bytes + L.field_grid_bytes);
+  L.parts = off; off += L.parts_bytes;
+  L.total = off;
+  return L;
+}
+
+const char* validate(const fdf_config* c) {
+  if (!c) return "config is NULL";
+  if (c->abi_version != FDF_ABI_VERSION) return "abi_version mismatch";
+  if (!is_pow2(c->grid_n) || c->grid_n < 8 || c->grid_n > 1024) return "grid_n must be a power of two in [8, 1024]";
+  if (!(c->box_mpc > 0) || !std::isfinite(c->box_mpc)) return "box_mpc must be positive";
+  if (!(c->h > 0)) return "h must be positive";
+  if (c->omega_m < 0 || c->omega_r < 0 || c->omega_l < 0 || c->omega_m + c->omega_r <= 0)
+    return "need omega_m + omega_r > 0 and non-negative densities";
+  if (!(c->z_begin > -1) || !(c->z_end > -1)) return "redshifts must exceed -1";
+  if (c->z_begin == c->z_end) return "z_begin must differ from z_end";
+  if (c->n_steps < 1) return "n_steps must be >= 1";
+  if (c->precision != FDF_PREC_FP64 && c->precision != FDF_PREC_FP32) return "unknown precision";
+  if (c->potential_model != FDF_MODEL_POISSON && c->potential_model != FDF_MODEL_RADMAT) return "unknown potential model";
+  if (c->potential_model == FDF_MODEL_RADMAT && !(c->omega_r > 0)) return "RADMAT needs omega_r > 0";
+  if (c->slip_amp < 0 || c->slip_amp >= 1 || !(c->slip_k > 0)) return "slip_amp in [0,1) and slip_k > 0 required";
+  if (!(c->sigma8 > 0) || !(c->gamma > 0)) return "sigma8 and gamma must be positive";
+  if (c->sort_every < 0) return "sort_every must be >= 0";
+  if (c->max_fields < 1 || c->max_species < 1 || c->max_particles < 1) return "capacities must be >= 1";
+  if (c->max_particles > ((int64_t)1 << 32)) return "at most 2^32 particles";
+  return nullptr;
+}
+
+struct FieldRec {
+  uint64_t seed = 0;
+  void* dk = nullptr;
+  void* grid = nullptr;
+  bool has_grid = false;
+  double grid_a = 0;
+};
+
+struct SpeciesRec {
+  int field = 0;
+  double m = 0;
+  int64_t n = 0;
+  uint64_t seed = 0;
+  int flags = 0;
+  Segment seg[2];   // state buffers (second copy only with sorting)
+  int cur = 0;
+};
+
+struct TimingRec {
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
+  double total_ms = 0;
+  int64_t launches = 0;
+};
+
+}  // namespace
+
+struct fdf_ctx {
+  fdf_config cfg{};
+  Cosmo cos{};
+  hipStream_t stream = nullptr;
+  std::vector<double> a, a_half, kick1, kick2, drift;
+  double amp = 0, tau_begin = 0;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  Layout lay{};
+  size_t field_next = 0, part_next = 0;
+  std::vector<FieldRec> fields;
+  std::vector<SpeciesRec> species;
+  int step_index = 0;
+  bool stepped = false;
+  bool seg_dirty = true;
+  int ppt = 4;
+  std::string err;
+  bool timing = false;
+  TimingRec tim[FDF_KERNEL_COUNT];
+  bool have_density = false;
+  int density_auto = 0;
+};
+
+namespace {
+
+int fail(fdf_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+int hip_check(fdf_ctx* c, hipError_t e, const char* what) {
+  if (e == hipSuccess) return FDF_OK;
+  return fail(c, FDF_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+int launched(fdf_ctx* c, const char* what) { return hip_check(c, hipGetLastError(), what); }
+
+void timing_begin(fdf_ctx* c, int cls, std::pair<hipEvent_t, hipEvent_t>* ev) {
+  if (!c->timing) return;
+  TimingRec& t = c->tim[cls];
+  if (t.pool.empty()) {
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    t.pool.push_back({e0, e1});
+  }
+  *ev = t.pool.back();
+  t.pool.pop_back();
+  (void)hipEventRecord(ev->first, c->stream);
+}
+
+void timing_end(fdf_ctx* c, int cls, std::pair<hipEvent_t, hipEvent_t>& ev) {
+  if (!c->timing) return;
+  (void)hipEventRecord(ev.second, c->stream);
+  c->tim[cls].pending.push_back(ev);
+  c->tim[cls].launches++;
+}
+
+void timing_collect(fdf_ctx* c) {
+  for (auto& t : c->tim) {
+    for (auto& ev : t.pending) {
+      float ms = 0;
+      (void)hipEventSynchronize(ev.second);
+      (void)hipEventElapsedTime(&ms, ev.first, ev.second);
+      t.total_ms += ms;
+      t.pool.push_back(ev);
+    }
+    t.pending.clear();
+  }
+}
+
+bool needs_ws(fdf_ctx* c) { return c->ws != nullptr; }
+
+// Carve the state arrays of one copy of a species.
+bool carve_species(fdf_ctx* c, Segment& s, int64_t n) {
+  const bool f64 = c->cfg.precision == FDF_PREC_FP64;
+  auto take = [&](size_t bytes) -> void* {
+    const size_t sz = align_up(bytes);
+    if (c->part_next + sz > c->lay.parts_bytes) return nullptr;
+    void* p = c->ws + c->lay.parts + c->part_next;
+    c->part_next += sz;
+    return p;
+  };
+  std::memset(&s, 0, sizeof(s));
+  for (int d = 0; d < 3; ++d) {
+    if (f64) {
+      s.xd[d] = (double*)take(n * 8);
+      s.qd[d] = (double*)take(n * 8);
+      s.q0d[d] = (double*)take(n * 8);
+      if (!s.xd[d] || !s.qd[d] || !s.q0d[d]) return false;
+    } else {
+      s.xu[d] = (uint32_t*)take(n * 4);
+      s.qf[d] = (float*)take(n * 4);
+      s.cf[d] = (float*)take(n * 4);
+      s.q0f[d] = (float*)take(n * 4);
+      if (!s.xu[d] || !s.qf[d] || !s.cf[d] || !s.q0f[d]) return false;
+    }
+  }
+  s.id = (uint32_t*)take(n * 4);
+  s.n = n;
+  return s.id != nullptr;
+}
+
+GridBuildArgs grid_recipe(fdf_ctx* c, const FieldRec& f, double a, bool pre_ic_grid) {
+  GridBuildArgs g{};
+  const fdf_config& cf = c->cfg;
+  g.G = cf.grid_n;
+  g.fp64 = cf.precision == FDF_PREC_FP64;
+  g.kf = 2.0 * kPi / cf.box_mpc;
+  const double base = -1.5 * c->cos.H0() * c->cos.H0() * cf.omega_m;   // Poisson: D(a)/a = 1
+  double gf = 1.0, dgf = 0.0;
+  if (cf.potential_model == FDF_MODEL_RADMAT) radmat_factor(a, cf.omega_m, cf.omega_r, &gf, &dgf);
+  g.tr.c_phi = base * gf;
+  g.tr.c_phidot = base * (a * a * c->cos.H(a) * dgf);
+  g.tr.slip_amp = cf.slip_amp;
+  g.tr.slip_k = cf.slip_k;
+  g.delta_k = f.dk;
+  g.scratch = c->ws + c->lay.scratch;
+  g.twiddle = c->ws + (g.fp64 ? c->lay.twiddle_d : c->lay.twiddle_f);
+  const bool phidot = cf.potential_model == FDF_MODEL_RADMAT;
+  int n = 0;
+  if (pre_ic_grid) {
+    g.nslot = 4;
+    g.out_type = g.fp64 ? GT_F64 : GT_F32;
+    const int kinds[4] = {SK_DX_PSI, SK_DY_PSI, SK_DZ_PSI, SK_PSI};
+    for (int i = 0; i < 4; ++i) { g.kind[n] = kinds[i]; g.slot[n] = i; ++n; }
+    g.out = c->ws + c->lay.dens;
+  } else {
+    g.nslot = c->lay.nslot;
+    g.out_type = g.fp64 ? GT_F64 : GT_BF16;
+    g.out = f.grid;
+    g.kind[n] = SK_DX_PSI; g.slot[n++] = 0;
+    g.kind[n] = SK_DY_PSI; g.slot[n++] = 1;
+    g.kind[n] = SK_DZ_PSI; g.slot[n++] = 2;
+    if (g.nslot == 8) {
+      g.kind[n] = SK_DX_PHI; g.slot[n++] = 3;
+      g.kind[n] = SK_DY_PHI; g.slot[n++] = 4;
+      g.kind[n] = SK_DZ_PHI; g.slot[n++] = 5;
+      if (phidot) { g.kind[n] = SK_PHIDOT; g.slot[n++] = 6; }
+    } else if (phidot) {
+      g.kind[n] = SK_PHIDOT; g.slot[n++] = 3;
+    }
+  }
+  g.nfft = n;
+  return g;
+}
+
+int build_grid(fdf_ctx* c, int field, double a) {
+  FieldRec& f = c->fields[field];
+  GridBuildArgs g = grid_recipe(c, f, a, false);
+  std::pair<hipEvent_t, hipEvent_t> ev;
+  timing_begin(c, FDF_KERNEL_GRID, &ev);
+  launch_build_grids(g, c->stream);
+  timing_end(c, FDF_KERNEL_GRID, ev);
+  f.has_grid = true;
+  f.grid_a = a;
+  return launched(c, "grid build");
+}
+
+int upload_segments(fdf_ctx* c) {
+  if (!c->seg_dirty) return FDF_OK;
+  std::vector<Segment> segs;
+  int64_t chunk = 0;
+  const int64_t per = push_chunk_particles(c->ppt);
+  for (auto& s : c->species) {
+    Segment g = s.seg[s.cur];
+    g.grid = c->fields[s.field].grid;
+    g.m = s.m;
+    g.chunk_begin = chunk;
+    chunk += (s.n + per - 1) / per;
+    segs.push_back(g);
+  }
+  int rc = hip_check(c, hipMemcpyAsync(c->ws + c->lay.seg, segs.data(), segs.size() * sizeof(Segment),
+                                       hipMemcpyHostToDevice, c->stream), "segment upload");
+  if (rc) return rc;
+  rc = hip_check(c, hipStreamSynchronize(c->stream), "segment upload");
+  c->seg_dirty = false;
+  return rc;
+}
+
+int64_t total_chunks(fdf_ctx* c) {
+  const int64_t per = push_chunk_particles(c->ppt);
+  int64_t t = 0;
+  for (auto& s : c->species) t += (s.n + per - 1) / per;
+  return t;
+}
+
+OutputArgs output_args(fdf_ctx* c, const SpeciesRec& s) {
+  OutputArgs o{};
+  o.seg = s.seg[s.cur];
+  o.fp64 = c->cfg.precision == FDF_PREC_FP64;
+  o.G = c->cfg.grid_n;
+  o.pre_ic = (s.flags & FDF_SPECIES_PRE_IC) != 0;
+  o.seed = s.seed;
+  o.t_nu = t_nu_ev();
+  o.box = c->cfg.box_mpc;
+  o.a = c->a[c->step_index];
+  o.m = s.m;
+  return o;
+}
+
+void fill_twiddles(fdf_ctx* c) {
+  const int G = c->cfg.grid_n;
+  std::vector<double> td(2 * G);
+  std::vector<float> tf(2 * G);
+  for (int m = 0; m < G; ++m) {
+    const long double ang = -2.0L * 3.141592653589793238462643383279502884L * m / G;
+    td[2 * m] = (double)cosl(ang);
+    td[2 * m + 1] = (double)sinl(ang);
+    tf[2 * m] = (float)cosl(ang);
+    tf[2 * m + 1] = (float)sinl(ang);
+  }
+  (void)hipMemcpy(c->ws + c->lay.twiddle_d, td.data(), td.size() * 8, hipMemcpyHostToDevice);
+  (void)hipMemcpy(c->ws + c->lay.twiddle_f, tf.data(), tf.size() * 4, hipMemcpyHostToDevice);
+}
+
+int add_field_slot(fdf_ctx* c, int32_t* id) {
+  if ((int)c->fields.size() >= c->cfg.max_fields) return fail(c, FDF_ERR_CAPACITY, "max_fields reached");
+  FieldRec f;
+  char* base = c->ws + c->lay.fields + c->field_next;
+  f.dk = base;
+  f.grid = base + c->lay.field_dk_bytes;
+  c->field_next += c->lay.field_dk_bytes + c->lay.field_grid_bytes;
+  c->fields.push_back(f);
+  *id = (int32_t)c->fields.size() - 1;
+  return FDF_OK;
+}
+
+int new_species(fdf_ctx* c, int32_t field_id, double m, int64_t n, uint64_t seed, int flags, int32_t* sid) {
+  if (field_id < 0 || field_id >= (int)c->fields.size()) return fail(c, FDF_ERR_ARG, "bad field id");
+  if (!(m >= 0) || !std::isfinite(m)) return fail(c, FDF_ERR_ARG, "mass must be finite and >= 0");
+  if (n < 1) return fail(c, FDF_ERR_ARG, "need at least one particle");
+  if (c->stepped) return fail(c, FDF_ERR_STATE, "species must be added before the first step");
+  if ((int)c->species.size() >= c->cfg.max_species) return fail(c, FDF_ERR_CAPACITY, "max_species reached");
+  int64_t tot = n;
+  for (auto& s : c->species) tot += s.n;
+  if (tot > c->cfg.max_particles) return fail(c, FDF_ERR_CAPACITY, "max_particles exceeded");
+  SpeciesRec s;
+  s.field = field_id; s.m = m; s.n = n; s.seed = seed; s.flags = flags;
+  const size_t save = c->part_next;
+  if (!carve_species(c, s.seg[0], n)) { c->part_next = save; return fail(c, FDF_ERR_CAPACITY, "workspace particles full"); }
+  if (c->cfg.sort_every > 0 && !carve_species(c, s.seg[1], n)) {
+    c->part_next = save;
+    return fail(c, FDF_ERR_CAPACITY, "workspace particles full");
+  }
+  c->species.push_back(s);
+  c->seg_dirty = true;
+  *sid = (int32_t)c->species.size() - 1;
+  return FDF_OK;
+}
+
+}  // namespace
+
+// ============================================================== C ABI ======
+extern "C" {
+
+const char* fdf_status_string(int s) {
+  switch (s) {
+    case FDF_OK: return "ok";
+    case FDF_ERR_ARG: return "invalid argument";
+    case FDF_ERR_STATE: return "invalid state";
+    case FDF_ERR_WORKSPACE: return "workspace missing or too small";
+    case FDF_ERR_HIP: return "HIP runtime error";
+    case FDF_ERR_CAPACITY: return "capacity exceeded";
+    case FDF_ERR_UNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+  }
+}
+
+const char* fdf_last_error(const fdf_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int fdf_workspace_size(const fdf_config* cfg, size_t* bytes) {
+  if (validate(cfg) || !bytes) return FDF_ERR_ARG;
+  *bytes = plan(*cfg).total;
+  return FDF_OK;
+}
+
+int fdf_create(const fdf_config* cfg, void* stream, fdf_ctx** out) {
+  if (!out) return FDF_ERR_ARG;
+  *out = nullptr;
+  if (validate(cfg)) return FDF_ERR_ARG;
+  fdf_ctx* c = new fdf_ctx();
+  c->cfg = *cfg;
+  c->cos = Cosmo{cfg->h, cfg->omega_m, cfg->omega_r, cfg->omega_l};
+  c->stream = (hipStream_t)stream;
+  c->lay = plan(*cfg);
+  const int n = cfg->n_steps;
+  const double lai = std::log(1.0 / (1.0 + cfg->z_begin)), laf = std::log(1.0 / (1.0 + cfg->z_end));
+  const double dl = (laf - lai) / n;
+  c->a.resize(n + 1);
+  c->a_half.resize(n);
+  c->kick1.resize(n);
+  c->kick2.resize(n);
+  c->drift.resize(n);
+  for (int k = 0; k <= n; ++k) c->a[k] = std::exp(lai + dl * k);
+  double max_drift = 0;
+  for (int k = 0; k < n; ++k) {
+    const double l0 = lai + dl * k, lh = lai + dl * (k + 0.5), l1 = lai + dl * (k + 1);
+    c->a_half[k] = std::exp(lh);
+    c->kick1[k] = dtau(c->cos, l0, lh);
+    c->kick2[k] = dtau(c->cos, lh, l1);
+    c->drift[k] = dtau(c->cos, l0, l1);
+    max_drift = std::max(max_drift, std::fabs(c->drift[k]));
+  }
+  if (!(max_drift < 0.5 * cfg->box_mpc)) {   // fixed-point drift must stay below half a box
+    delete c;
+    return FDF_ERR_ARG;
+  }
+  c->amp = power_amplitude(cfg->sigma8, cfg->ns, cfg->gamma, cfg->h);
+  c->tau_begin = conformal_time(c->cos, c->a[0]);
+  *out = c;
+  return FDF_OK;
+}
+
+int fdf_attach_workspace(fdf_ctx* c, void* dptr, size_t bytes) {
+  if (!c) return FDF_ERR_ARG;
+  if (!dptr || ((uintptr_t)dptr % kAlign) != 0) return fail(c, FDF_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  if (bytes < c->lay.total) return fail(c, FDF_ERR_WORKSPACE, "workspace too small");
+  c->ws = (char*)dptr;
+  c->ws_bytes = bytes;
+  fill_twiddles(c);
+  return fdf_reset(c);
+}
+
+int fdf_reset(fdf_ctx* c) {
+  if (!c) return FDF_ERR_ARG;
+  c->fields.clear();
+  c->species.clear();
+  c->field_next = 0;
+  c->part_next = 0;
+  c->step_index = 0;
+  c->stepped = false;
+  c->seg_dirty = true;
+  c->have_density = false;
+  return FDF_OK;
+}
+
+int fdf_destroy(fdf_ctx* c) {
+  if (!c) return FDF_ERR_ARG;
+  (void)hipStreamSynchronize(c->stream);
+  for (auto& t : c->tim) {
+    for (auto& e : t.pending) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
+    for (auto& e : t.pool) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
+  }
+  delete c;
+  return FDF_OK;
+}
+
+int fdf_add_field(fdf_ctx* c, uint64_t seed, int32_t fixed_amp, int32_t* field_id) {
+  if (!c || !field_id) return FDF_ERR_ARG;
+  if (!needs_ws(c)) return fail(c, FDF_ERR_WORKSPACE, "no workspace attached");
+  int rc = add_field_slot(c, field_id);
+  if (rc) return rc;
+  FieldRec& f = c->fields.back();
+  f.seed = seed;
+  FieldGenArgs g{};
+  g.G = c->cfg.grid_n;
+  g.fp64 = c->cfg.precision == FDF_PREC_FP64;
+  g.fixed_amp = fixed_amp;
+  g.seed = seed;
+  g.box = c->cfg.box_mpc;
+  g.amp = c->amp;
+  g.ns = c->cfg.ns;
+  g.gamma = c->cfg.gamma;
+  g.h = c->cfg.h;
+  g.out = f.dk;
+  std::pair<hipEvent_t, hipEvent_t> ev;
+  timing_begin(c, FDF_KERNEL_INIT, &ev);
+  launch_field_gen(g, c->stream);
+  timing_end(c, FDF_KERNEL_INIT, ev);
+  return launched(c, "field generation");
+}
+
+int fdf_set_field(fdf_ctx* c, const double* h, int32_t* field_id) {
+  if (!c || !h || !field_id) return FDF_ERR_ARG;
+  if (!needs_ws(c)) return fail(c, FDF_ERR_WORKSPACE, "no workspace attached");
+  int rc = add_field_slot(c, field_id);
+  if (rc) return rc;
+  const int G = c->cfg.grid_n, M = G / 2, H = G / 2 + 1;
+  const bool f64 = c->cfg.precision == FDF_PREC_FP64;
+  std::vector<double> d((size_t)G * G * M * 2);
+  std::vector<float> f(f64 ? 0 : d.size());
+  for (int ix = 0; ix < G; ++ix)
+    for (int iy = 0; iy < G; ++iy)
+      for (int iz = 0; iz < M; ++iz) {
+        const size_t src = (((size_t)ix * G + iy) * H + iz) * 2, dst = (((size_t)ix * G + iy) * M + iz) * 2;
+        const bool nyq = ix == M || iy == M;
+        d[dst] = nyq ? 0.0 : h[src];
+        d[dst + 1] = nyq ? 0.0 : h[src + 1];
+      }
+  if (!f64) for (size_t i = 0; i < d.size(); ++i) f[i] = (float)d[i];
+  rc = hip_check(c, hipMemcpyAsync(c->fields.back().dk, f64 ? (void*)d.data() : (void*)f.data(),
+                                   d.size() * (f64 ? 8 : 4), hipMemcpyHostToDevice, c->stream), "field upload");
+  if (rc) return rc;
+  return hip_check(c, hipStreamSynchronize(c->stream), "field upload");
+}
+
+int fdf_init_species(fdf_ctx* c, int32_t field_id, double m, int64_t n, uint64_t seed, int32_t flags,
+                     int32_t* species_id) {
+  if (!c || !species_id) return FDF_ERR_ARG;
+  if (!needs_ws(c)) return fail(c, FDF_ERR_WORKSPACE, "no workspace attached");
+  if (flags & ~FDF_SPECIES_PRE_IC) return fail(c, FDF_ERR_ARG, "unknown species flag");
+  int rc = new_species(c, field_id, m, n, seed, flags, species_id);
+  if (rc) return rc;
+  SpeciesRec& s = c->species.back();
+  SampleArgs sa{};
+  sa.seg = s.seg[0];
+  sa.fp64 = c->cfg.precision == FDF_PREC_FP64;
+  sa.seed = seed;
+  sa.box = c->cfg.box_mpc;
+  sa.t_nu = t_nu_ev();
+  std::pair<hipEvent_t, hipEvent_t> ev;
+  timing_begin(c, FDF_KERNEL_INIT, &ev);
+  launch_sample_species(sa, c->stream);
+  if (flags & FDF_SPECIES_PRE_IC) {
+    GridBuildArgs g = grid_recipe(c, c->fields[field_id], c->a[0], true);
+    launch_build_grids(g, c->stream);
+    PreIcArgs p{};
+    p.seg = s.seg[0];
+    p.fp64 = sa.fp64;
+    p.G = c->cfg.grid_n;
+    p.box = c->cfg.box_mpc;
+    p.m = m;
+    p.a = c->a[0];
+    p.tau = c->tau_begin;
+    p.grid = g.out;
+    launch_pre_ic(p, c->stream);
+  }
+  timing_end(c, FDF_KERNEL_INIT, ev);
+  return launched(c, "species sampling");
+}
+
+int fdf_set_species_state(fdf_ctx* c, int32_t field_id, double m, int64_t n, const uint32_t* xu,
+                          const float* q, int32_t* species_id) {
+  if (!c || !xu || !q || !species_id) return FDF_ERR_ARG;
+  if (!needs_ws(c)) return fail(c, FDF_ERR_WORKSPACE, "no workspace attached");
+  int rc = new_species(c, field_id, m, n, 0, 0, species_id);
+  if (rc) return rc;
+  Segment& s = c->species.back().seg[0];
+  const bool f64 = c->cfg.precision == FDF_PREC_FP64;
+  std::vector<uint32_t> ids(n);
+  for (int64_t i = 0; i < n; ++i) ids[i] = (uint32_t)i;
+  std::vector<double> dd(f64 ? n : 0);
+  std::vector<float> ff(f64 ? 0 : n), zero(f64 ? 0 : n, 0.0f);
+  std::vector<uint32_t> uu(f64 ? 0 : n);
+  auto put = [&](void* dst, const void* src, size_t bytes) {
+    return hip_check(c, hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice), "state upload");
+  };
+  for (int d = 0; d < 3 && !rc; ++d) {
+    if (f64) {
+      for (int64_t i = 0; i < n; ++i) dd[i] = (double)xu[3 * i + d] * (c->cfg.box_mpc * 0x1p-32);
+      rc = put(s.xd[d], dd.data(), n * 8);
+      for (int64_t i = 0; i < n; ++i) dd[i] = (double)q[3 * i + d];
+      if (!rc) rc = put(s.qd[d], dd.data(), n * 8);
+      if (!rc) rc = put(s.q0d[d], dd.data(), n * 8);
+    } else {
+      for (int64_t i = 0; i < n; ++i) { uu[i] = xu[3 * i + d]; ff[i] = q[3 * i + d]; }
+      rc = put(s.xu[d], uu.data(), n * 4);
+      if (!rc) rc = put(s.qf[d], ff.data(), n * 4);
+      if (!rc) rc = put(s.q0f[d], ff.data(), n * 4);
+      if (!rc) rc = put(s.cf[d], zero.data(), n * 4);
+    }
+  }
+  if (!rc) rc = put(s.id, ids.data(), n * 4);
+  return rc;
+}
+
+int fdf_build_potential_grids(fdf_ctx* c, int32_t field_id, double a) {
+  if (!c) return FDF_ERR_ARG;
+  if (!needs_ws(c)) return fail(c, FDF_ERR_WORKSPACE, "no workspace attached");
+  if (field_id < 0 || field_id >= (int)c->fields.size()) return fail(c, FDF_ERR_ARG, "bad field id");
+  if (!(a > 0) || !std::isfinite(a)) return fail(c, FDF_ERR_ARG, "a must be positive");
+  return build_grid(c, field_id, a);
+}
+
+int fdf_step(fdf_ctx* c, int32_t n) {
+  if (!c) return FDF_ERR_ARG;
+  if (!needs_ws(c)) return fail(c, FDF_ERR_WORKSPACE, "no workspace attached");
+  if (c->species.empty()) return fail(c, FDF_ERR_STATE, "no species");
+  const int k0 = c->step_index, nabs = std::abs(n);
+  if (n == 0) return FDF_OK;
+  if (k0 + n < 0 || k0 + n > c->cfg.n_steps) return fail(c, FDF_ERR_ARG, "step range outside the schedule");
+  const bool tdep = c->cfg.potential_model == FDF_MODEL_RADMAT;
+  int rc = upload_segments(c);
+  if (rc) return rc;
+  std::vector<int> used(c->fields.size(), 0);
+  for (auto& s : c->species) used[s.field] = 1;
+  PushArgs pa{};
+  pa.seg = (const Segment*)(c->ws + c->lay.seg);
+  pa.nseg = (int)c->species.size();
+  pa.total_chunks = total_chunks(c);
+  pa.fp64 = c->cfg.precision == FDF_PREC_FP64;
+  pa.nslot = c->lay.nslot;
+  pa.G = c->cfg.grid_n;
+  pa.log2g = ilog2(c->cfg.grid_n);
+  pa.box = c->cfg.box_mpc;
+  pa.ppt = c->ppt;
+  pa.do_kick = 1;
+  for (int j = 0; j <= nabs; ++j) {
+    int t;            // integer time of this launch's kick
+    double kick = 0, drift = 0, a_drift = 0;
+    if (n > 0) {
+      t = k0 + j;
+      if (j > 0) kick += c->kick2[t - 1];
+      if (j < nabs) { kick += c->kick1[t]; drift = c->drift[t]; a_drift = c->a_half[t]; }
+    } else {
+      t = k0 - j;
+      if (j > 0) kick -= c->kick1[t];
+      if (j < nabs) { kick -= c->kick2[t - 1]; drift = -c->drift[t - 1]; a_drift = c->a_half[t - 1]; }
+    }
+    const double a_kick = c->a[t];
+    for (size_t f = 0; f < c->fields.size(); ++f) {
+      if (!used[f]) continue;
+      if (!c->fields[f].has_grid || (tdep && c->fields[f].grid_a != a_kick)) {
+        rc = build_grid(c, (int)f, a_kick);
+        if (rc) return rc;
+      }
+    }
+    pa.kick = kick;
+    pa.a_kick = a_kick;
+    pa.do_drift = j < nabs;
+    pa.drift = drift;
+    pa.a_drift = a_drift;
+    std::pair<hipEvent_t, hipEvent_t> ev;
+    timing_begin(c, FDF_KERNEL_PUSH, &ev);
+    launch_push(pa, c->stream);
+    timing_end(c, FDF_KERNEL_PUSH, ev);
+    rc = launched(c, "push");
+    if (rc) return rc;
+  }
+  c->step_index = k0 + n;
+  c->stepped = true;
+  return FDF_OK;
+}
+
+int fdf_weights(fdf_ctx* c, int32_t sid, double* d_w) {
+  if (!c || !d_w) return FDF_ERR_ARG;
+  if (sid < 0 || sid >= (int)c->species.size()) return fail(c, FDF_ERR_ARG, "bad species id");
+  OutputArgs o = output_args(c, c->species[sid]);
+  o.w_out = d_w;
+  std::pair<hipEvent_t, hipEvent_t> ev;
+  timing_begin(c, FDF_KERNEL_OUTPUT, &ev);
+  launch_weights(o, c->stream);
+  timing_end(c, FDF_KERNEL_OUTPUT, ev);
+  return launched(c, "weights");
+}
+
+int fdf_density_power_spectrum(fdf_ctx* c, const int32_t* sp, int32_t ns, int32_t nbins, int32_t mode,
+                               double* hk, double* hp, double* hn) {
+  if (!c || !sp || ns < 1 || !hk || !hp || !hn) return FDF_ERR_ARG;
+  if (!needs_ws(c)) return fail(c, FDF_ERR_WORKSPACE, "no workspace attached");
+  if (nbins < 1 || nbins > kMaxBins) return fail(c, FDF_ERR_ARG, "n_bins must be in [1, 256]");
+  if (mode != FDF_PK_CROSS && mode != FDF_PK_AUTO) return fail(c, FDF_ERR_ARG, "unknown mode");
+  for (int i = 0; i < ns; ++i)
+    if (sp[i] < 0 || sp[i] >= (int)c->species.size()) return fail(c, FDF_ERR_ARG, "bad species id");
+  const int G = c->cfg.grid_n;
+  const bool f64 = c->cfg.precision == FDF_PREC_FP64;
+  const size_t rb = f64 ? 8 : 4, cells = (size_t)G * G * G;
+  const double a = c->a[c->step_index];
+  double esum = 0;
+  std::vector<double> emean(ns);
+  for (int i = 0; i < ns; ++i) { emean[i] = mean_energy(c->species[sp[i]].m, a); esum += emean[i]; }
+  char* dens = c->ws + c->lay.dens;
+  std::pair<hipEvent_t, hipEvent_t> ev;
+  timing_begin(c, FDF_KERNEL_OUTPUT, &ev);
+  launch_fill_zero(dens, align_up(2 * cells * rb), c->stream);
+  for (int i = 0; i < ns; ++i) {
+    const SpeciesRec& s = c->species[sp[i]];
+    OutputArgs o = output_args(c, s);
+    o.auto_mode = mode == FDF_PK_AUTO;
+    const double g3 = (double)cells;
+    if (o.auto_mode) {
+      o.norm[0] = o.norm[1] = g3 / ((double)s.n * esum);
+    } else {
+      const int64_t ne = (s.n + 1) / 2, no = s.n / 2;
+      o.norm[0] = g3 / ((double)ne * esum);
+      o.norm[1] = no ? g3 / ((double)no * esum) : 0.0;
+    }
+    o.dens[0] = dens;
+    o.dens[1] = dens + cells * rb;
+    launch_deposit(o, c->stream);
+  }
+  double* bins = (double*)(c->ws + c->lay.bins);
+  launch_fill_zero(bins, align_up(3 * kMaxBins * sizeof(double)), c->stream);
+  PkArgs pk{};
+  pk.G = G;
+  pk.fp64 = f64;
+  pk.nbins = nbins;
+  pk.auto_mode = mode == FDF_PK_AUTO;
+  pk.volume = c->cfg.box_mpc * c->cfg.box_mpc * c->cfg.box_mpc;
+  pk.grid_a = dens;
+  pk.grid_b = dens + cells * rb;
+  pk.scratch = c->ws + c->lay.scratch;
+  pk.twiddle = c->ws + (f64 ? c->lay.twiddle_d : c->lay.twiddle_f);
+  pk.bins = bins;
+  pk.kf = 2.0 * kPi / c->cfg.box_mpc;
+  launch_power_spectrum(pk, c->stream);
+  timing_end(c, FDF_KERNEL_OUTPUT, ev);
+  int rc = launched(c, "power spectrum");
+  if (rc) return rc;
+  std::vector<double> hb(3 * nbins);
+  rc = hip_check(c, hipMemcpyAsync(hb.data(), bins, hb.size() * 8, hipMemcpyDeviceToHost, c->stream), "bins");
+  if (!rc) rc = hip_check(c, hipStreamSynchronize(c->stream), "bins");
+  if (rc) return rc;
+  for (int b = 0; b < nbins; ++b) {
+    const double cnt = hb[b];
+    hn[b] = cnt;
+    hk[b] = cnt > 0 ? hb[nbins + b] / cnt : NAN;
+    hp[b] = cnt > 0 ? hb[2 * nbins + b] / cnt : NAN;
+  }
+  c->have_density = true;
+  c->density_auto = mode == FDF_PK_AUTO;
+  return FDF_OK;
+}
+
+int fdf_read_state(fdf_ctx* c, int32_t sid, double* hx, double* hq) {
+  if (!c) return FDF_ERR_ARG;
+  if (sid < 0 || sid >= (int)c->species.size()) return fail(c, FDF_ERR_ARG, "bad species id");
+  const SpeciesRec& s = c->species[sid];
+  const Segment& g = s.seg[s.cur];
+  const int64_t n = s.n;
+  const bool f64 = c->cfg.precision == FDF_PREC_FP64;
+  int rc = hip_check(c, hipStreamSynchronize(c->stream), "sync");
+  if (rc) return rc;
+  std::vector<uint32_t> id(n);
+  rc = hip_check(c, hipMemcpy(id.data(), g.id, n * 4, hipMemcpyDeviceToHost), "read ids");
+  if (rc) return rc;
+  std::vector<double> bd(f64 ? n : 0);
+  std::vector<float> bf(f64 ? 0 : n), bc(f64 ? 0 : n);
+  std::vector<uint32_t> bu(f64 ? 0 : n);
+  for (int d = 0; d < 3; ++d) {
+    if (hx) {
+      if (f64) {
+        rc = hip_check(c, hipMemcpy(bd.data(), g.xd[d], n * 8, hipMemcpyDeviceToHost), "read x");
+        for (int64_t i = 0; i < n && !rc; ++i) hx[3 * (size_t)id[i] + d] = bd[i];
+      } else {
+        rc = hip_check(c, hipMemcpy(bu.data(), g.xu[d], n * 4, hipMemcpyDeviceToHost), "read x");
+        for (int64_t i = 0; i < n && !rc; ++i) hx[3 * (size_t)id[i] + d] = (double)bu[i] * (c->cfg.box_mpc * 0x1p-32);
+      }
+    }
+    if (rc) return rc;
+    if (hq) {
+      if (f64) {
+        rc = hip_check(c, hipMemcpy(bd.data(), g.qd[d], n * 8, hipMemcpyDeviceToHost), "read q");
+        for (int64_t i = 0; i < n && !rc; ++i) hq[3 * (size_t)id[i] + d] = bd[i];
+      } else {
+        rc = hip_check(c, hipMemcpy(bf.data(), g.qf[d], n * 4, hipMemcpyDeviceToHost), "read q");
+        if (!rc) rc = hip_check(c, hipMemcpy(bc.data(), g.cf[d], n * 4, hipMemcpyDeviceToHost), "read c");
+        for (int64_t i = 0; i < n && !rc; ++i) hq[3 * (size_t)id[i] + d] = (double)bf[i] - (double)bc[i];
+      }
+    }
+    if (rc) return rc;
+  }
+  return FDF_OK;
+}
+
+int fdf_read_grid(fdf_ctx* c, int32_t field_id, int32_t slot, double* h) {
+  if (!c || !h) return FDF_ERR_ARG;
+  if (field_id < 0 || field_id >= (int)c->fields.size()) return fail(c, FDF_ERR_ARG, "bad field id");
+  if (slot < 0 || slot > 6) return fail(c, FDF_ERR_ARG, "slot must be in [0, 6]");
+  const FieldRec& f = c->fields[field_id];
+  if (!f.has_grid) return fail(c, FDF_ERR_STATE, "grid not built");
+  const int ns = c->lay.nslot;
+  int s = slot;
+  if (ns == 4) s = slot < 3 ? slot : (slot < 6 ? slot - 3 : 3);
+  if (ns == 4 && slot == 6 && c->cfg.potential_model != FDF_MODEL_RADMAT) {
+    std::fill(h, h + (size_t)c->cfg.grid_n * c->cfg.grid_n * c->cfg.grid_n, 0.0);
+    return FDF_OK;
+  }
+  const size_t cells = (size_t)c->cfg.grid_n * c->cfg.grid_n * c->cfg.grid_n;
+  const bool f64 = c->cfg.precision == FDF_PREC_FP64;
+  int rc = hip_check(c, hipStreamSynchronize(c->stream), "sync");
+  if (rc) return rc;
+  if (f64) {
+    std::vector<double> all(cells * ns);
+    rc = hip_check(c, hipMemcpy(all.data(), f.grid, all.size() * 8, hipMemcpyDeviceToHost), "read grid");
+    for (size_t i = 0; i < cells && !rc; ++i) h[i] = all[i * ns + s];
+  } else {
+    std::vector<uint16_t> all(cells * ns);
+    rc = hip_check(c, hipMemcpy(all.data(), f.grid, all.size() * 2, hipMemcpyDeviceToHost), "read grid");
+    for (size_t i = 0; i < cells && !rc; ++i) {
+      uint32_t u = (uint32_t)all[i * ns + s] << 16;
+      float v;
+      std::memcpy(&v, &u, 4);
+      h[i] = v;
+    }
+  }
+  return rc;
+}
+
+int fdf_read_field(fdf_ctx* c, int32_t field_id, double* h) {
+  if (!c || !h) return FDF_ERR_ARG;
+  if (field_id < 0 || field_id >= (int)c->fields.size()) return fail(c, FDF_ERR_ARG, "bad field id");
+  const int G = c->cfg.grid_n, M = G / 2, H = M + 1;
+  const bool f64 = c->cfg.precision == FDF_PREC_FP64;
+  const size_t n = (size_t)G * G * M * 2;
+  std::vector<double> d(n);
+  std::vector<float> f(f64 ? 0 : n);
+  int rc = hip_check(c, hipStreamSynchronize(c->stream), "sync");
+  if (!rc) rc = hip_check(c, hipMemcpy(f64 ? (void*)d.data() : (void*)f.data(), c->fields[field_id].dk,
+                                       n * (f64 ? 8 : 4), hipMemcpyDeviceToHost), "read field");
+  if (rc) return rc;
+  if (!f64) for (size_t i = 0; i < n; ++i) d[i] = f[i];
+  for (int ix = 0; ix < G; ++ix)
+    for (int iy = 0; iy < G; ++iy)
+      for (int iz = 0; iz < H; ++iz) {
+        const size_t dst = (((size_t)ix * G + iy) * H + iz) * 2;
+        if (iz == M) { h[dst] = 0; h[dst + 1] = 0; continue; }
+        const size_t src = (((size_t)ix * G + iy) * M + iz) * 2;
+        h[dst] = d[src];
+        h[dst + 1] = d[src + 1];
+      }
+  return FDF_OK;
+}
+
+int fdf_read_density(fdf_ctx* c, int32_t half, double* h) {
+  if (!c || !h) return FDF_ERR_ARG;
+  if (!c->have_density) return fail(c, FDF_ERR_STATE, "no density deposited yet");
+  if (half < 0 || half > 1) return fail(c, FDF_ERR_ARG, "half must be 0 or 1");
+  const size_t cells = (size_t)c->cfg.grid_n * c->cfg.grid_n * c->cfg.grid_n;
+  const bool f64 = c->cfg.precision == FDF_PREC_FP64;
+  const size_t rb = f64 ? 8 : 4;
+  char* src = c->ws + c->lay.dens + half * cells * rb;
+  int rc = hip_check(c, hipStreamSynchronize(c->stream), "sync");
+  if (rc) return rc;
+  if (f64) return hip_check(c, hipMemcpy(h, src, cells * 8, hipMemcpyDeviceToHost), "read density");
+  std::vector<float> f(cells);
+  rc = hip_check(c, hipMemcpy(f.data(), src, cells * 4, hipMemcpyDeviceToHost), "read density");
+  for (size_t i = 0; i < cells && !rc; ++i) h[i] = f[i];
+  return rc;
+}
+
+int fdf_read_schedule(const fdf_ctx* c, double* h) {
+  if (!c || !h) return FDF_ERR_ARG;
+  const int n = c->cfg.n_steps;
+  std::copy(c->a.begin(), c->a.end(), h);
+  std::copy(c->a_half.begin(), c->a_half.end(), h + n + 1);
+  std::copy(c->kick1.begin(), c->kick1.end(), h + 2 * n + 1);
+  std::copy(c->kick2.begin(), c->kick2.end(), h + 3 * n + 1);
+  std::copy(c->drift.begin(), c->drift.end(), h + 4 * n + 1);
+  return FDF_OK;
+}
+
+int fdf_get_info(const fdf_ctx* c, fdf_info* info) {
+  if (!c || !info) return FDF_ERR_ARG;
+  std::memset(info, 0, sizeof(*info));
+  info->step_index = c->step_index;
+  info->n_steps = c->cfg.n_steps;
+  info->a_current = c->a[c->step_index];
+  info->amplitude = c->amp;
+  info->tau_begin = c->tau_begin;
+  info->n_fields = (int32_t)c->fields.size();
+  info->n_species = (int32_t)c->species.size();
+  for (auto& s : c->species) info->n_particles += s.n;
+  info->workspace_used = c->lay.total;
+  return FDF_OK;
+}
+
+int fdf_sync(fdf_ctx* c) {
+  if (!c) return FDF_ERR_ARG;
+  return hip_check(c, hipStreamSynchronize(c->stream), "sync");
+}
+
+int fdf_timing_enable(fdf_ctx* c, int32_t on) {
+  if (!c) return FDF_ERR_ARG;
+  c->timing = on != 0;
+  return FDF_OK;
+}
+
+int fdf_read_timing(fdf_ctx* c, int32_t cls, double* ms, int64_t* launches) {
+  if (!c || !ms || !launches) return FDF_ERR_ARG;
+  if (cls < 0 || cls >= FDF_KERNEL_COUNT) return fail(c, FDF_ERR_ARG, "bad kernel class");
+  timing_collect(c);
+  *ms = c->tim[cls].total_ms;
+  *launches = c->tim[cls].launches;
+  return FDF_OK;
+}
+
+int fdf_timing_reset(fdf_ctx* c) {
+  if (!c) return FDF_ERR_ARG;
+  timing_collect(c);
+  for (auto& t : c->tim) { t.total_ms = 0; t.launches = 0; }
+  return FDF_OK;
+}
+
+}  // extern "C"

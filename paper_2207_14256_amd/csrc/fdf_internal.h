@@ -1,0 +1,148 @@
+// Internal interface between the host runtime (fdf_host.cpp) and the HIP
+// kernels.  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace fdf {
+
+// ----------------------------------------------------------------------------
+// Grid recipe: which potential-derived quantity each output slot carries.
+// ----------------------------------------------------------------------------
+enum SlotKind : int32_t {
+  SK_ZERO = 0,
+  SK_DX_PSI = 1, SK_DY_PSI = 2, SK_DZ_PSI = 3,
+  SK_DX_PHI = 4, SK_DY_PHI = 5, SK_DZ_PHI = 6,
+  SK_PHIDOT = 7,
+  SK_PSI = 8,
+};
+
+// Transfer functions at one scale factor (host evaluates the time factors):
+//   T_phi(k)    = c_phi / k^2
+//   T_psi(k)    = T_phi(k) (1 - slip_amp exp(-k / slip_k))
+//   T_phidot(k) = c_phidot / k^2
+struct Transfer {
+  double c_phi, c_phidot, slip_amp, slip_k;
+};
+
+// Output element type of a grid set.
+enum GridType : int32_t { GT_BF16 = 0, GT_F32 = 1, GT_F64 = 2 };
+
+struct GridBuildArgs {
+  int32_t G;
+  int32_t fp64;            // 1: FFT in binary64, 0: binary32
+  int32_t nslot;           // 4 or 8 slots per cell in the output
+  int32_t nfft;            // number of non-zero slots (FFTs to run)
+  int32_t kind[8];         // SlotKind of FFT i
+  int32_t slot[8];         // output slot of FFT i
+  int32_t out_type;        // GridType
+  double kf;               // 2 pi / L
+  Transfer tr;
+  const void* delta_k;     // complex [G][G][G/2]
+  void* scratch;           // complex [nfft][G][G][G/2]
+  const void* twiddle;     // complex [G], e^{-2 pi i m / G}, same precision as the FFT
+  void* out;               // [G^3][nslot] of out_type
+};
+
+struct PkArgs {
+  int32_t G;
+  int32_t fp64;
+  int32_t nbins;
+  int32_t auto_mode;       // 1: only grid a is transformed, P = |a|^2
+  double volume;           // L^3
+  const void* grid_a;      // real [G^3]
+  const void* grid_b;
+  void* scratch;           // complex [2][G][G][G/2]
+  const void* twiddle;
+  double* bins;            // [3][nbins]: count, sum |k|, sum P  (zeroed by caller)
+  double kf;
+};
+
+// Segment of the batched particle state: one species.
+struct Segment {
+  // FP32 form: positions as uint32 fixed point, q and Kahan residual c in f32
+  uint32_t* xu[3];
+  float* qf[3];
+  float* cf[3];
+  float* q0f[3];
+  // FP64 form
+  double* xd[3];
+  double* qd[3];
+  double* q0d[3];
+  uint32_t* id;
+  const void* grid;        // [G^3][nslot]
+  double m;                // mass [eV]
+  int64_t n;               // particles
+  int64_t chunk_begin;     // first chunk of this segment in the launch
+};
+
+struct PushArgs {
+  const Segment* seg;      // device array
+  int32_t nseg;
+  int64_t total_chunks;
+  int32_t fp64;
+  int32_t nslot;
+  int32_t log2g;
+  int32_t G;
+  int32_t do_kick, do_drift;
+  double kick;             // fused kick coefficient [Mpc]
+  double a_kick;           // a at the kick
+  double drift;            // Delta tau of the drift [Mpc]
+  double a_drift;          // a_{k+1/2}
+  double box;              // L
+  int32_t ppt;             // particles per thread
+  int32_t block;           // threads per block
+};
+
+struct SampleArgs {
+  Segment seg;
+  int32_t fp64;
+  uint64_t seed;
+  double box;
+  double t_nu;             // k_B T [eV]
+};
+
+struct FieldGenArgs {
+  int32_t G;
+  int32_t fp64;
+  int32_t fixed_amp;
+  uint64_t seed;
+  double box, amp, ns, gamma, h;
+  void* out;               // complex [G][G][G/2]
+};
+
+struct PreIcArgs {
+  Segment seg;
+  int32_t fp64;
+  int32_t G;
+  double box, m, a, tau;
+  const void* grid;        // [G^3][4] f64: dpsi/dx, dpsi/dy, dpsi/dz, psi
+};
+
+struct OutputArgs {
+  Segment seg;
+  int32_t fp64;
+  int32_t G;
+  int32_t pre_ic;          // p regenerated from (seed, id) instead of q0
+  uint64_t seed;
+  double t_nu;
+  double box, a, m;
+  double norm[2];          // deposit normalisation per half (even / odd id)
+  int32_t auto_mode;
+  double* w_out;           // weights by id (may be null)
+  void* dens[2];           // real [G^3] per half (f32 or f64)
+};
+
+void launch_field_gen(const FieldGenArgs& a, hipStream_t s);
+void launch_sample_species(const SampleArgs& a, hipStream_t s);
+void launch_pre_ic(const PreIcArgs& a, hipStream_t s);
+void launch_build_grids(const GridBuildArgs& a, hipStream_t s);
+void launch_push(const PushArgs& a, hipStream_t s);
+void launch_weights(const OutputArgs& a, hipStream_t s);
+void launch_deposit(const OutputArgs& a, hipStream_t s);
+void launch_power_spectrum(const PkArgs& a, hipStream_t s);
+void launch_fill_zero(void* ptr, size_t bytes, hipStream_t s);
+int push_chunk_particles(int ppt);
+
+}  // namespace fdf

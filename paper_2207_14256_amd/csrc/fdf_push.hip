@@ -1,0 +1,275 @@
+// Gather + kick-drift-kick push of the neutrino tracers (sec. 3.3), gfx950.
+//
+// One launch advances every species by one leapfrog step: the kick of the
+// closing half of step k-1 and the opening half of step k are evaluated at the
+// same (x_k, a_k), so they are applied as one kick with the summed Delta tau;
+// then the drift.  The last launch of a call is a kick alone, leaving q at a
+// schedule point.
+//
+// Per particle: CIC (trilinear) interpolation of the gradient grids at x,
+//   F = -eps0 grad psi - (q0^2/eps0) grad phi + q0 (q0 . grad phi)/eps0 + q0 phidot
+//   (eq. releq_approx, eps0 = sqrt(q0^2 + m^2 a^2)),
+//   q += kick * F,  x += drift * q / sqrt(q^2 + m^2 a_{k+1/2}^2)   (eq. discrete_drift).
+//
+// FP32 form: x is a uint32 fixed-point fraction of the box per axis, so the
+// periodic wrap is integer overflow and the cell index is the top log2(G)
+// bits; q is binary32 with a Kahan residual c (true momentum q - c); grids
+// are bfloat16 with 8 slots = one 16-byte load per CIC corner.
+// FP64 form: everything binary64; 8 slots = four 16-byte loads per corner.
+//
+// Blocks take contiguous chunks of one species; consecutive block ids are
+// spread over the 8 XCDs, so block ids are remapped to give each XCD (own
+// L2) a contiguous range of chunks, i.e. a compact region of sorted particles.
+#include "fdf_device.h"
+#include "fdf_internal.h"
+
+namespace fdf {
+namespace {
+
+constexpr int kBlock = 256;
+
+__device__ __forceinline__ int64_t xcd_chunk(int64_t b, int64_t nb) {
+  const int64_t full = nb - nb % 8;
+  if (b >= full) return b;
+  const int64_t per = full / 8;
+  return (b % 8) * per + b / 8;
+}
+
+__device__ __forceinline__ int find_segment(const Segment* seg, int nseg, int64_t chunk) {
+  int s = 0;
+  while (s + 1 < nseg && seg[s + 1].chunk_begin <= chunk) ++s;
+  return s;
+}
+
+template <typename T> __device__ __forceinline__ T ldnt(const T* p) { return __builtin_nontemporal_load(p); }
+template <typename T> __device__ __forceinline__ void stnt(T v, T* p) { __builtin_nontemporal_store(v, p); }
+
+// Gather of the slots (8-slot: gpsi[3], gphi[3], phidot; 4-slot: gpsi[3], phidot
+// with phi = psi) from a bfloat16 grid.
+template <int NSLOT>
+__device__ __forceinline__ void gather_bf16(const void* grid, const size_t* cell, const float* w,
+                                            float* g /* 7 */) {
+#pragma unroll
+  for (int s = 0; s < 7; ++s) g[s] = 0.0f;
+  if constexpr (NSLOT == 8) {
+    const uint4* gp = (const uint4*)grid;
+    uint4 v[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) v[c] = gp[cell[c]];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      g[0] += w[c] * bf16_lo(v[c].x); g[1] += w[c] * bf16_hi(v[c].x);
+      g[2] += w[c] * bf16_lo(v[c].y); g[3] += w[c] * bf16_hi(v[c].y);
+      g[4] += w[c] * bf16_lo(v[c].z); g[5] += w[c] * bf16_hi(v[c].z);
+      g[6] += w[c] * bf16_lo(v[c].w);
+    }
+  } else {
+    const uint2* gp = (const uint2*)grid;
+    uint2 v[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) v[c] = gp[cell[c]];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      g[0] += w[c] * bf16_lo(v[c].x); g[1] += w[c] * bf16_hi(v[c].x);
+      g[2] += w[c] * bf16_lo(v[c].y); g[6] += w[c] * bf16_hi(v[c].y);
+    }
+    g[3] = g[0]; g[4] = g[1]; g[5] = g[2];
+  }
+}
+
+template <int NSLOT, int PPT>
+__global__ void __launch_bounds__(kBlock) k_push_f32(PushArgs a) {
+  const int64_t chunk = xcd_chunk(blockIdx.x, gridDim.x);
+  const int s = find_segment(a.seg, a.nseg, chunk);
+  const Segment& sg = a.seg[s];
+  const int64_t n = sg.n;
+  const int64_t first = (chunk - sg.chunk_begin) * (int64_t)(kBlock * PPT) + threadIdx.x;
+  const int shift = 32 - a.log2g;
+  const uint32_t gmask = (uint32_t)a.G - 1u;
+  const uint32_t fmask = (shift >= 32) ? 0xFFFFFFFFu : ((1u << shift) - 1u);
+  const float finv = __uint_as_float((uint32_t)(127 - shift) << 23);   // 2^-shift
+  const float kick = (float)a.kick;
+  const float ma = (float)(sg.m * a.a_kick);
+  const float mah = (float)(sg.m * a.a_drift);
+  const float dscale = (float)(a.drift * 4294967296.0 / a.box);
+  const size_t G = (size_t)a.G;
+
+#pragma unroll
+  for (int p = 0; p < PPT; ++p) {
+    const int64_t i = first + (int64_t)p * kBlock;
+    if (i >= n) break;
+    uint32_t xu[3];
+    float q[3], c[3], q0[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      xu[d] = ldnt(&sg.xu[d][i]);
+      q[d] = ldnt(&sg.qf[d][i]);
+      c[d] = ldnt(&sg.cf[d][i]);
+      q0[d] = ldnt(&sg.q0f[d][i]);
+    }
+    // CIC corners and weights from the fixed-point position
+    uint32_t i0[3], i1[3];
+    float t[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      i0[d] = xu[d] >> shift;
+      i1[d] = (i0[d] + 1u) & gmask;
+      t[d] = (float)(xu[d] & fmask) * finv;
+    }
+    size_t cell[8];
+    float w[8];
+#pragma unroll
+    for (int cc = 0; cc < 8; ++cc) {
+      const int cx = cc >> 2, cy = (cc >> 1) & 1, cz = cc & 1;
+      cell[cc] = ((size_t)(cx ? i1[0] : i0[0]) * G + (cy ? i1[1] : i0[1])) * G + (cz ? i1[2] : i0[2]);
+      w[cc] = (cx ? t[0] : 1.0f - t[0]) * (cy ? t[1] : 1.0f - t[1]) * (cz ? t[2] : 1.0f - t[2]);
+    }
+    float g[7];
+    gather_bf16<NSLOT>(sg.grid, cell, w, g);
+    // separable force of eq. releq_approx
+    const float q0sq = q0[0] * q0[0] + q0[1] * q0[1] + q0[2] * q0[2];
+    const float e0 = sqrtf(q0sq + ma * ma);
+    const float ie0 = 1.0f / e0;
+    const float qg = (q0[0] * g[3] + q0[1] * g[4] + q0[2] * g[5]) * ie0 + g[6];
+    const float cphi = q0sq * ie0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const float F = -e0 * g[d] - cphi * g[3 + d] + q0[d] * qg;
+      // Kahan-compensated q += kick * F
+      const float y = kick * F - c[d];
+      const float tq = q[d] + y;
+      c[d] = (tq - q[d]) - y;
+      q[d] = tq;
+    }
+    if (a.do_drift) {
+      const float ie = 1.0f / sqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + mah * mah);
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const int disp = __float2int_rn(dscale * (q[d] * ie));
+        stnt(xu[d] + (uint32_t)disp, &sg.xu[d][i]);
+      }
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      stnt(q[d], &sg.qf[d][i]);
+      stnt(c[d], &sg.cf[d][i]);
+    }
+  }
+}
+
+template <int NSLOT>
+__device__ __forceinline__ void gather_f64(const void* grid, const size_t* cell, const double* w,
+                                           double* g /* 7 */) {
+#pragma unroll
+  for (int s = 0; s < 7; ++s) g[s] = 0.0;
+  const double2* gp = (const double2*)grid;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    if constexpr (NSLOT == 8) {
+      const double2 v0 = gp[4 * cell[c]], v1 = gp[4 * cell[c] + 1];
+      const double2 v2 = gp[4 * cell[c] + 2], v3 = gp[4 * cell[c] + 3];
+      g[0] += w[c] * v0.x; g[1] += w[c] * v0.y; g[2] += w[c] * v1.x;
+      g[3] += w[c] * v1.y; g[4] += w[c] * v2.x; g[5] += w[c] * v2.y;
+      g[6] += w[c] * v3.x;
+    } else {
+      const double2 v0 = gp[2 * cell[c]], v1 = gp[2 * cell[c] + 1];
+      g[0] += w[c] * v0.x; g[1] += w[c] * v0.y; g[2] += w[c] * v1.x;
+      g[6] += w[c] * v1.y;
+    }
+  }
+  if constexpr (NSLOT == 4) { g[3] = g[0]; g[4] = g[1]; g[5] = g[2]; }
+}
+
+template <int NSLOT, int PPT>
+__global__ void __launch_bounds__(kBlock) k_push_f64(PushArgs a) {
+  const int64_t chunk = xcd_chunk(blockIdx.x, gridDim.x);
+  const int s = find_segment(a.seg, a.nseg, chunk);
+  const Segment& sg = a.seg[s];
+  const int64_t n = sg.n;
+  const int64_t first = (chunk - sg.chunk_begin) * (int64_t)(kBlock * PPT) + threadIdx.x;
+  const int gm = a.G - 1;
+  const double ginv = (double)a.G / a.box;
+  const double ma = sg.m * a.a_kick;
+  const double mah = sg.m * a.a_drift;
+  const size_t G = (size_t)a.G;
+
+#pragma unroll
+  for (int p = 0; p < PPT; ++p) {
+    const int64_t i = first + (int64_t)p * kBlock;
+    if (i >= n) break;
+    double x[3], q[3], q0[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      x[d] = ldnt(&sg.xd[d][i]);
+      q[d] = ldnt(&sg.qd[d][i]);
+      q0[d] = ldnt(&sg.q0d[d][i]);
+    }
+    int i0[3], i1[3];
+    double t[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const double u = x[d] * ginv;
+      const double fl = floor(u);
+      t[d] = u - fl;
+      i0[d] = ((int)fl) & gm;
+      i1[d] = (i0[d] + 1) & gm;
+    }
+    size_t cell[8];
+    double w[8];
+#pragma unroll
+    for (int cc = 0; cc < 8; ++cc) {
+      const int cx = cc >> 2, cy = (cc >> 1) & 1, cz = cc & 1;
+      cell[cc] = ((size_t)(cx ? i1[0] : i0[0]) * G + (cy ? i1[1] : i0[1])) * G + (cz ? i1[2] : i0[2]);
+      w[cc] = (cx ? t[0] : 1.0 - t[0]) * (cy ? t[1] : 1.0 - t[1]) * (cz ? t[2] : 1.0 - t[2]);
+    }
+    double g[7];
+    gather_f64<NSLOT>(sg.grid, cell, w, g);
+    const double q0sq = q0[0] * q0[0] + q0[1] * q0[1] + q0[2] * q0[2];
+    const double e0 = sqrt(q0sq + ma * ma);
+    const double qg = (q0[0] * g[3] + q0[1] * g[4] + q0[2] * g[5]) / e0;
+    const double cphi = q0sq / e0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const double F = -e0 * g[d] - cphi * g[3 + d] + q0[d] * qg + q0[d] * g[6];
+      q[d] += a.kick * F;
+    }
+    if (a.do_drift) {
+      const double e = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + mah * mah);
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        double xn = fmod(x[d] + a.drift * (q[d] / e), a.box);   // floor-mod as numpy.mod
+        if (xn < 0.0) xn += a.box;
+        stnt(xn, &sg.xd[d][i]);
+      }
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) stnt(q[d], &sg.qd[d][i]);
+  }
+}
+
+template <int PPT>
+void push_ppt(const PushArgs& a, hipStream_t s) {
+  const dim3 grid((unsigned)a.total_chunks), block(kBlock);
+  if (a.fp64) {
+    if (a.nslot == 8) hipLaunchKernelGGL((k_push_f64<8, PPT>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_push_f64<4, PPT>), grid, block, 0, s, a);
+  } else {
+    if (a.nslot == 8) hipLaunchKernelGGL((k_push_f32<8, PPT>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_push_f32<4, PPT>), grid, block, 0, s, a);
+  }
+}
+
+}  // namespace
+
+int push_chunk_particles(int ppt) { return kBlock * ppt; }
+
+void launch_push(const PushArgs& a, hipStream_t s) {
+  switch (a.ppt) {
+    case 1: push_ppt<1>(a, s); break;
+    case 2: push_ppt<2>(a, s); break;
+    case 4: push_ppt<4>(a, s); break;
+    default: push_ppt<8>(a, s); break;
+  }
+}
+
+}  // namespace fdf

@@ -1,0 +1,281 @@
+"""GPU parity of the HIP path against the FP64 CPU oracle on identical seeded
+inputs, through the C ABI (ctypes binding).
+
+Tolerances: the FP64 path must match to 1e-5 relative (positions and momenta);
+it agrees far better in practice since both evaluate the same formulas in
+binary64 and differ only in rounding order (fused half-kicks, FMA, libm).
+The FP32 form (fixed-point x, Kahan q, bfloat16 grids) is held to stated
+error bounds.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import field as ofield, particles as oparticles, pipeline, push as opush
+from paper_2207_14256_amd import fastdf, workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print("[gpu-case] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+def periodic_diff(a, b, L):
+    return (a - b + L / 2) % L - L / 2
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    import torch
+    torch.cuda.set_device(0)
+    fastdf.load()
+    yield
+    torch.cuda.synchronize()
+
+
+# ------------------------------------------------------------------ inputs --
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("G", [8, 32])
+def test_field_generation(prec, G):
+    say("field generation G=%d %s" % (G, prec))
+    cfg = workloads.small("c1", grid_n=G, n_side=4, precision=prec)
+    ctx = fastdf.Context(cfg)
+    fid = ctx.add_field(cfg["fields"][0])
+    got = ctx.read_field(fid)
+    ref = pipeline.delta0(cfg)
+    tol = 1e-13 if prec == "fp64" else 2e-7
+    assert np.max(np.abs(got - ref)) <= tol * np.max(np.abs(ref))
+    ctx.close()
+
+
+def test_field_fixed_amplitude():
+    say("field fixed amplitude")
+    cfg = workloads.small("c1", grid_n=16, n_side=4, fixed_amp=True)
+    ctx = fastdf.Context(cfg)
+    fid = ctx.add_field(cfg["fields"][0], fixed_amp=True)
+    got = ctx.read_field(fid)
+    ref = pipeline.delta0(cfg)
+    assert np.max(np.abs(got - ref)) <= 1e-13 * np.max(np.abs(ref))
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_sampling_canonical_state(prec):
+    say("sampling %s" % prec)
+    cfg = workloads.small("c1", grid_n=16, n_side=20, precision=prec)
+    ctx, fields, species = fastdf.setup_workload(cfg)
+    x, q = ctx.read_state(species[0])
+    n = 20 ** 3
+    ids = np.arange(n)
+    xr = oparticles.positions_f64(cfg["species"][0]["seed"], ids, cfg["box_mpc"])
+    qr = oparticles.momenta_f64(cfg["species"][0]["seed"], ids)
+    assert np.array_equal(x, xr)                        # exact lattice positions
+    # momenta are binary32 values; libm differences may flip a last bit rarely
+    rel = np.abs(q - qr) / np.maximum(np.abs(qr), 1e-30)
+    assert np.mean(rel > 0) < 1e-3 and np.max(rel) < 2.5e-7
+    ctx.close()
+
+
+# ------------------------------------------------------------------- grids --
+
+@pytest.mark.parametrize("G", [8, 16, 64])
+@pytest.mark.parametrize("slip", [0.0, 0.01])
+def test_grid_build_fp64(G, slip):
+    say("grid build fp64 G=%d slip=%g" % (G, slip))
+    cfg = workloads.small("c2", grid_n=G, n_side=4, precision="fp64", slip_amp=slip,
+                          box_mpc=300.0)
+    ctx = fastdf.Context(cfg)
+    fid = ctx.add_field(cfg["fields"][0])
+    ctx.build_potential_grids(fid, 1e-3)
+    ref = ofield.potential_grids(pipeline.delta0(cfg), cfg["box_mpc"], 1e-3, pipeline.model_of(cfg))
+    scale = np.max(np.abs(ref["gpsi"]))
+    for s in range(3):
+        assert np.max(np.abs(ctx.read_grid(fid, s) - ref["gpsi"][s])) < 1e-12 * scale
+        assert np.max(np.abs(ctx.read_grid(fid, 3 + s) - ref["gphi"][s])) < 1e-12 * scale
+    assert np.all(ctx.read_grid(fid, 6) == 0.0)
+    ctx.close()
+
+
+def test_grid_build_bf16():
+    say("grid build fp32/bf16 G=64")
+    cfg = workloads.small("c2", grid_n=64, n_side=4, precision="fp32", box_mpc=600.0)
+    ctx = fastdf.Context(cfg)
+    fid = ctx.add_field(cfg["fields"][0])
+    ctx.build_potential_grids(fid, 1e-3)
+    ref = ofield.potential_grids(pipeline.delta0(cfg), cfg["box_mpc"], 1e-3, pipeline.model_of(cfg))
+    for s in range(3):
+        got = ctx.read_grid(fid, s)
+        err = np.abs(got - ref["gpsi"][s])
+        # bfloat16 keeps 8 significant bits: relative rounding <= 2^-8 per value
+        assert np.all(err <= 2.0 ** -8 * np.abs(ref["gpsi"][s]) + 1e-6 * np.abs(ref["gpsi"][s]).max())
+    ctx.close()
+
+
+def test_grid_build_radmat_phidot():
+    say("grid build radmat phidot")
+    cfg = workloads.small("c2", grid_n=32, n_side=4, precision="fp64", model="radmat",
+                          omega_m=0.9999, omega_r=1e-4, box_mpc=400.0)
+    ctx = fastdf.Context(cfg)
+    fid = ctx.add_field(cfg["fields"][0])
+    for a in (1e-5, 3e-3):
+        ctx.build_potential_grids(fid, a)
+        ref = ofield.potential_grids(pipeline.delta0(cfg), cfg["box_mpc"], a, pipeline.model_of(cfg))
+        got = ctx.read_grid(fid, 6)
+        assert np.max(np.abs(got - ref["phidot"])) < 1e-11 * np.max(np.abs(ref["phidot"]))
+        assert np.max(np.abs(ctx.read_grid(fid, 0) - ref["gpsi"][0])) < 1e-12 * np.max(np.abs(ref["gpsi"][0]))
+    ctx.close()
+
+
+# -------------------------------------------------------------------- push --
+
+def _run_gpu(cfg, n_steps=None):
+    ctx, fields, species = fastdf.setup_workload(cfg)
+    ctx.step(cfg["n_steps"] if n_steps is None else n_steps)
+    x, q = ctx.read_state(species[0])
+    w = ctx.weights(species[0]).cpu().numpy()
+    return ctx, species, x, q, w
+
+
+def test_c1_full_parity_fp64():
+    """c1 at its full size: 32^3 particles, 32^3 mesh, 50 steps z = 1e6 -> 31."""
+    say("c1 full fp64")
+    cfg = workloads.preset("c1")
+    ctx, species, x, q, w = _run_gpu(cfg)
+    ref = pipeline.run_particles(cfg, 0, np.arange(32 ** 3))
+    L = cfg["box_mpc"]
+    assert np.max(np.abs(periodic_diff(x, ref["x"], L))) < 1e-5 * L
+    assert np.max(np.abs(q - ref["q"])) < 1e-5 * np.max(np.abs(ref["q"]))
+    assert np.max(np.abs(q - ref["q"]) / np.abs(ref["q"]).max()) < 1e-9   # in practice
+    assert np.allclose(w, ref["w"], rtol=1e-5, atol=1e-7 * np.abs(ref["w"]).max())
+    # P(k): cross spectrum of the even/odd halves and the auto spectrum
+    for mode in ("cross", "auto"):
+        k, p, nm = ctx.power_spectrum(species, cfg["pk_bins"], mode)
+        (kr, pr, nr), _ = pipeline.density_spectrum(cfg, 0, ref, mode)
+        assert np.array_equal(nm, nr)
+        ok = nr > 0
+        assert np.allclose(k[ok], kr[ok], rtol=1e-12)
+        assert np.allclose(p[ok], pr[ok], rtol=1e-6, atol=1e-9 * np.abs(pr[ok]).max())
+        assert np.all(np.isnan(p[~ok]))
+    ctx.close()
+
+
+@pytest.mark.parametrize("G,n_side,steps", [(16, 13, 12), (32, 24, 7)])
+def test_slip_parity_fp64_ragged(G, n_side, steps):
+    """psi != phi (8-slot grids) with particle counts that leave a ragged last block."""
+    say("slip fp64 G=%d n=%d^3" % (G, n_side))
+    cfg = workloads.small("c2", grid_n=G, n_side=n_side, n_steps=steps, precision="fp64",
+                          box_mpc=500.0, z_begin=1e6, z_end=31.0)
+    ctx, species, x, q, w = _run_gpu(cfg)
+    ids = np.arange(n_side ** 3)
+    ref = pipeline.run_particles(cfg, 0, ids)
+    L = cfg["box_mpc"]
+    assert np.max(np.abs(periodic_diff(x, ref["x"], L))) < 1e-5 * L
+    assert np.max(np.abs(q - ref["q"])) < 1e-9 * np.max(np.abs(ref["q"]))
+    assert np.allclose(w, ref["w"], rtol=1e-5, atol=1e-7 * np.abs(ref["w"]).max())
+    ctx.close()
+
+
+def test_split_calls_equal_one_call_and_reversibility():
+    """step(a) + step(b) equals step(a + b) bit for bit; a backward walk returns
+    to the start (P3) within rounding."""
+    say("split steps + reversibility fp64")
+    cfg = workloads.small("c2", grid_n=16, n_side=16, n_steps=10, precision="fp64", box_mpc=500.0,
+                          z_begin=1e6, z_end=31.0)
+    ctx, fields, species = fastdf.setup_workload(cfg)
+    x0, q0 = ctx.read_state(species[0])
+    ctx.step(10)
+    x1, q1 = ctx.read_state(species[0])
+    ctx.step(-10)
+    xb, qb = ctx.read_state(species[0])
+    L = cfg["box_mpc"]
+    assert np.max(np.abs(periodic_diff(xb, x0, L))) < 1e-11 * L
+    assert np.max(np.abs(qb - q0)) < 1e-11 * np.max(np.abs(q0))
+    ctx2, _, sp2 = fastdf.setup_workload(cfg)
+    ctx2.step(3)
+    ctx2.step(7)
+    x2, q2 = ctx2.read_state(sp2[0])
+    # split calls add the two half-kicks at the seam separately: rounding only
+    assert np.max(np.abs(periodic_diff(x2, x1, L))) < 1e-12 * L
+    assert np.max(np.abs(q2 - q1)) < 1e-13 * np.max(np.abs(q1))
+    ctx.close()
+    ctx2.close()
+
+
+def test_radmat_parity_phidot_term():
+    """Time-dependent potentials: grids rebuilt at every kick time, phi-dot acts."""
+    say("radmat fp64")
+    cfg = workloads.small("c2", grid_n=16, n_side=12, n_steps=10, precision="fp64", model="radmat",
+                          omega_m=0.9999, omega_r=1e-4, box_mpc=500.0, z_begin=1e5, z_end=100.0)
+    ctx, species, x, q, w = _run_gpu(cfg)
+    ref = pipeline.run_particles(cfg, 0, np.arange(12 ** 3))
+    L = cfg["box_mpc"]
+    assert np.max(np.abs(periodic_diff(x, ref["x"], L))) < 1e-5 * L
+    assert np.max(np.abs(q - ref["q"])) < 1e-9 * np.max(np.abs(ref["q"]))
+    ctx.close()
+
+
+def test_pre_initial_conditions_parity():
+    say("pre-IC fp64")
+    cfg = workloads.small("c2", grid_n=16, n_side=12, n_steps=6, precision="fp64", box_mpc=800.0,
+                          z_begin=1e9, z_end=1e5, pre_ic=True)
+    ctx, fields, species = fastdf.setup_workload(cfg)
+    x0, q0 = ctx.read_state(species[0])
+    ids = np.arange(12 ** 3)
+    ref = pipeline.run_particles(cfg, 0, ids, k_end=0)
+    assert np.max(np.abs(q0 - ref["q"])) <= 2.5e-7 * np.max(np.abs(ref["q"]))
+    w0 = ctx.weights(species[0]).cpu().numpy()
+    # w depends on |q| - |p| ~ 1e-5 |p|: a rare last-bit flip of a binary32
+    # momentum component moves it by up to ~1%, so compare the bulk tightly
+    close = np.isclose(w0, ref["w"], rtol=1e-6, atol=1e-9 * np.abs(ref["w"]).max())
+    assert np.mean(close) > 0.995
+    ctx.close()
+
+
+def test_zero_field_free_streaming_and_zero_weights():
+    """P1/P2 on the GPU: zero potentials leave q unchanged, weights exactly 0, and
+    x follows the discrete free-streaming sum."""
+    say("free streaming hand-placed fp64 + fp32")
+    for prec in ("fp64", "fp32"):
+        cfg = workloads.small("c1", grid_n=16, n_side=4, n_steps=20, precision=prec, box_mpc=400.0)
+        ctx = fastdf.Context(cfg)
+        fid = ctx.set_field(np.zeros((16, 16, 9), dtype=complex))
+        xu, qf = workloads.hand_placed(100, cfg["box_mpc"])
+        sid = ctx.set_species_state(fid, 0.1, xu, qf)
+        ctx.step(20)
+        x, q = ctx.read_state(sid)
+        w = ctx.weights(sid).cpu().numpy()
+        q0 = qf.astype(np.float64)
+        assert np.array_equal(q, q0) and np.all(w == 0.0)
+        sched = pipeline.schedule(cfg)
+        x0 = xu.astype(np.float64) * (cfg["box_mpc"] / 2 ** 32)
+        s = sum(sched["drift"][k] / np.sqrt(np.sum(q0 ** 2, 1) + (0.1 * sched["a_half"][k]) ** 2)
+                for k in range(20))
+        ref = np.mod(x0 + q0 * s[:, None], cfg["box_mpc"])
+        tol = 1e-12 if prec == "fp64" else 1e-6
+        assert np.max(np.abs(periodic_diff(x, ref, cfg["box_mpc"]))) < tol * cfg["box_mpc"]
+        ctx.close()
+
+
+def test_fp32_form_error_statement_small():
+    """FP32 form against the FP64 oracle from the same canonical state; bounds
+    are the stated per-result errors of the precision form."""
+    say("fp32 form small G=32")
+    cfg = workloads.small("c3", grid_n=32, n_side=32, n_steps=100, precision="fp32",
+                          box_mpc=500.0, z_begin=1e9, z_end=0.0, sort_every=0)
+    ctx, species, x, q, w = _run_gpu(cfg)
+    ids = workloads.sample_ids(32 ** 3, 2000)
+    ref = pipeline.run_particles(cfg, 0, ids)
+    L, G = cfg["box_mpc"], cfg["grid_n"]
+    dx = periodic_diff(x[ids], ref["x"], L) * (G / L)        # in cells
+    pos_rms = np.sqrt(np.mean(np.sum(dx ** 2, 1)))
+    qn_ref = np.linalg.norm(ref["q"], axis=1)
+    qrel = np.abs(np.linalg.norm(q[ids], axis=1) - qn_ref) / qn_ref
+    say("fp32 small: pos rms %.3e cells, |q| rel rms %.3e max %.3e" %
+        (pos_rms, np.sqrt(np.mean(qrel ** 2)), qrel.max()))
+    assert pos_rms < 1e-2
+    assert np.sqrt(np.mean(qrel ** 2)) < 1e-3
+    ctx.close()
