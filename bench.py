@@ -1,0 +1,263 @@
+#!/usr/bin/env python3
+"""Benchmark of the FastDF neutrino push on one MI355X.
+
+One bench "step" is one whole job of the hot path on resident synthetic
+input: seeded field, particle sample, potential grids (Fourier stage + 3-D
+C2R FFT), the full leapfrog schedule (one push launch per step), delta-f
+weights, and the CIC-deposit + binned cross power spectrum.  The default
+workload is the precision form: 512^3 neutrinos (m = 0.1 eV) on a 512^3
+bfloat16 gradient mesh in a 1 Gpc box, 1000 steps from z = 1e9 to z = 0,
+FP32 push with 32-bit fixed-point positions and Kahan-compensated momenta.
+
+Printed: one JSON line with particle-updates/s over the whole job, the push
+kernel's achieved HBM bandwidth against the 8 TB/s peak (from HIP events on
+the library's stream), the same job in the FP64 form for the speedup and the
+P(k) difference, and the FP64 CPU oracle timed on a bounded sample.
+
+    python bench.py [--steps K] [--warmup W] [--workload c3] [--no-fp64-leg]
+                    [--no-cpu-baseline]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+METRIC = "particle-updates/s & HBM GB/s, FP32-fixed-pt vs FP64 push at stated P(k) error"
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def bytes_per_launch(cfg, n_particles, drift):
+    """Algorithmic HBM bytes of one push launch: state read + write per
+    particle, plus one read of the gradient mesh.  FP32 form: read x, q, c, q0
+    (48 B), write x, q, c (36 B; 24 B without the drift); FP64 form: read x, q,
+    q0 (72 B), write x, q (48 B; 24 B without the drift)."""
+    G = cfg["grid_n"]
+    nslot = 8 if cfg.get("slip_amp", 0.0) else 4
+    if cfg["precision"] == "fp32":
+        per = 48 + (36 if drift else 24)
+        grid = G ** 3 * nslot * 2
+    else:
+        per = 72 + (48 if drift else 24)
+        grid = G ** 3 * nslot * 8
+    return n_particles * per + grid
+
+
+def run_leg(cfg, steps, warmup, label):
+    import torch
+    from paper_2207_14256_amd import fastdf
+    n_total = sum(int(sp["n_side"]) ** 3 for sp in cfg["species"])
+    ctx = fastdf.Context(cfg)
+    wbuf = torch.empty(max(int(sp["n_side"]) ** 3 for sp in cfg["species"]),
+                       dtype=torch.float64, device="cuda")
+
+    def job():
+        _, fields, species = fastdf.setup_workload(cfg, ctx=ctx)
+        ctx.step(cfg["n_steps"])
+        for s in species:
+            ctx.weights(s, out=wbuf)
+        return ctx.power_spectrum(species, cfg["pk_bins"], "cross")
+
+    for i in range(warmup):
+        job()
+        log("%s warmup %d/%d done" % (label, i + 1, warmup))
+    ctx.timing(True)
+    ctx.timing_reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pk = None
+    for i in range(steps):
+        pk = job()
+        log("%s step %d/%d done" % (label, i + 1, steps))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    push_ms, launches = ctx.read_timing("push")
+    grid_ms, _ = ctx.read_timing("grid")
+    out_ms, _ = ctx.read_timing("output")
+    init_ms, _ = ctx.read_timing("init")
+    ctx.close()
+    del ctx
+    torch.cuda.empty_cache()
+    n = cfg["n_steps"]
+    job_s = (t1 - t0) / steps
+    per_job_launches = launches // steps
+    total_bytes = steps * (n * bytes_per_launch(cfg, n_total, True)
+                           + (per_job_launches - n) * bytes_per_launch(cfg, n_total, False))
+    avg_launch_ms = push_ms / launches
+    achieved = total_bytes / launches / (avg_launch_ms * 1e-3) / 1e9
+    return dict(job_s=job_s, updates_per_s=n_total * n / job_s, push_ms=push_ms, launches=launches,
+                avg_launch_ms=avg_launch_ms, bytes_per_launch=total_bytes / launches,
+                achieved_gbs=achieved, grid_ms_per_job=grid_ms / steps, output_ms_per_job=out_ms / steps,
+                init_ms_per_job=init_ms / steps, pk=pk, n_particles=n_total)
+
+
+def traffic_from_profile(workload):
+    """HBM bytes per push launch from committed rocprofv3 counter summaries,
+    if they were taken on the current push kernel source."""
+    path = os.path.join(ROOT, "profiles", "push_%s_traffic.json" % workload)
+    src = os.path.join(ROOT, "paper_2207_14256_amd", "csrc", "fdf_push.hip")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if rec.get("push_source_sha256") != sha:
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def _cpu_worker(cfg, queue):
+    try:
+        queue.put(cpu_baseline(cfg))
+    except Exception as exc:  # reported, never fatal for the GPU result
+        queue.put({"error": repr(exc)})
+
+
+def cpu_baseline(cfg, n_sample=32768, n_steps=40):
+    """The FP64 oracle (numpy, one thread) on a bounded sample of the same
+    workload: its own field and gradient grids at full mesh size, then
+    n_sample particles pushed through the first n_steps steps."""
+    import numpy as np
+    from oracle import field, particles, pipeline, push
+    t0 = time.perf_counter()
+    sched = pipeline.schedule(cfg)
+    d0 = pipeline.delta0(cfg)
+    grids = field.potential_grids(d0, cfg["box_mpc"], sched["a"][0], pipeline.model_of(cfg))
+    t_setup = time.perf_counter() - t0
+    log("cpu oracle: field + grids %.1f s" % t_setup)
+    sp = cfg["species"][0]
+    n_all = sp["n_side"] ** 3
+    ids = np.arange(0, n_all, n_all // n_sample)[:n_sample]
+    x0 = particles.positions_f64(sp["seed"], ids, cfg["box_mpc"])
+    q0 = particles.momenta_f64(sp["seed"], ids)
+    t1 = time.perf_counter()
+    push.kdk(x0, q0, q0, sp["m"], sched, cfg["box_mpc"], lambda k: grids, 0, n_steps)
+    t_push = time.perf_counter() - t1
+    rate = n_sample * n_steps / t_push
+    return dict(value=rate, unit="particle-updates/s", cores=1, kind="oracle",
+                sample="FP64 numpy oracle, 1 thread: %d of %d particles pushed through steps 0-%d "
+                       "of the %d-step schedule on the oracle's own %d^3 FP64 grids (%.1f s push; "
+                       "field + grid build %.1f s not in the rate)" % (
+                           n_sample, n_all, n_steps - 1, cfg["n_steps"], cfg["grid_n"], t_push, t_setup))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c3")
+    ap.add_argument("--no-fp64-leg", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        return 2
+
+    import multiprocessing as mp
+
+    from paper_2207_14256_amd import workloads
+    cfg = workloads.preset(args.workload)
+    # the oracle (CPU only, numpy) runs in a spawned process while the GPU legs run
+    cpu_proc = cpu_queue = None
+    if not args.no_cpu_baseline:
+        mpc = mp.get_context("spawn")
+        cpu_queue = mpc.Queue()
+        cpu_proc = mpc.Process(target=_cpu_worker, args=(cfg, cpu_queue), daemon=True)
+        cpu_proc.start()
+
+    import numpy as np
+    import torch
+    from paper_2207_14256_amd import fastdf
+    fastdf.load()
+    torch.cuda.set_device(0)
+    log("workload %s: precision %s" % (args.workload, cfg["precision"]))
+    main_leg = run_leg(cfg, args.steps, args.warmup, args.workload)
+    log("%s: %.3e updates/s, push %.3f ms/launch, %.0f GB/s" % (
+        args.workload, main_leg["updates_per_s"], main_leg["avg_launch_ms"], main_leg["achieved_gbs"]))
+
+    fp64 = None
+    if not args.no_fp64_leg and cfg["precision"] == "fp32":
+        cfg64 = workloads.preset(args.workload, precision="fp64")
+        leg = run_leg(cfg64, max(1, args.steps - 1), 1, args.workload + "-fp64")
+        k32, p32, n32 = main_leg["pk"]
+        k64, p64, n64 = leg["pk"]
+        kn = np.pi * cfg["grid_n"] / cfg["box_mpc"]
+        sel = (n64 > 0) & (k64 <= kn / 2)
+        rel = np.abs(p32[sel] / p64[sel] - 1.0)
+        fp64 = dict(updates_per_s=leg["updates_per_s"], ms_per_step=leg["job_s"] * 1e3,
+                    push_ms_per_launch=leg["avg_launch_ms"], push_achieved_gbs=leg["achieved_gbs"],
+                    push_roofline_frac=leg["achieved_gbs"] / PEAK_HBM_GBS,
+                    pk_rel_err_fp32_vs_fp64_max=float(rel.max()),
+                    pk_rel_err_fp32_vs_fp64_rms=float(np.sqrt(np.mean(rel ** 2))),
+                    pk_bins_compared="k <= k_N/2 (%d bins)" % int(sel.sum()))
+        log("fp64 leg: %.3e updates/s, P(k) fp32/fp64 max rel diff %.2e" % (
+            leg["updates_per_s"], rel.max()))
+
+    cpu = None
+    if cpu_proc is not None:
+        log("waiting for the cpu oracle sample")
+        while cpu_proc.is_alive() and cpu_queue.empty():
+            time.sleep(5)
+            log("cpu oracle still running")
+        cpu = cpu_queue.get(timeout=60)
+        cpu_proc.join(timeout=60)
+    traffic = traffic_from_profile(args.workload)
+    out = {
+        "metric": METRIC,
+        "value": main_leg["updates_per_s"],
+        "unit": "particle-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_leg["job_s"] * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if cfg["precision"] == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "%s: %d^3 neutrinos m=%g eV, %d^3 %s gradient mesh, L=%g Mpc, %d steps "
+                        "z=%g->%g, %s" % (
+                            args.workload, cfg["species"][0]["n_side"], cfg["species"][0]["m"],
+                            cfg["grid_n"], "bf16" if cfg["precision"] == "fp32" else "f64",
+                            cfg["box_mpc"], cfg["n_steps"], cfg["z_begin"], cfg["z_end"],
+                            "FP32 push, uint32 fixed-point x, Kahan q" if cfg["precision"] == "fp32"
+                            else "FP64 push"),
+            "particles": main_leg["n_particles"], "grid_n": cfg["grid_n"],
+            "push_steps_per_job": cfg["n_steps"],
+            "job": "field + sample + grid FFT + all push steps + weights + deposit/P(k)",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": main_leg["achieved_gbs"],
+            "peak": PEAK_HBM_GBS,
+            "unit": "GB/s",
+            "frac": main_leg["achieved_gbs"] / PEAK_HBM_GBS,
+            "traffic": traffic,
+            "kernel": "k_push_f32" if cfg["precision"] == "fp32" else "k_push_f64",
+            "avg_launch_ms": main_leg["avg_launch_ms"],
+            "algorithmic_bytes_per_launch": main_leg["bytes_per_launch"],
+        },
+        "hbm_gbs": main_leg["achieved_gbs"],
+        "breakdown_ms_per_job": {
+            "push": main_leg["push_ms"] / args.steps, "grid": main_leg["grid_ms_per_job"],
+            "output": main_leg["output_ms_per_job"], "init": main_leg["init_ms_per_job"]},
+        "fp64_leg": fp64,
+        "speedup_vs_fp64": (main_leg["updates_per_s"] / fp64["updates_per_s"]) if fp64 else None,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -59,7 +59,7 @@ def preset(name, **overrides):
     return cfg
 
 
-def small(name="c1", grid_n=16, n_side=16, n_steps=12, **kw):
+def small(name="c1", grid_n=16, n_side=16, n_steps=50, **kw):
     """A reduced copy of a preset for quick parity cases (same physics)."""
     cfg = preset(name, grid_n=grid_n, n_steps=n_steps, **kw)
     for sp in cfg["species"]:
