@@ -122,6 +122,17 @@ typedef struct fdf_info {
   size_t workspace_used;   /* bytes of the workspace in use */
 } fdf_info;
 
+/* Launch and sort parameters (picked by the autotuner or set by hand).  None
+ * changes results: the push is per particle and the sort only permutes. */
+typedef struct fdf_tuning {
+  int32_t particles_per_thread;  /* push: 1, 2, 4 or 8 */
+  int32_t sort_tiles;            /* tiles per axis of the sort key: a power of two
+                                    <= min(G/2, 256); 0 selects min(G/2, 256) */
+  int32_t sort_every;            /* re-sort cadence in steps; 0 never.  Values > 0
+                                    need a context created with sort_every > 0 */
+  int32_t reserved;
+} fdf_tuning;
+
 /* ---- lifetime -------------------------------------------------------------- */
 
 /* Bytes of device workspace a context with this configuration needs (host only;
@@ -220,6 +231,11 @@ int fdf_read_density(struct fdf_ctx* ctx, int32_t half, double* h_grid);
 int fdf_read_schedule(const struct fdf_ctx* ctx, double* h_table);
 
 int fdf_get_info(const struct fdf_ctx* ctx, fdf_info* info);
+
+/* Read or replace the launch and sort parameters.  Errors: FDF_ERR_ARG for a
+ * value outside the ranges documented in fdf_tuning. */
+int fdf_get_tuning(const struct fdf_ctx* ctx, fdf_tuning* tuning);
+int fdf_set_tuning(struct fdf_ctx* ctx, const fdf_tuning* tuning);
 int fdf_sync(struct fdf_ctx* ctx);
 
 /* Per-kernel-class timing with HIP events on the context stream. */

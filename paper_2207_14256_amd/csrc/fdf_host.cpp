@@ -144,7 +144,8 @@ int ilog2(int v) { int r = 0; while ((1 << r) < v) ++r; return r; }
 
 // ----------------------------------------------------------------- layout --
 struct Layout {
-  size_t twiddle_d, twiddle_f, seg, bins, scratch, dens, fields, parts, total;
+  size_t twiddle_d, twiddle_f, seg, bins, scratch, dens, fields, parts, sort_count, sort_scan, total;
+  int64_t sort_keys_max;
   size_t field_dk_bytes, field_grid_bytes, scratch_bytes, dens_bytes, parts_bytes;
   int nslot;
 };
@@ -169,12 +170,16 @@ Layout plan(const fdf_config& c) {
   size_t off = 0;
   L.twiddle_d = off; off += align_up(G * 16);
   L.twiddle_f = off; off += align_up(G * 8);
-  L.seg = off; off += align_up((size_t)c.max_species * sizeof(Segment));
+  L.seg = off; off += 2 * align_up((size_t)c.max_species * sizeof(Segment));
   L.bins = off; off += align_up(3 * kMaxBins * sizeof(double));
   L.scratch = off; off += L.scratch_bytes;
   L.dens = off; off += L.dens_bytes;
   L.fields = off; off += (size_t)c.max_fields * (L.field_dk_bytes + L.field_grid_bytes);
   L.parts = off; off += L.parts_bytes;
+  const int64_t tmax = std::min<int64_t>(c.grid_n / 2, 256);
+  L.sort_keys_max = c.sort_every > 0 ? tmax * tmax * tmax : 0;
+  L.sort_count = off; off += align_up((size_t)L.sort_keys_max * 4);
+  L.sort_scan = off; off += c.sort_every > 0 ? align_up(sort_scan_scratch_words(L.sort_keys_max) * 4) : 0;
   L.total = off;
   return L;
 }
@@ -244,6 +249,8 @@ struct fdf_ctx {
   bool stepped = false;
   bool seg_dirty = true;
   int ppt = 4;
+  int sort_tiles = 0;       // tiles per axis of the sort key (0: default)
+  int sort_every = 0;       // current re-sort cadence
   std::string err;
   bool timing = false;
   TimingRec tim[FDF_KERNEL_COUNT];
@@ -387,25 +394,59 @@ int build_grid(fdf_ctx* c, int field, double a) {
   return launched(c, "grid build");
 }
 
+// Two device tables of segments: one per buffer copy (all species sort together,
+// so they always sit in the same copy).
 int upload_segments(fdf_ctx* c) {
   if (!c->seg_dirty) return FDF_OK;
-  std::vector<Segment> segs;
-  int64_t chunk = 0;
   const int64_t per = push_chunk_particles(c->ppt);
-  for (auto& s : c->species) {
-    Segment g = s.seg[s.cur];
-    g.grid = c->fields[s.field].grid;
-    g.m = s.m;
-    g.chunk_begin = chunk;
-    chunk += (s.n + per - 1) / per;
-    segs.push_back(g);
+  const size_t table = align_up((size_t)c->cfg.max_species * sizeof(Segment));
+  for (int copy = 0; copy < 2; ++copy) {
+    std::vector<Segment> segs;
+    int64_t chunk = 0;
+    for (auto& s : c->species) {
+      Segment g = s.seg[copy];
+      g.grid = c->fields[s.field].grid;
+      g.m = s.m;
+      g.chunk_begin = chunk;
+      chunk += (s.n + per - 1) / per;
+      segs.push_back(g);
+    }
+    int rc = hip_check(c, hipMemcpyAsync(c->ws + c->lay.seg + copy * table, segs.data(),
+                                         segs.size() * sizeof(Segment), hipMemcpyHostToDevice, c->stream),
+                       "segment upload");
+    if (rc) return rc;
   }
-  int rc = hip_check(c, hipMemcpyAsync(c->ws + c->lay.seg, segs.data(), segs.size() * sizeof(Segment),
-                                       hipMemcpyHostToDevice, c->stream), "segment upload");
-  if (rc) return rc;
-  rc = hip_check(c, hipStreamSynchronize(c->stream), "segment upload");
+  int rc = hip_check(c, hipStreamSynchronize(c->stream), "segment upload");
   c->seg_dirty = false;
   return rc;
+}
+
+int sort_tiles_of(fdf_ctx* c) {
+  int t = c->sort_tiles > 0 ? c->sort_tiles : std::min(c->cfg.grid_n / 2, 256);
+  return std::min(t, std::min(c->cfg.grid_n / 2, 256));
+}
+
+// Spatial re-sort of every species into its other buffer copy.
+int sort_species(fdf_ctx* c) {
+  const int tiles = sort_tiles_of(c);
+  std::pair<hipEvent_t, hipEvent_t> ev;
+  timing_begin(c, FDF_KERNEL_SORT, &ev);
+  for (auto& s : c->species) {
+    SortArgs a{};
+    a.seg = s.seg[s.cur];
+    a.dst = s.seg[s.cur ^ 1];
+    a.fp64 = c->cfg.precision == FDF_PREC_FP64;
+    a.tiles = tiles;
+    a.shift = 32 - ilog2(tiles);
+    a.box = c->cfg.box_mpc;
+    a.nkeys = (int64_t)tiles * tiles * tiles;
+    a.count = (uint32_t*)(c->ws + c->lay.sort_count);
+    a.scan_scratch = (uint32_t*)(c->ws + c->lay.sort_scan);
+    launch_sort(a, c->stream);
+    s.cur ^= 1;
+  }
+  timing_end(c, FDF_KERNEL_SORT, ev);
+  return launched(c, "sort");
 }
 
 int64_t total_chunks(fdf_ctx* c) {
@@ -537,6 +578,7 @@ int fdf_create(const fdf_config* cfg, void* stream, fdf_ctx** out) {
     return FDF_ERR_ARG;
   }
   c->amp = power_amplitude(cfg->sigma8, cfg->ns, cfg->gamma, cfg->h);
+  c->sort_every = cfg->sort_every;
   c->tau_begin = conformal_time(c->cos, c->a[0]);
   *out = c;
   return FDF_OK;
@@ -715,8 +757,9 @@ int fdf_step(fdf_ctx* c, int32_t n) {
   if (rc) return rc;
   std::vector<int> used(c->fields.size(), 0);
   for (auto& s : c->species) used[s.field] = 1;
+  const size_t table = align_up((size_t)c->cfg.max_species * sizeof(Segment));
+  const int sort_every = c->sort_every;
   PushArgs pa{};
-  pa.seg = (const Segment*)(c->ws + c->lay.seg);
   pa.nseg = (int)c->species.size();
   pa.total_chunks = total_chunks(c);
   pa.fp64 = c->cfg.precision == FDF_PREC_FP64;
@@ -746,6 +789,11 @@ int fdf_step(fdf_ctx* c, int32_t n) {
         if (rc) return rc;
       }
     }
+    if (sort_every > 0 && j < nabs && t % sort_every == 0) {
+      rc = sort_species(c);
+      if (rc) return rc;
+    }
+    pa.seg = (const Segment*)(c->ws + c->lay.seg + c->species[0].cur * table);
     pa.kick = kick;
     pa.a_kick = a_kick;
     pa.do_drift = j < nabs;
@@ -983,6 +1031,31 @@ int fdf_get_info(const fdf_ctx* c, fdf_info* info) {
   info->n_species = (int32_t)c->species.size();
   for (auto& s : c->species) info->n_particles += s.n;
   info->workspace_used = c->lay.total;
+  return FDF_OK;
+}
+
+int fdf_get_tuning(const fdf_ctx* c, fdf_tuning* t) {
+  if (!c || !t) return FDF_ERR_ARG;
+  std::memset(t, 0, sizeof(*t));
+  t->particles_per_thread = c->ppt;
+  t->sort_tiles = c->sort_tiles;
+  t->sort_every = c->sort_every;
+  return FDF_OK;
+}
+
+int fdf_set_tuning(fdf_ctx* c, const fdf_tuning* t) {
+  if (!c || !t) return FDF_ERR_ARG;
+  const int p = t->particles_per_thread;
+  if (p != 1 && p != 2 && p != 4 && p != 8) return fail(c, FDF_ERR_ARG, "particles_per_thread must be 1, 2, 4 or 8");
+  const int tmax = std::min(c->cfg.grid_n / 2, 256);
+  if (t->sort_tiles != 0 && (!is_pow2(t->sort_tiles) || t->sort_tiles > tmax))
+    return fail(c, FDF_ERR_ARG, "sort_tiles must be 0 or a power of two <= min(G/2, 256)");
+  if (t->sort_every < 0 || (t->sort_every > 0 && c->cfg.sort_every == 0))
+    return fail(c, FDF_ERR_ARG, "sorting needs a context created with sort_every > 0");
+  if (p != c->ppt) c->seg_dirty = true;   // chunk boundaries depend on the block size
+  c->ppt = p;
+  c->sort_tiles = t->sort_tiles;
+  c->sort_every = t->sort_every;
   return FDF_OK;
 }
 

@@ -95,6 +95,19 @@ struct PushArgs {
   int32_t block;           // threads per block
 };
 
+struct SortArgs {
+  Segment seg;             // source copy
+  Segment dst;             // destination copy
+  int32_t fp64;
+  int32_t tiles;           // tiles per axis (the mesh side divided by the tile side)
+  int32_t shift;           // 32 - log2(tiles): tile coordinate of a fixed-point position
+  double box;
+  int64_t nkeys;           // tiles^3
+  uint32_t* count;         // [nkeys] counts, scanned in place into bucket starts
+  uint32_t* offset;        // bucket cursors used by the scatter
+  uint32_t* scan_scratch;  // sort_scan_scratch_words(nkeys) words
+};
+
 struct SampleArgs {
   Segment seg;
   int32_t fp64;
@@ -144,5 +157,7 @@ void launch_deposit(const OutputArgs& a, hipStream_t s);
 void launch_power_spectrum(const PkArgs& a, hipStream_t s);
 void launch_fill_zero(void* ptr, size_t bytes, hipStream_t s);
 int push_chunk_particles(int ppt);
+void launch_sort(const SortArgs& a, hipStream_t s);
+size_t sort_scan_scratch_words(int64_t nkeys);
 
 }  // namespace fdf

@@ -49,6 +49,7 @@ template <typename T> __device__ __forceinline__ void stnt(T v, T* p) { __builti
 template <int NSLOT>
 __device__ __forceinline__ void gather_bf16(const void* grid, const size_t* cell, const float* w,
                                             float* g /* 7 */) {
+#pragma clang fp contract(off)
 #pragma unroll
   for (int s = 0; s < 7; ++s) g[s] = 0.0f;
   if constexpr (NSLOT == 8) {
@@ -58,10 +59,10 @@ __device__ __forceinline__ void gather_bf16(const void* grid, const size_t* cell
     for (int c = 0; c < 8; ++c) v[c] = gp[cell[c]];
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
-      g[0] += w[c] * bf16_lo(v[c].x); g[1] += w[c] * bf16_hi(v[c].x);
-      g[2] += w[c] * bf16_lo(v[c].y); g[3] += w[c] * bf16_hi(v[c].y);
-      g[4] += w[c] * bf16_lo(v[c].z); g[5] += w[c] * bf16_hi(v[c].z);
-      g[6] += w[c] * bf16_lo(v[c].w);
+      g[0] = fmaf(w[c], bf16_lo(v[c].x), g[0]); g[1] = fmaf(w[c], bf16_hi(v[c].x), g[1]);
+      g[2] = fmaf(w[c], bf16_lo(v[c].y), g[2]); g[3] = fmaf(w[c], bf16_hi(v[c].y), g[3]);
+      g[4] = fmaf(w[c], bf16_lo(v[c].z), g[4]); g[5] = fmaf(w[c], bf16_hi(v[c].z), g[5]);
+      g[6] = fmaf(w[c], bf16_lo(v[c].w), g[6]);
     }
   } else {
     const uint2* gp = (const uint2*)grid;
@@ -70,15 +71,20 @@ __device__ __forceinline__ void gather_bf16(const void* grid, const size_t* cell
     for (int c = 0; c < 8; ++c) v[c] = gp[cell[c]];
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
-      g[0] += w[c] * bf16_lo(v[c].x); g[1] += w[c] * bf16_hi(v[c].x);
-      g[2] += w[c] * bf16_lo(v[c].y); g[6] += w[c] * bf16_hi(v[c].y);
+      g[0] = fmaf(w[c], bf16_lo(v[c].x), g[0]); g[1] = fmaf(w[c], bf16_hi(v[c].x), g[1]);
+      g[2] = fmaf(w[c], bf16_lo(v[c].y), g[2]); g[6] = fmaf(w[c], bf16_hi(v[c].y), g[6]);
     }
     g[3] = g[0]; g[4] = g[1]; g[5] = g[2];
   }
 }
 
+// Every floating-point operation of the per-particle update is written out
+// (explicit fmaf, no contraction) so that the unrolled copies of the loop are
+// instruction-identical: a particle gets bit-identical results in whichever
+// slot of whichever block it lands after a re-sort.
 template <int NSLOT, int PPT>
 __global__ void __launch_bounds__(kBlock) k_push_f32(PushArgs a) {
+#pragma clang fp contract(off)
   const int64_t chunk = xcd_chunk(blockIdx.x, gridDim.x);
   const int s = find_segment(a.seg, a.nseg, chunk);
   const Segment& sg = a.seg[s];
@@ -86,11 +92,12 @@ __global__ void __launch_bounds__(kBlock) k_push_f32(PushArgs a) {
   const int64_t first = (chunk - sg.chunk_begin) * (int64_t)(kBlock * PPT) + threadIdx.x;
   const int shift = 32 - a.log2g;
   const uint32_t gmask = (uint32_t)a.G - 1u;
-  const uint32_t fmask = (shift >= 32) ? 0xFFFFFFFFu : ((1u << shift) - 1u);
+  const uint32_t fmask = (1u << shift) - 1u;
   const float finv = __uint_as_float((uint32_t)(127 - shift) << 23);   // 2^-shift
   const float kick = (float)a.kick;
   const float ma = (float)(sg.m * a.a_kick);
   const float mah = (float)(sg.m * a.a_drift);
+  const float ma2 = ma * ma, mah2 = mah * mah;
   const float dscale = (float)(a.drift * 4294967296.0 / a.box);
   const size_t G = (size_t)a.G;
 
@@ -109,12 +116,13 @@ __global__ void __launch_bounds__(kBlock) k_push_f32(PushArgs a) {
     }
     // CIC corners and weights from the fixed-point position
     uint32_t i0[3], i1[3];
-    float t[3];
+    float t[3], u[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       i0[d] = xu[d] >> shift;
       i1[d] = (i0[d] + 1u) & gmask;
       t[d] = (float)(xu[d] & fmask) * finv;
+      u[d] = 1.0f - t[d];
     }
     size_t cell[8];
     float w[8];
@@ -122,27 +130,29 @@ __global__ void __launch_bounds__(kBlock) k_push_f32(PushArgs a) {
     for (int cc = 0; cc < 8; ++cc) {
       const int cx = cc >> 2, cy = (cc >> 1) & 1, cz = cc & 1;
       cell[cc] = ((size_t)(cx ? i1[0] : i0[0]) * G + (cy ? i1[1] : i0[1])) * G + (cz ? i1[2] : i0[2]);
-      w[cc] = (cx ? t[0] : 1.0f - t[0]) * (cy ? t[1] : 1.0f - t[1]) * (cz ? t[2] : 1.0f - t[2]);
+      w[cc] = ((cx ? t[0] : u[0]) * (cy ? t[1] : u[1])) * (cz ? t[2] : u[2]);
     }
     float g[7];
     gather_bf16<NSLOT>(sg.grid, cell, w, g);
     // separable force of eq. releq_approx
-    const float q0sq = q0[0] * q0[0] + q0[1] * q0[1] + q0[2] * q0[2];
-    const float e0 = sqrtf(q0sq + ma * ma);
+    const float q0sq = fmaf(q0[0], q0[0], fmaf(q0[1], q0[1], q0[2] * q0[2]));
+    const float e0 = sqrtf(q0sq + ma2);
     const float ie0 = 1.0f / e0;
-    const float qg = (q0[0] * g[3] + q0[1] * g[4] + q0[2] * g[5]) * ie0 + g[6];
-    const float cphi = q0sq * ie0;
+    const float q0g = fmaf(q0[0], g[3], fmaf(q0[1], g[4], q0[2] * g[5]));
+    const float qg = fmaf(q0g, ie0, g[6]);          // (q0 . grad phi)/eps0 + phidot
+    const float cphi = q0sq * ie0;                    // q0^2 / eps0
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      const float F = -e0 * g[d] - cphi * g[3 + d] + q0[d] * qg;
+      const float F = fmaf(q0[d], qg, fmaf(-cphi, g[3 + d], -(e0 * g[d])));
       // Kahan-compensated q += kick * F
-      const float y = kick * F - c[d];
+      const float y = fmaf(kick, F, -c[d]);
       const float tq = q[d] + y;
       c[d] = (tq - q[d]) - y;
       q[d] = tq;
     }
     if (a.do_drift) {
-      const float ie = 1.0f / sqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + mah * mah);
+      const float qq = fmaf(q[0], q[0], fmaf(q[1], q[1], q[2] * q[2]));
+      const float ie = 1.0f / sqrtf(qq + mah2);
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         const int disp = __float2int_rn(dscale * (q[d] * ie));
@@ -160,6 +170,7 @@ __global__ void __launch_bounds__(kBlock) k_push_f32(PushArgs a) {
 template <int NSLOT>
 __device__ __forceinline__ void gather_f64(const void* grid, const size_t* cell, const double* w,
                                            double* g /* 7 */) {
+#pragma clang fp contract(off)
 #pragma unroll
   for (int s = 0; s < 7; ++s) g[s] = 0.0;
   const double2* gp = (const double2*)grid;
@@ -168,13 +179,13 @@ __device__ __forceinline__ void gather_f64(const void* grid, const size_t* cell,
     if constexpr (NSLOT == 8) {
       const double2 v0 = gp[4 * cell[c]], v1 = gp[4 * cell[c] + 1];
       const double2 v2 = gp[4 * cell[c] + 2], v3 = gp[4 * cell[c] + 3];
-      g[0] += w[c] * v0.x; g[1] += w[c] * v0.y; g[2] += w[c] * v1.x;
-      g[3] += w[c] * v1.y; g[4] += w[c] * v2.x; g[5] += w[c] * v2.y;
-      g[6] += w[c] * v3.x;
+      g[0] = fma(w[c], v0.x, g[0]); g[1] = fma(w[c], v0.y, g[1]); g[2] = fma(w[c], v1.x, g[2]);
+      g[3] = fma(w[c], v1.y, g[3]); g[4] = fma(w[c], v2.x, g[4]); g[5] = fma(w[c], v2.y, g[5]);
+      g[6] = fma(w[c], v3.x, g[6]);
     } else {
       const double2 v0 = gp[2 * cell[c]], v1 = gp[2 * cell[c] + 1];
-      g[0] += w[c] * v0.x; g[1] += w[c] * v0.y; g[2] += w[c] * v1.x;
-      g[6] += w[c] * v1.y;
+      g[0] = fma(w[c], v0.x, g[0]); g[1] = fma(w[c], v0.y, g[1]); g[2] = fma(w[c], v1.x, g[2]);
+      g[6] = fma(w[c], v1.y, g[6]);
     }
   }
   if constexpr (NSLOT == 4) { g[3] = g[0]; g[4] = g[1]; g[5] = g[2]; }
@@ -182,6 +193,7 @@ __device__ __forceinline__ void gather_f64(const void* grid, const size_t* cell,
 
 template <int NSLOT, int PPT>
 __global__ void __launch_bounds__(kBlock) k_push_f64(PushArgs a) {
+#pragma clang fp contract(off)
   const int64_t chunk = xcd_chunk(blockIdx.x, gridDim.x);
   const int s = find_segment(a.seg, a.nseg, chunk);
   const Segment& sg = a.seg[s];
@@ -220,24 +232,24 @@ __global__ void __launch_bounds__(kBlock) k_push_f64(PushArgs a) {
     for (int cc = 0; cc < 8; ++cc) {
       const int cx = cc >> 2, cy = (cc >> 1) & 1, cz = cc & 1;
       cell[cc] = ((size_t)(cx ? i1[0] : i0[0]) * G + (cy ? i1[1] : i0[1])) * G + (cz ? i1[2] : i0[2]);
-      w[cc] = (cx ? t[0] : 1.0 - t[0]) * (cy ? t[1] : 1.0 - t[1]) * (cz ? t[2] : 1.0 - t[2]);
+      w[cc] = ((cx ? t[0] : 1.0 - t[0]) * (cy ? t[1] : 1.0 - t[1])) * (cz ? t[2] : 1.0 - t[2]);
     }
     double g[7];
     gather_f64<NSLOT>(sg.grid, cell, w, g);
-    const double q0sq = q0[0] * q0[0] + q0[1] * q0[1] + q0[2] * q0[2];
+    const double q0sq = fma(q0[0], q0[0], fma(q0[1], q0[1], q0[2] * q0[2]));
     const double e0 = sqrt(q0sq + ma * ma);
-    const double qg = (q0[0] * g[3] + q0[1] * g[4] + q0[2] * g[5]) / e0;
+    const double qg = fma(q0[0], g[3], fma(q0[1], g[4], q0[2] * g[5])) / e0 + g[6];
     const double cphi = q0sq / e0;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      const double F = -e0 * g[d] - cphi * g[3 + d] + q0[d] * qg + q0[d] * g[6];
-      q[d] += a.kick * F;
+      const double F = fma(q0[d], qg, fma(-cphi, g[3 + d], -(e0 * g[d])));
+      q[d] = fma(a.kick, F, q[d]);
     }
     if (a.do_drift) {
-      const double e = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + mah * mah);
+      const double e = sqrt(fma(q[0], q[0], fma(q[1], q[1], q[2] * q[2])) + mah * mah);
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        double xn = fmod(x[d] + a.drift * (q[d] / e), a.box);   // floor-mod as numpy.mod
+        double xn = fmod(fma(a.drift, q[d] / e, x[d]), a.box);   // floor-mod as numpy.mod
         if (xn < 0.0) xn += a.box;
         stnt(xn, &sg.xd[d][i]);
       }

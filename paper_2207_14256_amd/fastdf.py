@@ -29,6 +29,7 @@ EXPORTS = [
     "fdf_read_state", "fdf_read_grid", "fdf_read_field", "fdf_read_density",
     "fdf_read_schedule", "fdf_get_info", "fdf_sync", "fdf_timing_enable",
     "fdf_read_timing", "fdf_timing_reset", "fdf_status_string", "fdf_last_error",
+    "fdf_get_tuning", "fdf_set_tuning",
 ]
 
 
@@ -56,6 +57,11 @@ class Info(ctypes.Structure):
         ("n_species", ctypes.c_int32), ("n_particles", ctypes.c_int64),
         ("workspace_used", ctypes.c_size_t),
     ]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("particles_per_thread", ctypes.c_int32), ("sort_tiles", ctypes.c_int32),
+                ("sort_every", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class FastDFError(RuntimeError):
@@ -100,6 +106,8 @@ def load():
         "fdf_sync": [P], "fdf_timing_enable": [P, I32],
         "fdf_read_timing": [P, I32, PD, ctypes.POINTER(I64)],
         "fdf_timing_reset": [P],
+        "fdf_get_tuning": [P, ctypes.POINTER(Tuning)],
+        "fdf_set_tuning": [P, ctypes.POINTER(Tuning)],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -306,6 +314,18 @@ class Context:
         self._check(self.lib.fdf_read_schedule(self.ctx, _dptr(t)), "fdf_read_schedule")
         return dict(a=t[:n + 1], a_half=t[n + 1:2 * n + 1], kick1=t[2 * n + 1:3 * n + 1],
                     kick2=t[3 * n + 1:4 * n + 1], drift=t[4 * n + 1:])
+
+    def get_tuning(self):
+        t = Tuning()
+        self._check(self.lib.fdf_get_tuning(self.ctx, ctypes.byref(t)), "fdf_get_tuning")
+        return dict(particles_per_thread=t.particles_per_thread, sort_tiles=t.sort_tiles,
+                    sort_every=t.sort_every)
+
+    def set_tuning(self, **kw):
+        cur = self.get_tuning()
+        cur.update(kw)
+        t = Tuning(cur["particles_per_thread"], cur["sort_tiles"], cur["sort_every"], 0)
+        self._check(self.lib.fdf_set_tuning(self.ctx, ctypes.byref(t)), "fdf_set_tuning")
 
     def sync(self):
         self._check(self.lib.fdf_sync(self.ctx), "fdf_sync")
