@@ -81,6 +81,7 @@ def run_leg(cfg, steps, warmup, label):
     t1 = time.perf_counter()
     push_ms, launches = ctx.read_timing("push")
     grid_ms, _ = ctx.read_timing("grid")
+    sort_ms, sorts = ctx.read_timing("sort")
     out_ms, _ = ctx.read_timing("output")
     init_ms, _ = ctx.read_timing("init")
     ctx.close()
@@ -96,7 +97,8 @@ def run_leg(cfg, steps, warmup, label):
     return dict(job_s=job_s, updates_per_s=n_total * n / job_s, push_ms=push_ms, launches=launches,
                 avg_launch_ms=avg_launch_ms, bytes_per_launch=total_bytes / launches,
                 achieved_gbs=achieved, grid_ms_per_job=grid_ms / steps, output_ms_per_job=out_ms / steps,
-                init_ms_per_job=init_ms / steps, pk=pk, n_particles=n_total)
+                init_ms_per_job=init_ms / steps, sort_ms_per_job=sort_ms / steps,
+                sorts_per_job=sorts / steps, pk=pk, n_particles=n_total)
 
 
 def traffic_from_profile(workload):
@@ -249,7 +251,8 @@ def main():
         },
         "hbm_gbs": main_leg["achieved_gbs"],
         "breakdown_ms_per_job": {
-            "push": main_leg["push_ms"] / args.steps, "grid": main_leg["grid_ms_per_job"],
+            "push": main_leg["push_ms"] / args.steps, "sort": main_leg["sort_ms_per_job"],
+            "sorts": main_leg["sorts_per_job"], "grid": main_leg["grid_ms_per_job"],
             "output": main_leg["output_ms_per_job"], "init": main_leg["init_ms_per_job"]},
         "fp64_leg": fp64,
         "speedup_vs_fp64": (main_leg["updates_per_s"] / fp64["updates_per_s"]) if fp64 else None,

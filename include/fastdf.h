@@ -126,11 +126,16 @@ typedef struct fdf_info {
  * changes results: the push is per particle and the sort only permutes. */
 typedef struct fdf_tuning {
   int32_t particles_per_thread;  /* push: 1, 2, 4 or 8 */
-  int32_t sort_tiles;            /* tiles per axis of the sort key: a power of two
-                                    <= min(G/2, 256); 0 selects min(G/2, 256) */
+  int32_t sort_tiles;            /* sort buckets per axis: a power of two <= min(G, 256);
+                                    particles are ordered by the Morton index of
+                                    their bucket, then of their cell inside it;
+                                    0 selects G/4 (4^3 cells per bucket) */
   int32_t sort_every;            /* re-sort cadence in steps; 0 never.  Values > 0
                                     need a context created with sort_every > 0 */
-  int32_t reserved;
+  float sort_cells;              /* > 0: adaptive cadence instead -- re-sort once the
+                                    typical drift since the last sort (mean-momentum
+                                    particle of the fastest species, in mesh cells)
+                                    reaches this value; 0: use sort_every */
 } fdf_tuning;
 
 /* ---- lifetime -------------------------------------------------------------- */

@@ -144,7 +144,8 @@ int ilog2(int v) { int r = 0; while ((1 << r) < v) ++r; return r; }
 
 // ----------------------------------------------------------------- layout --
 struct Layout {
-  size_t twiddle_d, twiddle_f, seg, bins, scratch, dens, fields, parts, sort_count, sort_scan, total;
+  size_t twiddle_d, twiddle_f, seg, bins, scratch, dens, fields, parts, sort_count, sort_scan, sort_rank,
+      sort_bucket, sort_src, total;
   int64_t sort_keys_max;
   size_t field_dk_bytes, field_grid_bytes, scratch_bytes, dens_bytes, parts_bytes;
   int nslot;
@@ -176,10 +177,14 @@ Layout plan(const fdf_config& c) {
   L.dens = off; off += L.dens_bytes;
   L.fields = off; off += (size_t)c.max_fields * (L.field_dk_bytes + L.field_grid_bytes);
   L.parts = off; off += L.parts_bytes;
-  const int64_t tmax = std::min<int64_t>(c.grid_n / 2, 256);
-  L.sort_keys_max = c.sort_every > 0 ? tmax * tmax * tmax : 0;
+  const int64_t tmax = std::min<int64_t>(c.grid_n, 256);
+  const bool sorting = c.sort_every > 0;
+  L.sort_keys_max = sorting ? tmax * tmax * tmax : 0;
   L.sort_count = off; off += align_up((size_t)L.sort_keys_max * 4);
-  L.sort_scan = off; off += c.sort_every > 0 ? align_up(sort_scan_scratch_words(L.sort_keys_max) * 4) : 0;
+  L.sort_scan = off; off += sorting ? align_up(sort_scan_scratch_words(L.sort_keys_max) * 4) : 0;
+  L.sort_rank = off; off += sorting ? align_up((size_t)c.max_particles * 4) : 0;
+  L.sort_bucket = off; off += sorting ? align_up((size_t)c.max_particles * 4) : 0;
+  L.sort_src = off; off += sorting ? align_up((size_t)c.max_particles * 4) : 0;
   L.total = off;
   return L;
 }
@@ -251,6 +256,9 @@ struct fdf_ctx {
   int ppt = 4;
   int sort_tiles = 0;       // tiles per axis of the sort key (0: default)
   int sort_every = 0;       // current re-sort cadence
+  float sort_cells = 0;     // adaptive cadence threshold in cells (0: fixed cadence)
+  double drift_cells = 0;   // typical drift since the last sort, in cells
+  bool sorted_once = false;
   std::string err;
   bool timing = false;
   TimingRec tim[FDF_KERNEL_COUNT];
@@ -421,9 +429,21 @@ int upload_segments(fdf_ctx* c) {
   return rc;
 }
 
+// Buckets per axis of the sort: default one per 4^3 cells, at most 256.
 int sort_tiles_of(fdf_ctx* c) {
-  int t = c->sort_tiles > 0 ? c->sort_tiles : std::min(c->cfg.grid_n / 2, 256);
-  return std::min(t, std::min(c->cfg.grid_n / 2, 256));
+  const int tmax = std::min(c->cfg.grid_n, 256);
+  int t = c->sort_tiles > 0 ? c->sort_tiles : std::max(1, c->cfg.grid_n / 4);
+  return std::min(t, tmax);
+}
+
+// Drift of a mean-momentum particle (|q| = 3.151 T) of the fastest species
+// over one drift of length dt at a, in mesh cells: the adaptive sort cadence.
+double typical_drift_cells(fdf_ctx* c, double dt, double a) {
+  const double q = 3.151374 * t_nu_ev();
+  double mmin = 1e300;
+  for (auto& s : c->species) mmin = std::min(mmin, s.m);
+  const double v = q / std::sqrt(q * q + mmin * mmin * a * a);
+  return std::fabs(dt) * v * c->cfg.grid_n / c->cfg.box_mpc;
 }
 
 // Spatial re-sort of every species into its other buffer copy.
@@ -436,12 +456,16 @@ int sort_species(fdf_ctx* c) {
     a.seg = s.seg[s.cur];
     a.dst = s.seg[s.cur ^ 1];
     a.fp64 = c->cfg.precision == FDF_PREC_FP64;
-    a.tiles = tiles;
-    a.shift = 32 - ilog2(tiles);
+    a.grid_n = c->cfg.grid_n;
+    a.cell_shift = 32 - ilog2(c->cfg.grid_n);
+    a.fine_bits = ilog2(c->cfg.grid_n / tiles);
     a.box = c->cfg.box_mpc;
     a.nkeys = (int64_t)tiles * tiles * tiles;
     a.count = (uint32_t*)(c->ws + c->lay.sort_count);
     a.scan_scratch = (uint32_t*)(c->ws + c->lay.sort_scan);
+    a.rank = (uint32_t*)(c->ws + c->lay.sort_rank);
+    a.bucket = (uint32_t*)(c->ws + c->lay.sort_bucket);
+    a.src = (uint32_t*)(c->ws + c->lay.sort_src);
     launch_sort(a, c->stream);
     s.cur ^= 1;
   }
@@ -604,6 +628,8 @@ int fdf_reset(fdf_ctx* c) {
   c->stepped = false;
   c->seg_dirty = true;
   c->have_density = false;
+  c->drift_cells = 0;
+  c->sorted_once = false;
   return FDF_OK;
 }
 
@@ -789,9 +815,21 @@ int fdf_step(fdf_ctx* c, int32_t n) {
         if (rc) return rc;
       }
     }
-    if (sort_every > 0 && j < nabs && t % sort_every == 0) {
-      rc = sort_species(c);
-      if (rc) return rc;
+    if (j < nabs) {
+      bool do_sort = false;
+      if (c->sort_cells > 0) {
+        do_sort = !c->sorted_once || c->drift_cells >= c->sort_cells;
+      } else if (sort_every > 0) {
+        do_sort = t % sort_every == 0;
+      }
+      if (do_sort) {
+        rc = sort_species(c);
+        if (!rc && !c->sorted_once) rc = sort_species(c);   // second pass orders cells in buckets
+        if (rc) return rc;
+        c->sorted_once = true;
+        c->drift_cells = 0;
+      }
+      c->drift_cells += typical_drift_cells(c, drift, a_drift);
     }
     pa.seg = (const Segment*)(c->ws + c->lay.seg + c->species[0].cur * table);
     pa.kick = kick;
@@ -1040,6 +1078,7 @@ int fdf_get_tuning(const fdf_ctx* c, fdf_tuning* t) {
   t->particles_per_thread = c->ppt;
   t->sort_tiles = c->sort_tiles;
   t->sort_every = c->sort_every;
+  t->sort_cells = c->sort_cells;
   return FDF_OK;
 }
 
@@ -1047,15 +1086,18 @@ int fdf_set_tuning(fdf_ctx* c, const fdf_tuning* t) {
   if (!c || !t) return FDF_ERR_ARG;
   const int p = t->particles_per_thread;
   if (p != 1 && p != 2 && p != 4 && p != 8) return fail(c, FDF_ERR_ARG, "particles_per_thread must be 1, 2, 4 or 8");
-  const int tmax = std::min(c->cfg.grid_n / 2, 256);
+  const int tmax = std::min(c->cfg.grid_n, 256);
   if (t->sort_tiles != 0 && (!is_pow2(t->sort_tiles) || t->sort_tiles > tmax))
-    return fail(c, FDF_ERR_ARG, "sort_tiles must be 0 or a power of two <= min(G/2, 256)");
+    return fail(c, FDF_ERR_ARG, "sort_tiles must be 0 or a power of two <= min(G, 256)");
   if (t->sort_every < 0 || (t->sort_every > 0 && c->cfg.sort_every == 0))
     return fail(c, FDF_ERR_ARG, "sorting needs a context created with sort_every > 0");
+  if (!(t->sort_cells >= 0) || (t->sort_cells > 0 && c->cfg.sort_every == 0))
+    return fail(c, FDF_ERR_ARG, "sort_cells must be >= 0 (and > 0 needs sort_every > 0 at create)");
   if (p != c->ppt) c->seg_dirty = true;   // chunk boundaries depend on the block size
   c->ppt = p;
   c->sort_tiles = t->sort_tiles;
   c->sort_every = t->sort_every;
+  c->sort_cells = t->sort_cells;
   return FDF_OK;
 }
 

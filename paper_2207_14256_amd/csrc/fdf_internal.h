@@ -99,13 +99,16 @@ struct SortArgs {
   Segment seg;             // source copy
   Segment dst;             // destination copy
   int32_t fp64;
-  int32_t tiles;           // tiles per axis (the mesh side divided by the tile side)
-  int32_t shift;           // 32 - log2(tiles): tile coordinate of a fixed-point position
+  int32_t grid_n;          // G
+  int32_t cell_shift;      // 32 - log2(G): cell index of a fixed-point position
+  int32_t fine_bits;       // log2 of the bucket tile side in cells
   double box;
-  int64_t nkeys;           // tiles^3
-  uint32_t* count;         // [nkeys] counts, scanned in place into bucket starts
-  uint32_t* offset;        // bucket cursors used by the scatter
+  int64_t nkeys;           // number of buckets, (G >> fine_bits)^3
+  uint32_t* count;         // [nkeys] bucket counts, scanned in place into bucket starts
   uint32_t* scan_scratch;  // sort_scan_scratch_words(nkeys) words
+  uint32_t* rank;          // [n] per sorted element of each 1024-block: rank inside its bucket
+  uint32_t* bucket;        // [n] per sorted element: bucket
+  uint32_t* src;           // [n] per sorted element: source slot inside the block
 };
 
 struct SampleArgs {

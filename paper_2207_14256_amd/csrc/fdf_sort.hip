@@ -1,12 +1,14 @@
 // Spatial bucket sort of the particle state (gfx950).
 //
-// Key = Morton index of the T^3-cell tile holding the particle, taken from the
-// top bits of the position.  A counting sort: count particles per key, an
-// exclusive scan of the counts, then a scatter of every state array into the
-// other buffer copy.  Both atomic passes aggregate runs of equal keys within a
-// 64-lane wavefront (nearly sorted input has long runs), so one lane per run
-// issues the atomic.  The order inside a tile is arbitrary; the push is per
-// particle, so results do not depend on it.  Particles keep their id.
+// Order = Morton index of the coarse T^3-cell tile holding the particle (the
+// bucket of a counting sort), then the Morton index of its cell inside the
+// tile.  Rank pass: each block of 1024 particles sorts itself by that key in
+// LDS and reserves one contiguous range per bucket it touches (one atomic per
+// block and bucket).  Scan: bucket counts become bucket starts.  Move pass:
+// every state array goes to start + rank in the other buffer copy.  Within a
+// bucket the fragments of different blocks follow each other in arbitrary
+// order, each sorted by cell.  The push is per particle, so results do not
+// depend on the order.  Particles keep their id.
 #include "fdf_device.h"
 #include "fdf_internal.h"
 
@@ -22,76 +24,174 @@ __device__ __forceinline__ uint32_t part1by2(uint32_t v) {   // spread 10 bits t
   return v;
 }
 
-__device__ __forceinline__ uint32_t tile_key(const SortArgs& a, int64_t i) {
-  uint32_t t[3];
+// Full key of particle i: Morton index of its coarse tile (the counting-sort
+// bucket) above the Morton index of its cell inside the tile.
+__device__ __forceinline__ uint32_t full_key(const SortArgs& a, int64_t i) {
+  uint32_t c[3];
   if (a.fp64) {
-    const double s = (double)a.tiles / a.box;
-    for (int d = 0; d < 3; ++d) t[d] = (uint32_t)(int64_t)floor(a.seg.xd[d][i] * s) & (uint32_t)(a.tiles - 1);
+    const double s = (double)a.grid_n / a.box;
+    for (int d = 0; d < 3; ++d) c[d] = (uint32_t)(int64_t)floor(a.seg.xd[d][i] * s) & (uint32_t)(a.grid_n - 1);
   } else {
-    for (int d = 0; d < 3; ++d) t[d] = a.seg.xu[d][i] >> a.shift;
+    for (int d = 0; d < 3; ++d) c[d] = a.seg.xu[d][i] >> a.cell_shift;
   }
-  return (part1by2(t[0]) << 2) | (part1by2(t[1]) << 1) | part1by2(t[2]);
+  const int fb = a.fine_bits;                       // log2 of the tile side in cells
+  const uint32_t fm = (1u << fb) - 1u;
+  const uint32_t coarse = (part1by2(c[0] >> fb) << 2) | (part1by2(c[1] >> fb) << 1) | part1by2(c[2] >> fb);
+  const uint32_t fine = (part1by2(c[0] & fm) << 2) | (part1by2(c[1] & fm) << 1) | part1by2(c[2] & fm);
+  return (coarse << (3 * fb)) | fine;
 }
 
-struct WaveRun {
-  int leader;   // lane that starts this lane's run
-  int len;      // run length (valid on leaders)
-};
-
-// Runs of equal keys among the active lanes of a wavefront.
-__device__ __forceinline__ WaveRun wave_runs(uint32_t key, bool active) {
-  const int lane = threadIdx.x & 63;
-  const uint32_t kprev = (uint32_t)__shfl_up((int)key, 1, 64);
-  const bool start = active && (lane == 0 || kprev != key);
-  const uint64_t smask = __ballot(start);
-  const uint64_t bmask = __ballot(start || !active);
-  const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
-  const uint64_t above = bmask & ~upto;
-  const int end = above ? __ffsll((unsigned long long)above) - 1 : 64;
-  WaveRun r;
-  r.len = end - lane;
-  const uint64_t below = smask & upto;
-  r.leader = below ? 63 - __clzll(below) : lane;
-  return r;
+// Blocks are dispatched round-robin over the 8 XCDs; remap so each XCD (own
+// L2) takes a contiguous range of particles: the bucket fragments written by
+// neighbouring blocks then merge into whole lines in one L2.
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb) {
+  const int64_t full = nb - nb % 8;
+  if (b >= full) return b;
+  return (b % 8) * (full / 8) + b / 8;
 }
 
-__global__ void k_sort_count(SortArgs a) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  const bool active = i < a.seg.n;
-  const uint32_t key = active ? tile_key(a, i) : 0xFFFFFFFFu;
-  const WaveRun r = wave_runs(key, active);
-  if (active && r.leader == (int)(threadIdx.x & 63)) atomicAdd(&a.count[key], (uint32_t)r.len);
-}
+constexpr int kRankThreads = 256;
+constexpr int kRankBlock = 1024;          // particles per block
+constexpr uint64_t kIdxMask = kRankBlock - 1;
 
-template <typename T>
-__device__ __forceinline__ void move(const T* src, T* dst, int64_t i, uint32_t pos) { dst[pos] = src[i]; }
 
-__global__ void k_sort_scatter(SortArgs a) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  const bool active = i < a.seg.n;
-  const uint32_t key = active ? tile_key(a, i) : 0xFFFFFFFFu;
-  const WaveRun r = wave_runs(key, active);
-  const int lane = threadIdx.x & 63;
-  uint32_t base = 0;
-  if (active && r.leader == lane) base = atomicAdd(&a.offset[key], (uint32_t)r.len);
-  base = (uint32_t)__shfl((int)base, r.leader, 64);
-  if (!active) return;
-  const uint32_t pos = base + (uint32_t)(lane - r.leader);
-  const Segment& s = a.seg;
-  const Segment& d = a.dst;
-  for (int k = 0; k < 3; ++k) {
-    if (a.fp64) {
-      move(s.xd[k], d.xd[k], i, pos);
-      move(s.qd[k], d.qd[k], i, pos);
-      move(s.q0d[k], d.q0d[k], i, pos);
-    } else {
-      move(s.xu[k], d.xu[k], i, pos);
-      move(s.qf[k], d.qf[k], i, pos);
-      move(s.cf[k], d.cf[k], i, pos);
-      move(s.q0f[k], d.q0f[k], i, pos);
+
+// Rank pass.  A block sorts its 1024 particles by full key in LDS (bitonic
+// network), cuts the sorted run into segments of equal bucket, and reserves
+// one contiguous range per segment with a single atomicAdd on the bucket
+// count.  Each particle's rank inside its bucket and its bucket are written
+// in source order.  The fragment a block writes into a bucket is therefore
+// contiguous and ordered by cell.
+__global__ void __launch_bounds__(kRankThreads) k_sort_rank(SortArgs a) {
+  __shared__ uint64_t kv[kRankBlock];
+  __shared__ uint32_t seg_start[kRankBlock];
+  __shared__ uint32_t seg_base[kRankBlock];
+  __shared__ uint32_t wave_max[kRankThreads / 64];
+  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t i0 = blk * kRankBlock;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < kRankBlock; e += kRankThreads) {
+    const int64_t i = i0 + e;
+    const uint64_t key = i < a.seg.n ? (uint64_t)full_key(a, i) : 0xFFFFFFFFull;
+    kv[e] = (key << 10) | (uint64_t)e;
+  }
+  __syncthreads();
+  for (int k = 2; k <= kRankBlock; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int t = tid; t < kRankBlock / 2; t += kRankThreads) {
+        const int p = (t / j) * 2 * j + (t % j);
+        const uint64_t x = kv[p], y = kv[p + j];
+        const bool up = (p & k) == 0;
+        if ((x > y) == up) { kv[p] = y; kv[p + j] = x; }
+      }
+      __syncthreads();
     }
   }
-  move(s.id, d.id, i, pos);
+  // segment starts: inclusive max-scan of head positions over the sorted run;
+  // thread tid owns sorted elements 4 tid .. 4 tid + 3
+  const int sh = 10 + 3 * a.fine_bits;   // key bits below the bucket index
+  uint32_t loc[4];
+  uint32_t m = 0;
+  for (int r = 0; r < 4; ++r) {
+    const int e = 4 * tid + r;
+    const bool head = e == 0 || (kv[e] >> sh) != (kv[e - 1] >> sh);
+    m = head ? (uint32_t)e : m;
+    loc[r] = m;
+  }
+  const int lane = tid & 63, wid = tid >> 6;
+  uint32_t inc = m;
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t y = (uint32_t)__shfl_up((int)inc, off, 64);
+    if (lane >= off) inc = max(inc, y);
+  }
+  if (lane == 63) wave_max[wid] = inc;
+  __syncthreads();
+  uint32_t carry = (uint32_t)__shfl_up((int)inc, 1, 64);
+  if (lane == 0) carry = 0;
+  for (int w = 0; w < wid; ++w) carry = max(carry, wave_max[w]);
+  for (int r = 0; r < 4; ++r) {
+    const uint32_t st = max(loc[r], carry);
+    seg_start[4 * tid + r] = st;
+    carry = max(carry, loc[r]);
+  }
+  __syncthreads();
+  // the last element of each segment reserves the segment's range
+  for (int r = 0; r < 4; ++r) {
+    const int e = 4 * tid + r;
+    const uint64_t key = kv[e] >> 10;
+    const bool last = e == kRankBlock - 1 || (kv[e + 1] >> sh) != (kv[e] >> sh);
+    if (last && key != 0xFFFFFFFFull) {
+      const uint32_t st = seg_start[e];
+      seg_base[st] = atomicAdd(&a.count[(uint32_t)(key >> (3 * a.fine_bits))], (uint32_t)(e - st + 1));
+    }
+  }
+  __syncthreads();
+  // outputs in sorted order: source slot, bucket and rank of sorted element e
+  for (int r = 0; r < 4; ++r) {
+    const int e = 4 * tid + r;
+    const uint64_t key = kv[e] >> 10;
+    const int64_t o = i0 + e;
+    if (o >= a.seg.n) continue;   // sentinels sort last: e < n - i0 holds real particles
+    const uint32_t st = seg_start[e];
+    a.src[o] = (uint32_t)(kv[e] & kIdxMask);
+    a.rank[o] = seg_base[st] + (uint32_t)(e - st);
+    a.bucket[o] = (uint32_t)(key >> (3 * a.fine_bits));
+  }
+}
+
+// Move pass, one 1024-block at a time and one state array at a time: the
+// block's window of the array is read once, coalesced, into LDS; element e of
+// the sorted order then takes source slot src[e] from LDS and is written to
+// start[bucket] + rank, so consecutive threads write consecutive addresses
+// inside each bucket fragment.
+template <typename T>
+__device__ __forceinline__ void move_array(const T* __restrict__ src, T* __restrict__ dst, T* lds,
+                                           int64_t i0, int cnt, const int* sidx, const uint32_t* pos) {
+  for (int e = threadIdx.x; e < cnt; e += 256) lds[e] = src[i0 + e];
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kRankBlock / 256; ++r) {
+    const int e = threadIdx.x + r * 256;
+    if (e < cnt) dst[pos[r]] = lds[sidx[r]];
+  }
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(256) k_sort_move(SortArgs a) {
+  __shared__ uint64_t lds_raw[kRankBlock];
+  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t i0 = blk * kRankBlock;
+  const int cnt = (int)min<int64_t>(kRankBlock, a.seg.n - i0);
+  int sidx[kRankBlock / 256];
+  uint32_t pos[kRankBlock / 256];
+#pragma unroll
+  for (int r = 0; r < kRankBlock / 256; ++r) {
+    const int e = threadIdx.x + r * 256;
+    if (e < cnt) {
+      const int64_t o = i0 + e;
+      sidx[r] = (int)a.src[o];
+      pos[r] = a.count[a.bucket[o]] + a.rank[o];
+    }
+  }
+  const Segment& s = a.seg;
+  const Segment& d = a.dst;
+  if (a.fp64) {
+    double* l = (double*)lds_raw;
+    for (int k = 0; k < 3; ++k) {
+      move_array(s.xd[k], d.xd[k], l, i0, cnt, sidx, pos);
+      move_array(s.qd[k], d.qd[k], l, i0, cnt, sidx, pos);
+      move_array(s.q0d[k], d.q0d[k], l, i0, cnt, sidx, pos);
+    }
+  } else {
+    uint32_t* l = (uint32_t*)lds_raw;
+    for (int k = 0; k < 3; ++k) {
+      move_array(s.xu[k], d.xu[k], l, i0, cnt, sidx, pos);
+      move_array((const uint32_t*)s.qf[k], (uint32_t*)d.qf[k], l, i0, cnt, sidx, pos);
+      move_array((const uint32_t*)s.cf[k], (uint32_t*)d.cf[k], l, i0, cnt, sidx, pos);
+      move_array((const uint32_t*)s.q0f[k], (uint32_t*)d.q0f[k], l, i0, cnt, sidx, pos);
+    }
+  }
+  move_array(s.id, d.id, (uint32_t*)lds_raw, i0, cnt, sidx, pos);
 }
 
 // ------------------------------------------------- exclusive scan (uint32) --
@@ -162,13 +262,10 @@ size_t sort_scan_scratch_words(int64_t nkeys) {
 
 void launch_sort(const SortArgs& a, hipStream_t s) {
   const int64_t n = a.seg.n;
-  const unsigned grid = (unsigned)((n + 255) / 256);
   launch_fill_zero(a.count, ((size_t)a.nkeys * 4 + 15) / 16 * 16, s);
-  hipLaunchKernelGGL(k_sort_count, dim3(grid), dim3(256), 0, s, a);
-  scan_exclusive(a.count, a.nkeys, a.scan_scratch, s);
-  SortArgs b = a;
-  b.offset = a.count;   // the scanned counts are the bucket starts
-  hipLaunchKernelGGL(k_sort_scatter, dim3(grid), dim3(256), 0, s, b);
+  hipLaunchKernelGGL(k_sort_rank, dim3((unsigned)((n + kRankBlock - 1) / kRankBlock)), dim3(kRankThreads), 0, s, a);
+  scan_exclusive(a.count, a.nkeys, a.scan_scratch, s);   // bucket counts -> bucket starts
+  hipLaunchKernelGGL(k_sort_move, dim3((unsigned)((n + kRankBlock - 1) / kRankBlock)), dim3(256), 0, s, a);
 }
 
 }  // namespace fdf

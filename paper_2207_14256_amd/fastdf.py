@@ -61,7 +61,7 @@ class Info(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("particles_per_thread", ctypes.c_int32), ("sort_tiles", ctypes.c_int32),
-                ("sort_every", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("sort_every", ctypes.c_int32), ("sort_cells", ctypes.c_float)]
 
 
 class FastDFError(RuntimeError):
@@ -319,12 +319,13 @@ class Context:
         t = Tuning()
         self._check(self.lib.fdf_get_tuning(self.ctx, ctypes.byref(t)), "fdf_get_tuning")
         return dict(particles_per_thread=t.particles_per_thread, sort_tiles=t.sort_tiles,
-                    sort_every=t.sort_every)
+                    sort_every=t.sort_every, sort_cells=t.sort_cells)
 
     def set_tuning(self, **kw):
         cur = self.get_tuning()
         cur.update(kw)
-        t = Tuning(cur["particles_per_thread"], cur["sort_tiles"], cur["sort_every"], 0)
+        t = Tuning(cur["particles_per_thread"], cur["sort_tiles"], cur["sort_every"],
+                   float(cur["sort_cells"]))
         self._check(self.lib.fdf_set_tuning(self.ctx, ctypes.byref(t)), "fdf_set_tuning")
 
     def sync(self):
@@ -353,6 +354,8 @@ def setup_workload(cfg, device="cuda", ctx=None):
         ctx = Context(cfg, device)
     else:
         ctx.reset()
+    if cfg.get("sort_cells", 0.0) > 0 and cfg.get("sort_every", 0) > 0:
+        ctx.set_tuning(sort_cells=float(cfg["sort_cells"]))
     fields = [ctx.add_field(seed, cfg.get("fixed_amp", False)) for seed in cfg["fields"]]
     species = []
     for sp in cfg["species"]:

@@ -10,7 +10,9 @@ specification: c1 32^3 FP64 EdS; c2 256^3 FP64 with gravitational slip;
 c3 512^3 precision form; c4 batched species and seeds; c5 1024^3 scale run.
 Cosmology: h = 0.7, Einstein-de Sitter background (Omega_m = 1), BBKS shape
 Gamma = 0.2, n_s = 0.965, sigma_8 = 0.8.  Field seed = 1000 + preset index,
-species seed = 2000 + 10 * preset index + species index.
+species seed = 2000 + 10 * preset index + species index.  sort_every enables
+the spatial re-sort; sort_cells > 0 replaces the fixed cadence by the adaptive
+one (re-sort after that many cells of typical drift).
 """
 import copy
 
@@ -18,7 +20,7 @@ import numpy as np
 
 BASE = dict(h=0.7, omega_m=1.0, omega_r=0.0, omega_l=0.0, ns=0.965, sigma8=0.8,
             gamma=0.2, model="poisson", slip_amp=0.0, slip_k=1.0,
-            fixed_amp=False, pk_bins=64, sort_every=0, pre_ic=False)
+            fixed_amp=False, pk_bins=64, sort_every=0, sort_cells=0.0, pre_ic=False)
 
 
 def _preset(idx, **kw):
@@ -37,7 +39,8 @@ PRESETS = {
                   species=[dict(field=0, m=0.06, n_side=256, seed=2020)]),
     "c3": _preset(3, grid_n=512, box_mpc=1000.0, z_begin=1e9, z_end=0.0, n_steps=1000,
                   precision="fp32", slip_amp=0.01, slip_k=1.0, fields=[1003],
-                  species=[dict(field=0, m=0.1, n_side=512, seed=2030)], sort_every=20),
+                  species=[dict(field=0, m=0.1, n_side=512, seed=2030)], sort_every=20,
+                  sort_cells=2.0),
     "c4": _preset(4, grid_n=256, box_mpc=768.0, z_begin=1e9, z_end=31.0, n_steps=300,
                   precision="fp32", slip_amp=0.01, slip_k=1.0,
                   fields=[1004 + 100 * s for s in range(17)],
@@ -45,7 +48,7 @@ PRESETS = {
                             dict(field=0, m=0.00995, n_side=256, seed=2041),
                             dict(field=0, m=0.0502, n_side=384, seed=2042)]
                            + [dict(field=s, m=0.05, n_side=128, seed=2043 + s)
-                              for s in range(1, 17)]), sort_every=20),
+                              for s in range(1, 17)]), sort_every=20, sort_cells=2.0),
     "c5": _preset(5, grid_n=512, box_mpc=2000.0, z_begin=1e9, z_end=0.0, n_steps=1000,
                   precision="fp32", slip_amp=0.01, slip_k=1.0, fields=[1005],
                   species=[dict(field=0, m=0.15, n_side=1024, seed=2050)], sort_every=20),
