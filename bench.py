@@ -51,7 +51,7 @@ def bytes_per_launch(cfg, n_particles, drift):
     return n_particles * per + grid
 
 
-def run_leg(cfg, steps, warmup, label):
+def run_leg(cfg, steps, warmup, label, tuning=None):
     import torch
     from paper_2207_14256_amd import fastdf
     n_total = sum(int(sp["n_side"]) ** 3 for sp in cfg["species"])
@@ -60,7 +60,7 @@ def run_leg(cfg, steps, warmup, label):
                        dtype=torch.float64, device="cuda")
 
     def job():
-        _, fields, species = fastdf.setup_workload(cfg, ctx=ctx)
+        _, fields, species = fastdf.setup_workload(cfg, ctx=ctx, tuning=tuning)
         ctx.step(cfg["n_steps"])
         for s in species:
             ctx.weights(s, out=wbuf)
@@ -158,6 +158,7 @@ def main():
     ap.add_argument("--workload", default="c3")
     ap.add_argument("--no-fp64-leg", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--autotune", action="store_true", help="tune the launch and sort policy first")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -181,15 +182,20 @@ def main():
     from paper_2207_14256_amd import fastdf
     fastdf.load()
     torch.cuda.set_device(0)
-    log("workload %s: precision %s" % (args.workload, cfg["precision"]))
-    main_leg = run_leg(cfg, args.steps, args.warmup, args.workload)
+    from paper_2207_14256_amd import autotune
+    if args.autotune:
+        autotune.autotune(cfg, log=log)
+    tuning = autotune.cached_tuning(cfg)
+    log("workload %s: precision %s, tuning %s" % (args.workload, cfg["precision"], tuning))
+    main_leg = run_leg(cfg, args.steps, args.warmup, args.workload, tuning)
     log("%s: %.3e updates/s, push %.3f ms/launch, %.0f GB/s" % (
         args.workload, main_leg["updates_per_s"], main_leg["avg_launch_ms"], main_leg["achieved_gbs"]))
 
     fp64 = None
     if not args.no_fp64_leg and cfg["precision"] == "fp32":
         cfg64 = workloads.preset(args.workload, precision="fp64")
-        leg = run_leg(cfg64, max(1, args.steps - 1), 1, args.workload + "-fp64")
+        leg = run_leg(cfg64, max(1, args.steps - 1), 1, args.workload + "-fp64",
+                      autotune.cached_tuning(cfg64))
         k32, p32, n32 = main_leg["pk"]
         k64, p64, n64 = leg["pk"]
         kn = np.pi * cfg["grid_n"] / cfg["box_mpc"]
@@ -237,6 +243,7 @@ def main():
             "particles": main_leg["n_particles"], "grid_n": cfg["grid_n"],
             "push_steps_per_job": cfg["n_steps"],
             "job": "field + sample + grid FFT + all push steps + weights + deposit/P(k)",
+            "tuning": tuning,
         },
         "roofline": {
             "bound": "hbm",

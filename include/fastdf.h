@@ -136,6 +136,12 @@ typedef struct fdf_tuning {
                                     typical drift since the last sort (mean-momentum
                                     particle of the fastest species, in mesh cells)
                                     reaches this value; 0: use sort_every */
+  int32_t persistent_blocks;     /* push launch: 0 = one block per particle chunk;
+                                    > 0 = a persistent grid of this many blocks
+                                    (a multiple of 8) striding over the chunks */
+  int32_t use_graph;             /* 1: fdf_step captures its launch sequence into
+                                    a hipGraph (once per distinct starting state)
+                                    and replays it; per-kernel timing is then off */
 } fdf_tuning;
 
 /* ---- lifetime -------------------------------------------------------------- */

@@ -1,0 +1,120 @@
+"""Autotuner for the push launch shape and the particle re-sort policy.
+
+Candidates are timed on the device through the C ABI's own HIP-event timers:
+
+  1. launch shape -- particles per thread and one-block-per-chunk versus a
+     persistent grid -- on a short stretch of steps right after the initial
+     sort;
+  2. sort policy -- bucket size and the drift threshold of the adaptive
+     cadence -- over the full schedule, since the cost of a stale order and the
+     number of re-sorts both depend on how far the particles travel.
+
+Results are cached in ``tuning_cache.json`` next to this file, keyed by the
+device architecture, mesh size, particles per cell, precision and number of
+species.  None of the parameters changes results (the push is per particle
+and the sort only permutes), only speed.
+"""
+import json
+import os
+import time
+
+from . import fastdf
+
+CACHE_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_cache.json")
+
+
+def cache_key(cfg):
+    import torch
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0] if torch.cuda.is_available() else "cpu"
+    n = sum(int(sp["n_side"]) ** 3 for sp in cfg["species"])
+    return "%s|G=%d|N/G3=%.4g|%s|species=%d|steps=%d" % (
+        arch, cfg["grid_n"], n / cfg["grid_n"] ** 3, cfg["precision"], len(cfg["species"]), cfg["n_steps"])
+
+
+def load_cache(path=CACHE_PATH):
+    if os.path.exists(path):
+        with open(path) as f:
+            return json.load(f)
+    return {}
+
+
+def cached_tuning(cfg, path=CACHE_PATH):
+    return load_cache(path).get(cache_key(cfg))
+
+
+def _run(ctx, cfg, tuning, steps):
+    import torch
+    fastdf.setup_workload(cfg, ctx=ctx)
+    ctx.set_tuning(**tuning)
+    ctx.timing(True)
+    ctx.timing_reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.step(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    push_ms, launches = ctx.read_timing("push")
+    sort_ms, sorts = ctx.read_timing("sort")
+    return dict(wall_s=wall, push_ms=push_ms / max(launches, 1), sort_ms=sort_ms, sorts=sorts)
+
+
+def autotune(cfg, path=CACHE_PATH, log=print, full_schedule=True):
+    """Time the candidates for this workload, store the best in the cache and
+    return it (a dict accepted by Context.set_tuning)."""
+    ctx = fastdf.Context(cfg)
+    sorting = cfg.get("sort_every", 0) > 0
+    base = dict(particles_per_thread=4, sort_tiles=0, sort_every=cfg.get("sort_every", 0),
+                sort_cells=2.0 if sorting else 0.0, persistent_blocks=0, use_graph=0)
+    # 1. launch shape
+    best, best_ms = None, float("inf")
+    short = min(40, cfg["n_steps"])
+    for ppt in (1, 2, 4, 8):
+        for pers in (0, 2048):
+            t = dict(base, particles_per_thread=ppt, persistent_blocks=pers)
+            r = _run(ctx, cfg, t, short)
+            log("[autotune] ppt=%d persistent=%d: push %.3f ms" % (ppt, pers, r["push_ms"]))
+            if r["push_ms"] < best_ms:
+                best, best_ms = t, r["push_ms"]
+    # 2. sort policy over the whole schedule
+    if sorting and full_schedule:
+        G = cfg["grid_n"]
+        best_wall = float("inf")
+        chosen = best
+        for tiles in sorted({max(1, G // 8), max(1, G // 4), min(256, max(1, G // 2))}):
+            for cells in (1.0, 2.0, 4.0):
+                t = dict(best, sort_tiles=min(tiles, 256), sort_cells=cells)
+                r = _run(ctx, cfg, t, cfg["n_steps"])
+                log("[autotune] tiles=%d cells=%.1f: %.3f s (push %.3f ms, %d sorts, %.0f ms sorting)" % (
+                    tiles, cells, r["wall_s"], r["push_ms"], r["sorts"], r["sort_ms"]))
+                if r["wall_s"] < best_wall:
+                    chosen, best_wall = t, r["wall_s"]
+        best = chosen
+    ctx.close()
+    cache = load_cache(path)
+    cache[cache_key(cfg)] = best
+    with open(path, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+    return best
+
+
+def main(argv=None):
+    import argparse
+    import sys
+
+    import torch
+
+    from . import workloads
+    ap = argparse.ArgumentParser(description="autotune a workload preset and store the result")
+    ap.add_argument("workload")
+    ap.add_argument("--cache", default=CACHE_PATH)
+    ap.add_argument("--launch-only", action="store_true", help="skip the full-schedule sort sweep")
+    args = ap.parse_args(argv)
+    torch.cuda.set_device(0)
+    cfg = workloads.preset(args.workload)
+    best = autotune(cfg, path=args.cache, full_schedule=not args.launch_only,
+                    log=lambda m: print(m, file=sys.stderr, flush=True))
+    print(json.dumps({cache_key(cfg): best}))
+
+
+if __name__ == "__main__":
+    main()

@@ -229,6 +229,32 @@ struct SpeciesRec {
   int cur = 0;
 };
 
+// A captured step sequence: the host state it was captured from and the host
+// state it leaves behind, so a replay can stand in for the enqueue.
+struct HostStepState {
+  int step_index = 0;
+  int cur = 0;
+  bool sorted_once = false;
+  double drift_cells = 0;
+  std::vector<double> grid_a;      // per field; NaN = no grid
+  bool operator==(const HostStepState& o) const {
+    if (step_index != o.step_index || cur != o.cur || sorted_once != o.sorted_once ||
+        std::memcmp(&drift_cells, &o.drift_cells, sizeof(double)) != 0 || grid_a.size() != o.grid_a.size())
+      return false;
+    for (size_t i = 0; i < grid_a.size(); ++i)
+      if (std::memcmp(&grid_a[i], &o.grid_a[i], sizeof(double)) != 0) return false;
+    return true;
+  }
+};
+
+struct GraphRec {
+  int n = 0;
+  std::vector<double> layout;      // fields and species that fix every device pointer
+  HostStepState before, after;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
 struct TimingRec {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
@@ -257,6 +283,11 @@ struct fdf_ctx {
   int sort_tiles = 0;       // tiles per axis of the sort key (0: default)
   int sort_every = 0;       // current re-sort cadence
   float sort_cells = 0;     // adaptive cadence threshold in cells (0: fixed cadence)
+  int persistent = 0;       // push grid size when > 0 (a multiple of 8)
+  bool use_graph = false;   // capture step sequences into hipGraphs
+  hipStream_t cap_stream = nullptr;   // private stream used only for graph capture
+  hipStream_t launch_stream = nullptr;  // stream kernels are enqueued on right now
+  std::vector<GraphRec> graphs;       // captured step sequences
   double drift_cells = 0;   // typical drift since the last sort, in cells
   bool sorted_once = false;
   std::string err;
@@ -280,8 +311,18 @@ int hip_check(fdf_ctx* c, hipError_t e, const char* what) {
 
 int launched(fdf_ctx* c, const char* what) { return hip_check(c, hipGetLastError(), what); }
 
+hipStream_t stream_of(fdf_ctx* c) { return c->launch_stream ? c->launch_stream : c->stream; }
+
+void clear_graphs(fdf_ctx* c) {
+  for (auto& g : c->graphs) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+  }
+  c->graphs.clear();
+}
+
 void timing_begin(fdf_ctx* c, int cls, std::pair<hipEvent_t, hipEvent_t>* ev) {
-  if (!c->timing) return;
+  if (!c->timing || c->launch_stream) return;
   TimingRec& t = c->tim[cls];
   if (t.pool.empty()) {
     hipEvent_t e0, e1;
@@ -295,7 +336,7 @@ void timing_begin(fdf_ctx* c, int cls, std::pair<hipEvent_t, hipEvent_t>* ev) {
 }
 
 void timing_end(fdf_ctx* c, int cls, std::pair<hipEvent_t, hipEvent_t>& ev) {
-  if (!c->timing) return;
+  if (!c->timing || c->launch_stream) return;
   (void)hipEventRecord(ev.second, c->stream);
   c->tim[cls].pending.push_back(ev);
   c->tim[cls].launches++;
@@ -395,7 +436,7 @@ int build_grid(fdf_ctx* c, int field, double a) {
   GridBuildArgs g = grid_recipe(c, f, a, false);
   std::pair<hipEvent_t, hipEvent_t> ev;
   timing_begin(c, FDF_KERNEL_GRID, &ev);
-  launch_build_grids(g, c->stream);
+  launch_build_grids(g, stream_of(c));
   timing_end(c, FDF_KERNEL_GRID, ev);
   f.has_grid = true;
   f.grid_a = a;
@@ -466,7 +507,7 @@ int sort_species(fdf_ctx* c) {
     a.rank = (uint32_t*)(c->ws + c->lay.sort_rank);
     a.bucket = (uint32_t*)(c->ws + c->lay.sort_bucket);
     a.src = (uint32_t*)(c->ws + c->lay.sort_src);
-    launch_sort(a, c->stream);
+    launch_sort(a, stream_of(c));
     s.cur ^= 1;
   }
   timing_end(c, FDF_KERNEL_SORT, ev);
@@ -636,6 +677,8 @@ int fdf_reset(fdf_ctx* c) {
 int fdf_destroy(fdf_ctx* c) {
   if (!c) return FDF_ERR_ARG;
   (void)hipStreamSynchronize(c->stream);
+  clear_graphs(c);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   for (auto& t : c->tim) {
     for (auto& e : t.pending) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
     for (auto& e : t.pool) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
@@ -768,19 +811,19 @@ int fdf_build_potential_grids(fdf_ctx* c, int32_t field_id, double a) {
   if (!needs_ws(c)) return fail(c, FDF_ERR_WORKSPACE, "no workspace attached");
   if (field_id < 0 || field_id >= (int)c->fields.size()) return fail(c, FDF_ERR_ARG, "bad field id");
   if (!(a > 0) || !std::isfinite(a)) return fail(c, FDF_ERR_ARG, "a must be positive");
-  return build_grid(c, field_id, a);
+  return build_grid(c, field_id, a);   // graphs are keyed on grid_a, so replays stay consistent
 }
 
-int fdf_step(fdf_ctx* c, int32_t n) {
-  if (!c) return FDF_ERR_ARG;
-  if (!needs_ws(c)) return fail(c, FDF_ERR_WORKSPACE, "no workspace attached");
-  if (c->species.empty()) return fail(c, FDF_ERR_STATE, "no species");
+}  // extern "C"
+
+namespace {
+
+// Enqueue the launches of n steps (grid rebuilds, re-sorts, pushes) on the
+// current launch stream and advance the host-side state.
+int enqueue_steps(fdf_ctx* c, int32_t n) {
   const int k0 = c->step_index, nabs = std::abs(n);
-  if (n == 0) return FDF_OK;
-  if (k0 + n < 0 || k0 + n > c->cfg.n_steps) return fail(c, FDF_ERR_ARG, "step range outside the schedule");
   const bool tdep = c->cfg.potential_model == FDF_MODEL_RADMAT;
-  int rc = upload_segments(c);
-  if (rc) return rc;
+  int rc = FDF_OK;
   std::vector<int> used(c->fields.size(), 0);
   for (auto& s : c->species) used[s.field] = 1;
   const size_t table = align_up((size_t)c->cfg.max_species * sizeof(Segment));
@@ -794,6 +837,7 @@ int fdf_step(fdf_ctx* c, int32_t n) {
   pa.log2g = ilog2(c->cfg.grid_n);
   pa.box = c->cfg.box_mpc;
   pa.ppt = c->ppt;
+  pa.persistent = c->persistent;
   pa.do_kick = 1;
   for (int j = 0; j <= nabs; ++j) {
     int t;            // integer time of this launch's kick
@@ -839,7 +883,7 @@ int fdf_step(fdf_ctx* c, int32_t n) {
     pa.a_drift = a_drift;
     std::pair<hipEvent_t, hipEvent_t> ev;
     timing_begin(c, FDF_KERNEL_PUSH, &ev);
-    launch_push(pa, c->stream);
+    launch_push(pa, stream_of(c));
     timing_end(c, FDF_KERNEL_PUSH, ev);
     rc = launched(c, "push");
     if (rc) return rc;
@@ -847,6 +891,104 @@ int fdf_step(fdf_ctx* c, int32_t n) {
   c->step_index = k0 + n;
   c->stepped = true;
   return FDF_OK;
+}
+
+// The workspace is carved deterministically, so fields and species added in
+// the same order with the same sizes sit at the same device addresses: a graph
+// captured for one such layout replays correctly after fdf_reset + re-adding.
+std::vector<double> layout_signature(fdf_ctx* c) {
+  std::vector<double> v;
+  v.push_back((double)c->fields.size());
+  for (auto& s : c->species) {
+    v.push_back(s.field);
+    v.push_back(s.m);
+    v.push_back((double)s.n);
+    v.push_back((double)s.flags);
+  }
+  return v;
+}
+
+HostStepState host_state(fdf_ctx* c) {
+  HostStepState h;
+  h.step_index = c->step_index;
+  h.cur = c->species.empty() ? 0 : c->species[0].cur;
+  h.sorted_once = c->sorted_once;
+  h.drift_cells = c->drift_cells;
+  for (auto& f : c->fields) h.grid_a.push_back(f.has_grid ? f.grid_a : NAN);
+  return h;
+}
+
+void apply_state(fdf_ctx* c, const HostStepState& h) {
+  c->step_index = h.step_index;
+  for (auto& s : c->species) s.cur = h.cur;
+  c->sorted_once = h.sorted_once;
+  c->drift_cells = h.drift_cells;
+  for (size_t i = 0; i < c->fields.size() && i < h.grid_a.size(); ++i) {
+    c->fields[i].has_grid = !std::isnan(h.grid_a[i]);
+    c->fields[i].grid_a = h.grid_a[i];
+  }
+  c->stepped = true;
+}
+
+// Graph mode: the launches of step(n) from a given host state are captured
+// once (on a private stream) and replayed on the context stream afterwards.
+int step_graph(fdf_ctx* c, int32_t n) {
+  const HostStepState before = host_state(c);
+  const std::vector<double> layout = layout_signature(c);
+  for (auto& g : c->graphs) {
+    if (g.n == n && g.before == before && g.layout == layout) {
+      int rc = hip_check(c, hipGraphLaunch(g.exec, c->stream), "graph launch");
+      if (!rc) apply_state(c, g.after);
+      return rc;
+    }
+  }
+  if (!c->cap_stream) {
+    int rc = hip_check(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking), "capture stream");
+    if (rc) return rc;
+  }
+  if (c->graphs.size() >= 16) clear_graphs(c);   // bounded cache
+  GraphRec g;
+  g.n = n;
+  g.before = before;
+  g.layout = layout;
+  int rc = hip_check(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
+  if (rc) return rc;
+  c->launch_stream = c->cap_stream;
+  const int rc_enq = enqueue_steps(c, n);
+  c->launch_stream = nullptr;
+  rc = hip_check(c, hipStreamEndCapture(c->cap_stream, &g.graph), "end capture");
+  if (rc_enq || rc) {
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+    apply_state(c, before);
+    return rc_enq ? rc_enq : rc;
+  }
+  rc = hip_check(c, hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0), "graph instantiate");
+  if (rc) {
+    (void)hipGraphDestroy(g.graph);
+    apply_state(c, before);
+    return rc;
+  }
+  g.after = host_state(c);
+  rc = hip_check(c, hipGraphLaunch(g.exec, c->stream), "graph launch");
+  c->graphs.push_back(g);
+  return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fdf_step(fdf_ctx* c, int32_t n) {
+  if (!c) return FDF_ERR_ARG;
+  if (!needs_ws(c)) return fail(c, FDF_ERR_WORKSPACE, "no workspace attached");
+  if (c->species.empty()) return fail(c, FDF_ERR_STATE, "no species");
+  if (n == 0) return FDF_OK;
+  const int k0 = c->step_index;
+  if (k0 + n < 0 || k0 + n > c->cfg.n_steps) return fail(c, FDF_ERR_ARG, "step range outside the schedule");
+  int rc = upload_segments(c);
+  if (rc) return rc;
+  if (c->use_graph) return step_graph(c, n);
+  return enqueue_steps(c, n);
 }
 
 int fdf_weights(fdf_ctx* c, int32_t sid, double* d_w) {
@@ -1079,6 +1221,8 @@ int fdf_get_tuning(const fdf_ctx* c, fdf_tuning* t) {
   t->sort_tiles = c->sort_tiles;
   t->sort_every = c->sort_every;
   t->sort_cells = c->sort_cells;
+  t->persistent_blocks = c->persistent;
+  t->use_graph = c->use_graph ? 1 : 0;
   return FDF_OK;
 }
 
@@ -1093,7 +1237,13 @@ int fdf_set_tuning(fdf_ctx* c, const fdf_tuning* t) {
     return fail(c, FDF_ERR_ARG, "sorting needs a context created with sort_every > 0");
   if (!(t->sort_cells >= 0) || (t->sort_cells > 0 && c->cfg.sort_every == 0))
     return fail(c, FDF_ERR_ARG, "sort_cells must be >= 0 (and > 0 needs sort_every > 0 at create)");
+  if (t->persistent_blocks < 0 || t->persistent_blocks % 8 != 0 || t->persistent_blocks > (1 << 20))
+    return fail(c, FDF_ERR_ARG, "persistent_blocks must be 0 or a positive multiple of 8");
+  if (t->use_graph != 0 && t->use_graph != 1) return fail(c, FDF_ERR_ARG, "use_graph must be 0 or 1");
   if (p != c->ppt) c->seg_dirty = true;   // chunk boundaries depend on the block size
+  clear_graphs(c);
+  c->persistent = t->persistent_blocks;
+  c->use_graph = t->use_graph != 0;
   c->ppt = p;
   c->sort_tiles = t->sort_tiles;
   c->sort_every = t->sort_every;

@@ -92,7 +92,7 @@ struct PushArgs {
   double a_drift;          // a_{k+1/2}
   double box;              // L
   int32_t ppt;             // particles per thread
-  int32_t block;           // threads per block
+  int32_t persistent;      // 0: one block per chunk; > 0: this many blocks (a multiple of 8) loop
 };
 
 struct SortArgs {

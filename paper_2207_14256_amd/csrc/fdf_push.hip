@@ -83,9 +83,8 @@ __device__ __forceinline__ void gather_bf16(const void* grid, const size_t* cell
 // instruction-identical: a particle gets bit-identical results in whichever
 // slot of whichever block it lands after a re-sort.
 template <int NSLOT, int PPT>
-__global__ void __launch_bounds__(kBlock) k_push_f32(PushArgs a) {
+__device__ __forceinline__ void push_chunk_f32(const PushArgs& a, int64_t chunk) {
 #pragma clang fp contract(off)
-  const int64_t chunk = xcd_chunk(blockIdx.x, gridDim.x);
   const int s = find_segment(a.seg, a.nseg, chunk);
   const Segment& sg = a.seg[s];
   const int64_t n = sg.n;
@@ -192,9 +191,8 @@ __device__ __forceinline__ void gather_f64(const void* grid, const size_t* cell,
 }
 
 template <int NSLOT, int PPT>
-__global__ void __launch_bounds__(kBlock) k_push_f64(PushArgs a) {
+__device__ __forceinline__ void push_chunk_f64(const PushArgs& a, int64_t chunk) {
 #pragma clang fp contract(off)
-  const int64_t chunk = xcd_chunk(blockIdx.x, gridDim.x);
   const int s = find_segment(a.seg, a.nseg, chunk);
   const Segment& sg = a.seg[s];
   const int64_t n = sg.n;
@@ -259,9 +257,29 @@ __global__ void __launch_bounds__(kBlock) k_push_f64(PushArgs a) {
   }
 }
 
+// Chunk loop.  One block per chunk, or (persistent) a fixed grid whose
+// blocks stride over the chunks; either way each XCD (block id mod 8) walks a
+// contiguous eighth of the chunk range.
+template <int NSLOT, int PPT>
+__global__ void __launch_bounds__(kBlock) k_push_f32(PushArgs a) {
+  if (!a.persistent) { push_chunk_f32<NSLOT, PPT>(a, xcd_chunk(blockIdx.x, gridDim.x)); return; }
+  const int64_t per = (a.total_chunks + 7) / 8, x = blockIdx.x % 8, stride = gridDim.x / 8;
+  const int64_t end = min((x + 1) * per, a.total_chunks);
+  for (int64_t c = x * per + blockIdx.x / 8; c < end; c += stride) push_chunk_f32<NSLOT, PPT>(a, c);
+}
+
+template <int NSLOT, int PPT>
+__global__ void __launch_bounds__(kBlock) k_push_f64(PushArgs a) {
+  if (!a.persistent) { push_chunk_f64<NSLOT, PPT>(a, xcd_chunk(blockIdx.x, gridDim.x)); return; }
+  const int64_t per = (a.total_chunks + 7) / 8, x = blockIdx.x % 8, stride = gridDim.x / 8;
+  const int64_t end = min((x + 1) * per, a.total_chunks);
+  for (int64_t c = x * per + blockIdx.x / 8; c < end; c += stride) push_chunk_f64<NSLOT, PPT>(a, c);
+}
+
 template <int PPT>
 void push_ppt(const PushArgs& a, hipStream_t s) {
-  const dim3 grid((unsigned)a.total_chunks), block(kBlock);
+  const int64_t grid_blocks = a.persistent ? a.persistent : a.total_chunks;
+  const dim3 grid((unsigned)grid_blocks), block(kBlock);
   if (a.fp64) {
     if (a.nslot == 8) hipLaunchKernelGGL((k_push_f64<8, PPT>), grid, block, 0, s, a);
     else hipLaunchKernelGGL((k_push_f64<4, PPT>), grid, block, 0, s, a);

@@ -61,7 +61,8 @@ class Info(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("particles_per_thread", ctypes.c_int32), ("sort_tiles", ctypes.c_int32),
-                ("sort_every", ctypes.c_int32), ("sort_cells", ctypes.c_float)]
+                ("sort_every", ctypes.c_int32), ("sort_cells", ctypes.c_float),
+                ("persistent_blocks", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
 
 
 class FastDFError(RuntimeError):
@@ -319,13 +320,14 @@ class Context:
         t = Tuning()
         self._check(self.lib.fdf_get_tuning(self.ctx, ctypes.byref(t)), "fdf_get_tuning")
         return dict(particles_per_thread=t.particles_per_thread, sort_tiles=t.sort_tiles,
-                    sort_every=t.sort_every, sort_cells=t.sort_cells)
+                    sort_every=t.sort_every, sort_cells=t.sort_cells,
+                    persistent_blocks=t.persistent_blocks, use_graph=t.use_graph)
 
     def set_tuning(self, **kw):
         cur = self.get_tuning()
         cur.update(kw)
         t = Tuning(cur["particles_per_thread"], cur["sort_tiles"], cur["sort_every"],
-                   float(cur["sort_cells"]))
+                   float(cur["sort_cells"]), int(cur["persistent_blocks"]), int(cur["use_graph"]))
         self._check(self.lib.fdf_set_tuning(self.ctx, ctypes.byref(t)), "fdf_set_tuning")
 
     def sync(self):
@@ -346,15 +348,18 @@ class Context:
         self._check(self.lib.fdf_timing_reset(self.ctx), "fdf_timing_reset")
 
 
-def setup_workload(cfg, device="cuda", ctx=None):
-    """Create (or reset) a context and add the workload's fields and species.
+def setup_workload(cfg, device="cuda", ctx=None, tuning=None):
+    """Create (or reset) a context and add the workload's fields and species;
+    tuning (a dict for Context.set_tuning) is applied when given.
 
     Returns (ctx, field_ids, species_ids)."""
     if ctx is None:
         ctx = Context(cfg, device)
     else:
         ctx.reset()
-    if cfg.get("sort_cells", 0.0) > 0 and cfg.get("sort_every", 0) > 0:
+    if tuning:
+        ctx.set_tuning(**tuning)
+    elif cfg.get("sort_cells", 0.0) > 0 and cfg.get("sort_every", 0) > 0:
         ctx.set_tuning(sort_cells=float(cfg["sort_cells"]))
     fields = [ctx.add_field(seed, cfg.get("fixed_amp", False)) for seed in cfg["fields"]]
     species = []
