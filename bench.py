@@ -159,6 +159,8 @@ def main():
     ap.add_argument("--no-fp64-leg", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", action="store_true", help="tune the launch and sort policy first")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="start with a plain 4 GiB device copy (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -182,6 +184,13 @@ def main():
     from paper_2207_14256_amd import fastdf
     fastdf.load()
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        a = torch.ones(1 << 30, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        torch.cuda.empty_cache()
     from paper_2207_14256_amd import autotune
     if args.autotune:
         autotune.autotune(cfg, log=log)

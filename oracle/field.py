@@ -9,8 +9,10 @@ spectrum P(k) has <|delta_k|^2> = P(k) / V, V = L^3.
 Half-complex storage: arrays of shape (G, G, G/2+1) hold the modes with
 n_z >= 0; index (ix, iy, iz) is n = (ix or ix-G, iy or iy-G, iz).
 """
+import os
+
 import numpy as np
-from scipy import integrate
+from scipy import fft as sfft, integrate
 
 from . import philox
 from .background import hubble, hubble0
@@ -129,7 +131,8 @@ def gaussian_field(G, L, seed, amp, ns, gamma, h, fixed_amplitude=False):
     _, _, _, kmag = wavevectors(G, L)
     pk = power_spectrum(np.where(kmag > 0, kmag, 1.0), amp, ns, gamma, h)
     delta = np.empty((G, G, H), dtype=np.complex128)
-    for ix in range(G):  # one slab at a time keeps memory modest
+
+    def slab(ix):  # one slab at a time keeps memory modest; slabs are independent
         m = (ix * G + np.arange(G)[:, None]) * H + np.arange(H)[None, :]
         w = philox.draw(seed, philox.STREAM_FIELD, m)
         u1 = philox.to_unit_open(w[..., 0])
@@ -137,6 +140,14 @@ def gaussian_field(G, L, seed, amp, ns, gamma, h, fixed_amplitude=False):
         r = np.ones_like(u1) if fixed_amplitude else np.sqrt(-np.log(u1))
         phase = 2.0 * np.pi * u2
         delta[ix] = np.sqrt(pk[ix] / V) * r * (np.cos(phase) + 1j * np.sin(phase))
+
+    if G >= 64:   # numpy releases the GIL in these array operations
+        import concurrent.futures
+        with concurrent.futures.ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+            list(ex.map(slab, range(G)))
+    else:
+        for ix in range(G):
+            slab(ix)
     delta[nyquist_or_zero_mask(G)] = 0.0
     # Hermitian symmetry on the iz = 0 plane
     plane = delta[:, :, 0]
@@ -218,7 +229,7 @@ def potential_grids(delta0, L, a, model, with_psi=False):
       gpsi (3, G, G, G): d psi / d x_a,   gphi (3, G, G, G): d phi / d x_a,
       phidot (G, G, G), and psi (G, G, G) when with_psi.
     Gradients are spectral: d/dx_a -> i k_a.  The inverse transform is the
-    unnormalised sum of the module docstring, i.e. G^3 * numpy.fft.irfftn.
+    unnormalised sum of the module docstring, i.e. G^3 * scipy.fft.irfftn.
     """
     G = delta0.shape[0]
     kx, ky, kz, kmag = wavevectors(G, L)
@@ -230,7 +241,7 @@ def potential_grids(delta0, L, a, model, with_psi=False):
     t_phidot = np.where(zero, 0.0, t_phidot)
 
     def inv(fk):
-        return np.fft.irfftn(fk, s=(G, G, G), axes=(0, 1, 2)) * float(G) ** 3
+        return sfft.irfftn(fk, s=(G, G, G), axes=(0, 1, 2), workers=os.cpu_count()) * float(G) ** 3
 
     psi_k = t_psi * delta0
     phi_k = t_phi * delta0

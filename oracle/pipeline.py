@@ -6,7 +6,10 @@ of the method: schedule -> field -> potential grids -> sample -> push ->
 weights -> density -> P(k).  Any subset of particle ids can be integrated,
 because particles are independent given the grids (sec. 2.1, last paragraph).
 """
+import os
+
 import numpy as np
+from scipy import fft as sfft
 
 from . import background, field, particles, push, stats
 
@@ -91,7 +94,7 @@ def super_horizon_grids(cfg, d0, a, tau):
     inv_lap_theta = np.where(kmag > 0, -theta_k / safe ** 2, 0.0)
 
     def inv(fk):
-        return np.fft.irfftn(fk, s=(G, G, G), axes=(0, 1, 2)) * float(G) ** 3
+        return sfft.irfftn(fk, s=(G, G, G), axes=(0, 1, 2), workers=os.cpu_count()) * float(G) ** 3
     d_grid = inv(delta_k)
     v_grid = np.stack([inv(1j * kv * inv_lap_theta) for kv in (kx, ky, kz)])
     return d_grid, v_grid

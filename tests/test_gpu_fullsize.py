@@ -1,0 +1,119 @@
+"""Parity at the full benchmark sizes, in the launch configuration bench.py
+times (same presets, cached autotuned tuning), on outputs the oracle can
+compute one by one: a sample of particle ids integrated by the FP64 oracle on
+its own full-size grids.  Properties that hold at any size cover the rest
+(mode counts of the spectrum bins).
+
+Set FDF_REPORT_DIR to also write the per-result error statements as JSON.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import pipeline, stats
+from paper_2207_14256_amd import autotune, fastdf, workloads
+
+pytestmark = pytest.mark.gpu
+
+N_SAMPLE = 2048
+
+
+def _report(name, data):
+    d = os.environ.get("FDF_REPORT_DIR")
+    if d:
+        os.makedirs(d, exist_ok=True)
+        with open(os.path.join(d, name), "w") as f:
+            json.dump(data, f, indent=1)
+    print("[gpu-report] %s %s" % (name, json.dumps(data)), flush=True)
+
+
+def _mode_counts(cfg):
+    G = cfg["grid_n"]
+    z = np.zeros((G, G, G))
+    k, _, n = stats.binned_power(z, z, cfg["box_mpc"], cfg["pk_bins"])
+    return k, n
+
+
+def _error_statement(cfg, x, q, w, ref, ids):
+    L, G = cfg["box_mpc"], cfg["grid_n"]
+    dx = ((x[ids] - ref["x"] + L / 2) % L - L / 2) * (G / L)
+    pos = np.sqrt(np.sum(dx ** 2, axis=1))
+    qn = np.linalg.norm(ref["q"], axis=1)
+    qrel = np.abs(np.linalg.norm(q[ids], axis=1) - qn) / qn
+    wscale = np.abs(ref["w"]).max()
+    return dict(n_sample=len(ids), pos_rms_cells=float(np.sqrt(np.mean(pos ** 2))),
+                pos_max_cells=float(pos.max()), q_rel_rms=float(np.sqrt(np.mean(qrel ** 2))),
+                q_rel_max=float(qrel.max()),
+                w_abs_rms_over_max_w=float(np.sqrt(np.mean((w[ids] - ref["w"]) ** 2)) / wscale))
+
+
+def test_c2_full_fp64_sampled():
+    """256^3 particles on a 256^3 mesh, 500 steps z = 1e9 -> 31, FP64, psi != phi."""
+    print("[gpu-case] c2 full fp64", flush=True)
+    cfg = workloads.preset("c2")
+    ctx, fields, species = fastdf.setup_workload(cfg, tuning=autotune.cached_tuning(cfg))
+    ctx.step(cfg["n_steps"])
+    x, q = ctx.read_state(species[0])
+    w = ctx.weights(species[0]).cpu().numpy()
+    k, p, nm = ctx.power_spectrum(species, cfg["pk_bins"])
+    ctx.close()
+    ids = workloads.sample_ids(256 ** 3, N_SAMPLE)
+    ref = pipeline.run_particles(cfg, 0, ids)
+    es = _error_statement(cfg, x, q, w, ref, ids)
+    _report("error_statement_c2_fp64.json", es)
+    L = cfg["box_mpc"]
+    assert np.max(np.abs(((x[ids] - ref["x"] + L / 2) % L - L / 2))) < 1e-5 * L
+    assert np.max(np.abs(q[ids] - ref["q"])) < 1e-5 * np.max(np.abs(ref["q"]))
+    assert es["w_abs_rms_over_max_w"] < 1e-6
+    kr, nr = _mode_counts(cfg)
+    assert np.array_equal(nm, nr)                 # binning is exact integer logic
+    ok = nr > 0
+    assert np.allclose(k[ok], kr[ok], rtol=1e-12)
+    assert np.all(np.isfinite(p[ok])) and np.all(np.isnan(p[~ok]))
+
+
+def test_c3_full_fp32_error_statement():
+    """Precision form at full size (512^3, 1000 steps z = 1e9 -> 0, bf16 mesh,
+    fixed-point x, Kahan q) against the FP64 oracle on sampled ids, and its
+    P(k) against the FP64 path at the same size on k <= k_N / 2."""
+    print("[gpu-case] c3 full fp32 + fp64", flush=True)
+    cfg = workloads.preset("c3")
+    ctx, fields, species = fastdf.setup_workload(cfg, tuning=autotune.cached_tuning(cfg))
+    ctx.step(cfg["n_steps"])
+    x, q = ctx.read_state(species[0])
+    w = ctx.weights(species[0]).cpu().numpy()
+    k32, p32, n32 = ctx.power_spectrum(species, cfg["pk_bins"])
+    ctx.close()
+    del ctx
+    cfg64 = workloads.preset("c3", precision="fp64")
+    c64, _, s64 = fastdf.setup_workload(cfg64, tuning=autotune.cached_tuning(cfg64))
+    c64.step(cfg64["n_steps"])
+    x64, q64 = c64.read_state(s64[0])
+    w64 = c64.weights(s64[0]).cpu().numpy()
+    k64, p64, n64 = c64.power_spectrum(s64, cfg64["pk_bins"])
+    c64.close()
+    del c64
+    import torch
+    torch.cuda.empty_cache()
+    ids = workloads.sample_ids(512 ** 3, N_SAMPLE)
+    ref = pipeline.run_particles(cfg, 0, ids)
+    es32 = _error_statement(cfg, x, q, w, ref, ids)
+    es64 = _error_statement(cfg64, x64, q64, w64, ref, ids)
+    kn = np.pi * cfg["grid_n"] / cfg["box_mpc"]
+    sel = (n64 > 0) & (k64 <= kn / 2)
+    prel = np.abs(p32[sel] / p64[sel] - 1)
+    es32.update(pk_rel_err_vs_fp64_path_max=float(prel.max()),
+                pk_rel_err_vs_fp64_path_rms=float(np.sqrt(np.mean(prel ** 2))),
+                pk_bins=int(sel.sum()))
+    _report("error_statement_c3_fp32.json", es32)
+    _report("error_statement_c3_fp64.json", es64)
+    L = cfg["box_mpc"]
+    # FP64 path: parity to 1e-5
+    assert np.max(np.abs(((x64[ids] - ref["x"] + L / 2) % L - L / 2))) < 1e-5 * L
+    assert np.max(np.abs(q64[ids] - ref["q"])) < 1e-5 * np.max(np.abs(ref["q"]))
+    # precision form: stated bounds
+    assert es32["pos_rms_cells"] < 1e-2
+    assert es32["q_rel_rms"] < 1e-2
+    assert es32["pk_rel_err_vs_fp64_path_max"] < 1e-2
