@@ -109,6 +109,11 @@ typedef struct fdf_config {
   int32_t max_species;     /* capacity: number of species */
   int32_t pad1;
   int64_t max_particles;   /* capacity: total particles over all species */
+  double superstep_tol;    /* time-dependent potentials only.  0: rebuild the grids at
+                              every kick time.  > 0: super-steps (sec. 2.1) -- grids are
+                              built at anchor times where the transfer functions have
+                              changed by more than this fraction since the previous
+                              anchor, and linearly interpolated in a in between */
 } fdf_config;
 
 typedef struct fdf_info {

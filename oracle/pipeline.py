@@ -39,9 +39,39 @@ def delta0(cfg, field_index=0):
                                 cfg.get("fixed_amp", False))
 
 
+def superstep_anchors(cfg, sched, tol):
+    """Super-steps of sec. 2.1 (last paragraph): potential grids are computed
+    only when the transfer functions have changed by more than tol since the
+    last computed set.  Starting at the first time of the schedule, the next
+    anchor is the first schedule time a_k with max |T(k, a_k)/T(k, a_anchor) - 1|
+    > tol over phi and psi; the last time of the schedule closes the list.
+    Returns schedule indices."""
+    model = model_of(cfg)
+    ks = np.array([1e-3, 1e-2, 0.1, 1.0])
+    a = sched["a"]
+
+    def transfers(ai):
+        t_phi, t_psi, _ = field.potential_transfers(ks, ai, model)
+        return np.concatenate([t_phi, t_psi])
+
+    anchors = [0]
+    ref = transfers(a[0])
+    for k in range(1, len(a)):
+        cur = transfers(a[k])
+        if np.max(np.abs(cur / ref - 1.0)) > tol:
+            anchors.append(k)
+            ref = cur
+    if anchors[-1] != len(a) - 1:
+        anchors.append(len(a) - 1)
+    return anchors
+
+
 def grids_provider(cfg, d0, sched, with_psi=False):
-    """grids_at(k) for the schedule: one build for time-independent potentials,
-    otherwise a rebuild at every a_k (cached)."""
+    """grids_at(k) for the schedule.  Time-independent potentials: one build.
+    Time-dependent potentials: a rebuild at every a_k, or, with
+    cfg['superstep_tol'] > 0, the super-step scheme of sec. 2.1: grids at the
+    anchors and, in between, linear interpolation in a,
+        G(a_k) = (1 - t) G(a_A) + t G(a_B),  t = (a_k - a_A) / (a_B - a_A)."""
     L = cfg["box_mpc"]
     model = model_of(cfg)
     if model["kind"] == "poisson":
@@ -49,11 +79,32 @@ def grids_provider(cfg, d0, sched, with_psi=False):
         return lambda k: g
     cache = {}
 
-    def at(k):
+    def build(k):
         if k not in cache:
-            cache.clear()
+            if len(cache) > 3:
+                cache.clear()
             cache[k] = field.potential_grids(d0, L, sched["a"][k], model, with_psi)
         return cache[k]
+
+    tol = cfg.get("superstep_tol", 0.0)
+    if tol <= 0:
+        return build
+    anchors = superstep_anchors(cfg, sched, tol)
+    a = sched["a"]
+
+    def at(k):
+        i = max(j for j in range(len(anchors) - 1) if anchors[j] <= k) if k < anchors[-1] else len(anchors) - 2
+        kA, kB = anchors[i], anchors[i + 1]
+        t = (a[k] - a[kA]) / (a[kB] - a[kA])
+        gA, gB = build(kA), build(kB)
+        out = {}
+        for key in gA:
+            if key == "gphi" and gA["gphi"] is gA["gpsi"]:
+                continue
+            out[key] = (1.0 - t) * gA[key] + t * gB[key]
+        if "gphi" not in out:
+            out["gphi"] = out["gpsi"]
+        return out
     return at
 
 

@@ -147,6 +147,7 @@ struct Layout {
   size_t twiddle_d, twiddle_f, seg, bins, scratch, dens, fields, parts, sort_count, sort_scan, sort_rank,
       sort_bucket, sort_src, total;
   int64_t sort_keys_max;
+  int grid_sets;
   size_t field_dk_bytes, field_grid_bytes, scratch_bytes, dens_bytes, parts_bytes;
   int nslot;
 };
@@ -175,7 +176,8 @@ Layout plan(const fdf_config& c) {
   L.bins = off; off += align_up(3 * kMaxBins * sizeof(double));
   L.scratch = off; off += L.scratch_bytes;
   L.dens = off; off += L.dens_bytes;
-  L.fields = off; off += (size_t)c.max_fields * (L.field_dk_bytes + L.field_grid_bytes);
+  L.grid_sets = (c.potential_model == FDF_MODEL_RADMAT && c.superstep_tol > 0) ? 2 : 1;
+  L.fields = off; off += (size_t)c.max_fields * (L.field_dk_bytes + L.grid_sets * L.field_grid_bytes);
   L.parts = off; off += L.parts_bytes;
   const int64_t tmax = std::min<int64_t>(c.grid_n, 256);
   const bool sorting = c.sort_every > 0;
@@ -208,6 +210,7 @@ const char* validate(const fdf_config* c) {
   if (c->sort_every < 0) return "sort_every must be >= 0";
   if (c->max_fields < 1 || c->max_species < 1 || c->max_particles < 1) return "capacities must be >= 1";
   if (c->max_particles > ((int64_t)1 << 32)) return "at most 2^32 particles";
+  if (!(c->superstep_tol >= 0) || !std::isfinite(c->superstep_tol)) return "superstep_tol must be >= 0";
   return nullptr;
 }
 
@@ -215,8 +218,10 @@ struct FieldRec {
   uint64_t seed = 0;
   void* dk = nullptr;
   void* grid = nullptr;
+  void* grid2 = nullptr;      // second grid set (super-steps)
   bool has_grid = false;
   double grid_a = 0;
+  int tag[2] = {-1, -1};      // super-steps: anchor (schedule index) held by each set
 };
 
 struct SpeciesRec {
@@ -237,8 +242,9 @@ struct HostStepState {
   bool sorted_once = false;
   double drift_cells = 0;
   std::vector<double> grid_a;      // per field; NaN = no grid
+  std::vector<int> tags;           // per field, two super-step set tags
   bool operator==(const HostStepState& o) const {
-    if (step_index != o.step_index || cur != o.cur || sorted_once != o.sorted_once ||
+    if (step_index != o.step_index || cur != o.cur || sorted_once != o.sorted_once || tags != o.tags ||
         std::memcmp(&drift_cells, &o.drift_cells, sizeof(double)) != 0 || grid_a.size() != o.grid_a.size())
       return false;
     for (size_t i = 0; i < grid_a.size(); ++i)
@@ -269,6 +275,7 @@ struct fdf_ctx {
   Cosmo cos{};
   hipStream_t stream = nullptr;
   std::vector<double> a, a_half, kick1, kick2, drift;
+  std::vector<int> anchors;   // super-step anchors (schedule indices), empty when unused
   double amp = 0, tau_begin = 0;
   char* ws = nullptr;
   size_t ws_bytes = 0;
@@ -431,15 +438,18 @@ GridBuildArgs grid_recipe(fdf_ctx* c, const FieldRec& f, double a, bool pre_ic_g
   return g;
 }
 
-int build_grid(fdf_ctx* c, int field, double a) {
+int build_grid(fdf_ctx* c, int field, double a, int buf = 0) {
   FieldRec& f = c->fields[field];
   GridBuildArgs g = grid_recipe(c, f, a, false);
+  if (buf == 1) g.out = f.grid2;
   std::pair<hipEvent_t, hipEvent_t> ev;
   timing_begin(c, FDF_KERNEL_GRID, &ev);
   launch_build_grids(g, stream_of(c));
   timing_end(c, FDF_KERNEL_GRID, ev);
-  f.has_grid = true;
-  f.grid_a = a;
+  if (buf == 0) {
+    f.has_grid = true;
+    f.grid_a = a;
+  }
   return launched(c, "grid build");
 }
 
@@ -455,6 +465,7 @@ int upload_segments(fdf_ctx* c) {
     for (auto& s : c->species) {
       Segment g = s.seg[copy];
       g.grid = c->fields[s.field].grid;
+      g.grid2 = c->fields[s.field].grid2;
       g.m = s.m;
       g.chunk_begin = chunk;
       chunk += (s.n + per - 1) / per;
@@ -556,7 +567,8 @@ int add_field_slot(fdf_ctx* c, int32_t* id) {
   char* base = c->ws + c->lay.fields + c->field_next;
   f.dk = base;
   f.grid = base + c->lay.field_dk_bytes;
-  c->field_next += c->lay.field_dk_bytes + c->lay.field_grid_bytes;
+  f.grid2 = c->lay.grid_sets > 1 ? base + c->lay.field_dk_bytes + c->lay.field_grid_bytes : nullptr;
+  c->field_next += c->lay.field_dk_bytes + c->lay.grid_sets * c->lay.field_grid_bytes;
   c->fields.push_back(f);
   *id = (int32_t)c->fields.size() - 1;
   return FDF_OK;
@@ -644,6 +656,22 @@ int fdf_create(const fdf_config* cfg, void* stream, fdf_ctx** out) {
   }
   c->amp = power_amplitude(cfg->sigma8, cfg->ns, cfg->gamma, cfg->h);
   c->sort_every = cfg->sort_every;
+  if (cfg->potential_model == FDF_MODEL_RADMAT && cfg->superstep_tol > 0) {
+    // Super-steps (sec. 2.1): a new anchor where phi or psi changed by more
+    // than the tolerance since the last one (the model's transfer functions
+    // are k-independent multiples of g(a), so the ratio test uses g alone).
+    double g0, dg0, g, dg;
+    radmat_factor(c->a[0], cfg->omega_m, cfg->omega_r, &g0, &dg0);
+    c->anchors.push_back(0);
+    for (int k = 1; k <= n; ++k) {
+      radmat_factor(c->a[k], cfg->omega_m, cfg->omega_r, &g, &dg);
+      if (std::fabs(g / g0 - 1.0) > cfg->superstep_tol) {
+        c->anchors.push_back(k);
+        g0 = g;
+      }
+    }
+    if (c->anchors.back() != n) c->anchors.push_back(n);
+  }
   c->tau_begin = conformal_time(c->cos, c->a[0]);
   *out = c;
   return FDF_OK;
@@ -811,6 +839,7 @@ int fdf_build_potential_grids(fdf_ctx* c, int32_t field_id, double a) {
   if (!needs_ws(c)) return fail(c, FDF_ERR_WORKSPACE, "no workspace attached");
   if (field_id < 0 || field_id >= (int)c->fields.size()) return fail(c, FDF_ERR_ARG, "bad field id");
   if (!(a > 0) || !std::isfinite(a)) return fail(c, FDF_ERR_ARG, "a must be positive");
+  c->fields[field_id].tag[0] = -1;   // buffer 0 no longer holds a super-step anchor
   return build_grid(c, field_id, a);   // graphs are keyed on grid_a, so replays stay consistent
 }
 
@@ -852,11 +881,45 @@ int enqueue_steps(fdf_ctx* c, int32_t n) {
       if (j < nabs) { kick -= c->kick2[t - 1]; drift = -c->drift[t - 1]; a_drift = c->a_half[t - 1]; }
     }
     const double a_kick = c->a[t];
-    for (size_t f = 0; f < c->fields.size(); ++f) {
-      if (!used[f]) continue;
-      if (!c->fields[f].has_grid || (tdep && c->fields[f].grid_a != a_kick)) {
-        rc = build_grid(c, (int)f, a_kick);
+    pa.blend = 0;
+    if (!c->anchors.empty()) {
+      // super-steps: grids at the anchors around t, interpolated linearly in a
+      const auto& an = c->anchors;
+      size_t iv = 0;
+      while (iv + 2 < an.size() && an[iv + 1] <= t) ++iv;
+      const int kA = an[iv], kB = an[iv + 1];
+      int sel = -1;
+      for (size_t f = 0; f < c->fields.size(); ++f) {
+        if (!used[f]) continue;
+        FieldRec& fr = c->fields[f];
+        int fsel;
+        if (fr.tag[0] == kA && fr.tag[1] == kB) fsel = 0;
+        else if (fr.tag[1] == kA && fr.tag[0] == kB) fsel = 1;
+        else if (fr.tag[0] == kA) { rc = build_grid(c, (int)f, c->a[kB], 1); fr.tag[1] = kB; fsel = 0; }
+        else if (fr.tag[1] == kA) { rc = build_grid(c, (int)f, c->a[kB], 0); fr.tag[0] = kB; fsel = 1; }
+        else if (fr.tag[0] == kB) { rc = build_grid(c, (int)f, c->a[kA], 1); fr.tag[1] = kA; fsel = 1; }
+        else if (fr.tag[1] == kB) { rc = build_grid(c, (int)f, c->a[kA], 0); fr.tag[0] = kA; fsel = 0; }
+        else {
+          rc = build_grid(c, (int)f, c->a[kA], 0);
+          if (!rc) rc = build_grid(c, (int)f, c->a[kB], 1);
+          fr.tag[0] = kA;
+          fr.tag[1] = kB;
+          fsel = 0;
+        }
         if (rc) return rc;
+        if (sel >= 0 && fsel != sel) return fail(c, FDF_ERR_STATE, "grid sets of fields out of step");
+        sel = fsel;
+      }
+      pa.blend = 1;
+      pa.grid_sel = sel < 0 ? 0 : sel;
+      pa.blend_t = (a_kick - c->a[kA]) / (c->a[kB] - c->a[kA]);
+    } else {
+      for (size_t f = 0; f < c->fields.size(); ++f) {
+        if (!used[f]) continue;
+        if (!c->fields[f].has_grid || (tdep && c->fields[f].grid_a != a_kick)) {
+          rc = build_grid(c, (int)f, a_kick);
+          if (rc) return rc;
+        }
       }
     }
     if (j < nabs) {
@@ -914,7 +977,11 @@ HostStepState host_state(fdf_ctx* c) {
   h.cur = c->species.empty() ? 0 : c->species[0].cur;
   h.sorted_once = c->sorted_once;
   h.drift_cells = c->drift_cells;
-  for (auto& f : c->fields) h.grid_a.push_back(f.has_grid ? f.grid_a : NAN);
+  for (auto& f : c->fields) {
+    h.grid_a.push_back(f.has_grid ? f.grid_a : NAN);
+    h.tags.push_back(f.tag[0]);
+    h.tags.push_back(f.tag[1]);
+  }
   return h;
 }
 
@@ -926,6 +993,8 @@ void apply_state(fdf_ctx* c, const HostStepState& h) {
   for (size_t i = 0; i < c->fields.size() && i < h.grid_a.size(); ++i) {
     c->fields[i].has_grid = !std::isnan(h.grid_a[i]);
     c->fields[i].grid_a = h.grid_a[i];
+    c->fields[i].tag[0] = h.tags[2 * i];
+    c->fields[i].tag[1] = h.tags[2 * i + 1];
   }
   c->stepped = true;
 }

@@ -72,6 +72,7 @@ struct Segment {
   double* q0d[3];
   uint32_t* id;
   const void* grid;        // [G^3][nslot]
+  const void* grid2;       // second grid set (super-steps), or null
   double m;                // mass [eV]
   int64_t n;               // particles
   int64_t chunk_begin;     // first chunk of this segment in the launch
@@ -93,6 +94,9 @@ struct PushArgs {
   double box;              // L
   int32_t ppt;             // particles per thread
   int32_t persistent;      // 0: one block per chunk; > 0: this many blocks (a multiple of 8) loop
+  int32_t blend;           // 1: interpolate two grid sets (super-steps)
+  int32_t grid_sel;        // which set holds the earlier anchor: 0 = grid, 1 = grid2
+  double blend_t;          // interpolation weight of the later anchor
 };
 
 struct SortArgs {

@@ -48,10 +48,8 @@ template <typename T> __device__ __forceinline__ void stnt(T v, T* p) { __builti
 // with phi = psi) from a bfloat16 grid.
 template <int NSLOT>
 __device__ __forceinline__ void gather_bf16(const void* grid, const size_t* cell, const float* w,
-                                            float* g /* 7 */) {
+                                            float* g /* 7, accumulated */) {
 #pragma clang fp contract(off)
-#pragma unroll
-  for (int s = 0; s < 7; ++s) g[s] = 0.0f;
   if constexpr (NSLOT == 8) {
     const uint4* gp = (const uint4*)grid;
     uint4 v[8];
@@ -74,7 +72,6 @@ __device__ __forceinline__ void gather_bf16(const void* grid, const size_t* cell
       g[0] = fmaf(w[c], bf16_lo(v[c].x), g[0]); g[1] = fmaf(w[c], bf16_hi(v[c].x), g[1]);
       g[2] = fmaf(w[c], bf16_lo(v[c].y), g[2]); g[6] = fmaf(w[c], bf16_hi(v[c].y), g[6]);
     }
-    g[3] = g[0]; g[4] = g[1]; g[5] = g[2];
   }
 }
 
@@ -82,7 +79,7 @@ __device__ __forceinline__ void gather_bf16(const void* grid, const size_t* cell
 // (explicit fmaf, no contraction) so that the unrolled copies of the loop are
 // instruction-identical: a particle gets bit-identical results in whichever
 // slot of whichever block it lands after a re-sort.
-template <int NSLOT, int PPT>
+template <int NSLOT, int PPT, bool BLEND>
 __device__ __forceinline__ void push_chunk_f32(const PushArgs& a, int64_t chunk) {
 #pragma clang fp contract(off)
   const int s = find_segment(a.seg, a.nseg, chunk);
@@ -99,6 +96,9 @@ __device__ __forceinline__ void push_chunk_f32(const PushArgs& a, int64_t chunk)
   const float ma2 = ma * ma, mah2 = mah * mah;
   const float dscale = (float)(a.drift * 4294967296.0 / a.box);
   const size_t G = (size_t)a.G;
+  const void* gridA = (BLEND && a.grid_sel) ? sg.grid2 : sg.grid;
+  const void* gridB = (BLEND && a.grid_sel) ? sg.grid : sg.grid2;
+  const float tb = (float)a.blend_t, ta = 1.0f - tb;
 
 #pragma unroll
   for (int p = 0; p < PPT; ++p) {
@@ -131,8 +131,17 @@ __device__ __forceinline__ void push_chunk_f32(const PushArgs& a, int64_t chunk)
       cell[cc] = ((size_t)(cx ? i1[0] : i0[0]) * G + (cy ? i1[1] : i0[1])) * G + (cz ? i1[2] : i0[2]);
       w[cc] = ((cx ? t[0] : u[0]) * (cy ? t[1] : u[1])) * (cz ? t[2] : u[2]);
     }
-    float g[7];
-    gather_bf16<NSLOT>(sg.grid, cell, w, g);
+    float g[7] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    if (BLEND) {   // super-steps: (1 - t) G_A + t G_B folded into the CIC weights
+      float wa[8], wb[8];
+#pragma unroll
+      for (int cc = 0; cc < 8; ++cc) { wa[cc] = ta * w[cc]; wb[cc] = tb * w[cc]; }
+      gather_bf16<NSLOT>(gridA, cell, wa, g);
+      gather_bf16<NSLOT>(gridB, cell, wb, g);
+    } else {
+      gather_bf16<NSLOT>(gridA, cell, w, g);
+    }
+    if (NSLOT == 4) { g[3] = g[0]; g[4] = g[1]; g[5] = g[2]; }
     // separable force of eq. releq_approx
     const float q0sq = fmaf(q0[0], q0[0], fmaf(q0[1], q0[1], q0[2] * q0[2]));
     const float e0 = sqrtf(q0sq + ma2);
@@ -168,10 +177,8 @@ __device__ __forceinline__ void push_chunk_f32(const PushArgs& a, int64_t chunk)
 
 template <int NSLOT>
 __device__ __forceinline__ void gather_f64(const void* grid, const size_t* cell, const double* w,
-                                           double* g /* 7 */) {
+                                           double* g /* 7, accumulated */) {
 #pragma clang fp contract(off)
-#pragma unroll
-  for (int s = 0; s < 7; ++s) g[s] = 0.0;
   const double2* gp = (const double2*)grid;
 #pragma unroll
   for (int c = 0; c < 8; ++c) {
@@ -187,10 +194,9 @@ __device__ __forceinline__ void gather_f64(const void* grid, const size_t* cell,
       g[6] = fma(w[c], v1.y, g[6]);
     }
   }
-  if constexpr (NSLOT == 4) { g[3] = g[0]; g[4] = g[1]; g[5] = g[2]; }
 }
 
-template <int NSLOT, int PPT>
+template <int NSLOT, int PPT, bool BLEND>
 __device__ __forceinline__ void push_chunk_f64(const PushArgs& a, int64_t chunk) {
 #pragma clang fp contract(off)
   const int s = find_segment(a.seg, a.nseg, chunk);
@@ -202,6 +208,9 @@ __device__ __forceinline__ void push_chunk_f64(const PushArgs& a, int64_t chunk)
   const double ma = sg.m * a.a_kick;
   const double mah = sg.m * a.a_drift;
   const size_t G = (size_t)a.G;
+  const void* gridA = (BLEND && a.grid_sel) ? sg.grid2 : sg.grid;
+  const void* gridB = (BLEND && a.grid_sel) ? sg.grid : sg.grid2;
+  const double tb = a.blend_t, ta = 1.0 - tb;
 
 #pragma unroll
   for (int p = 0; p < PPT; ++p) {
@@ -232,8 +241,17 @@ __device__ __forceinline__ void push_chunk_f64(const PushArgs& a, int64_t chunk)
       cell[cc] = ((size_t)(cx ? i1[0] : i0[0]) * G + (cy ? i1[1] : i0[1])) * G + (cz ? i1[2] : i0[2]);
       w[cc] = ((cx ? t[0] : 1.0 - t[0]) * (cy ? t[1] : 1.0 - t[1])) * (cz ? t[2] : 1.0 - t[2]);
     }
-    double g[7];
-    gather_f64<NSLOT>(sg.grid, cell, w, g);
+    double g[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (BLEND) {
+      double wa[8], wb[8];
+#pragma unroll
+      for (int cc = 0; cc < 8; ++cc) { wa[cc] = ta * w[cc]; wb[cc] = tb * w[cc]; }
+      gather_f64<NSLOT>(gridA, cell, wa, g);
+      gather_f64<NSLOT>(gridB, cell, wb, g);
+    } else {
+      gather_f64<NSLOT>(gridA, cell, w, g);
+    }
+    if (NSLOT == 4) { g[3] = g[0]; g[4] = g[1]; g[5] = g[2]; }
     const double q0sq = fma(q0[0], q0[0], fma(q0[1], q0[1], q0[2] * q0[2]));
     const double e0 = sqrt(q0sq + ma * ma);
     const double qg = fma(q0[0], g[3], fma(q0[1], g[4], q0[2] * g[5])) / e0 + g[6];
@@ -260,33 +278,39 @@ __device__ __forceinline__ void push_chunk_f64(const PushArgs& a, int64_t chunk)
 // Chunk loop.  One block per chunk, or (persistent) a fixed grid whose
 // blocks stride over the chunks; either way each XCD (block id mod 8) walks a
 // contiguous eighth of the chunk range.
-template <int NSLOT, int PPT>
+template <int NSLOT, int PPT, bool BLEND>
 __global__ void __launch_bounds__(kBlock) k_push_f32(PushArgs a) {
-  if (!a.persistent) { push_chunk_f32<NSLOT, PPT>(a, xcd_chunk(blockIdx.x, gridDim.x)); return; }
+  if (!a.persistent) { push_chunk_f32<NSLOT, PPT, BLEND>(a, xcd_chunk(blockIdx.x, gridDim.x)); return; }
   const int64_t per = (a.total_chunks + 7) / 8, x = blockIdx.x % 8, stride = gridDim.x / 8;
   const int64_t end = min((x + 1) * per, a.total_chunks);
-  for (int64_t c = x * per + blockIdx.x / 8; c < end; c += stride) push_chunk_f32<NSLOT, PPT>(a, c);
+  for (int64_t c = x * per + blockIdx.x / 8; c < end; c += stride) push_chunk_f32<NSLOT, PPT, BLEND>(a, c);
 }
 
-template <int NSLOT, int PPT>
+template <int NSLOT, int PPT, bool BLEND>
 __global__ void __launch_bounds__(kBlock) k_push_f64(PushArgs a) {
-  if (!a.persistent) { push_chunk_f64<NSLOT, PPT>(a, xcd_chunk(blockIdx.x, gridDim.x)); return; }
+  if (!a.persistent) { push_chunk_f64<NSLOT, PPT, BLEND>(a, xcd_chunk(blockIdx.x, gridDim.x)); return; }
   const int64_t per = (a.total_chunks + 7) / 8, x = blockIdx.x % 8, stride = gridDim.x / 8;
   const int64_t end = min((x + 1) * per, a.total_chunks);
-  for (int64_t c = x * per + blockIdx.x / 8; c < end; c += stride) push_chunk_f64<NSLOT, PPT>(a, c);
+  for (int64_t c = x * per + blockIdx.x / 8; c < end; c += stride) push_chunk_f64<NSLOT, PPT, BLEND>(a, c);
+}
+
+template <int PPT, bool BLEND>
+void push_launch(const PushArgs& a, hipStream_t s) {
+  const int64_t grid_blocks = a.persistent ? a.persistent : a.total_chunks;
+  const dim3 grid((unsigned)grid_blocks), block(kBlock);
+  if (a.fp64) {
+    if (a.nslot == 8) hipLaunchKernelGGL((k_push_f64<8, PPT, BLEND>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_push_f64<4, PPT, BLEND>), grid, block, 0, s, a);
+  } else {
+    if (a.nslot == 8) hipLaunchKernelGGL((k_push_f32<8, PPT, BLEND>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_push_f32<4, PPT, BLEND>), grid, block, 0, s, a);
+  }
 }
 
 template <int PPT>
 void push_ppt(const PushArgs& a, hipStream_t s) {
-  const int64_t grid_blocks = a.persistent ? a.persistent : a.total_chunks;
-  const dim3 grid((unsigned)grid_blocks), block(kBlock);
-  if (a.fp64) {
-    if (a.nslot == 8) hipLaunchKernelGGL((k_push_f64<8, PPT>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((k_push_f64<4, PPT>), grid, block, 0, s, a);
-  } else {
-    if (a.nslot == 8) hipLaunchKernelGGL((k_push_f32<8, PPT>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((k_push_f32<4, PPT>), grid, block, 0, s, a);
-  }
+  if (a.blend) push_launch<PPT, true>(a, s);
+  else push_launch<PPT, false>(a, s);
 }
 
 }  // namespace

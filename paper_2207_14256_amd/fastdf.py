@@ -45,7 +45,7 @@ class Config(ctypes.Structure):
         ("ns", ctypes.c_double), ("sigma8", ctypes.c_double), ("gamma", ctypes.c_double),
         ("sort_every", ctypes.c_int32), ("max_fields", ctypes.c_int32),
         ("max_species", ctypes.c_int32), ("pad1", ctypes.c_int32),
-        ("max_particles", ctypes.c_int64),
+        ("max_particles", ctypes.c_int64), ("superstep_tol", ctypes.c_double),
     ]
 
 
@@ -147,6 +147,7 @@ def make_config(cfg):
     c.max_fields = int(cfg.get("max_fields", len(cfg["fields"])))
     c.max_species = int(cfg.get("max_species", len(cfg["species"])))
     c.max_particles = int(cfg.get("max_particles", n_particles))
+    c.superstep_tol = float(cfg.get("superstep_tol", 0.0))
     return c
 
 

@@ -280,3 +280,33 @@ def test_fp32_form_error_statement_small():
     assert pos_rms < 1e-2
     assert np.sqrt(np.mean(qrel ** 2)) < 1e-3
     ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_superstep_parity(prec):
+    """Super-steps (sec. 2.1): grids at anchors where the transfers changed by
+    more than 1 %, linear interpolation in between, against the oracle's own
+    super-step scheme; and close to rebuilding at every step."""
+    say("super-steps %s" % prec)
+    cfg = workloads.small("c2", grid_n=16, n_side=12, n_steps=60, precision=prec, model="radmat",
+                          omega_m=0.9999, omega_r=1e-4, box_mpc=800.0, z_begin=1e6, z_end=30.0,
+                          superstep_tol=0.01)
+    ctx, species, x, q, w = _run_gpu(cfg)
+    ctx.close()
+    ids = np.arange(12 ** 3)
+    ref = pipeline.run_particles(cfg, 0, ids)
+    L = cfg["box_mpc"]
+    if prec == "fp64":
+        assert np.max(np.abs(periodic_diff(x, ref["x"], L))) < 1e-5 * L
+        assert np.max(np.abs(q - ref["q"])) < 1e-9 * np.max(np.abs(ref["q"]))
+    else:
+        dx = periodic_diff(x, ref["x"], L) * cfg["grid_n"] / L
+        assert np.sqrt(np.mean(np.sum(dx ** 2, 1))) < 1e-2
+        dq = np.linalg.norm(q, axis=1) / np.linalg.norm(ref["q"], axis=1) - 1
+        assert np.sqrt(np.mean(dq ** 2)) < 1e-3
+    # interpolating the potentials changes the kicks by far less than 1 %
+    ctx2, _, x2, q2, _ = _run_gpu(dict(cfg, superstep_tol=0.0))
+    ctx2.close()
+    kick = np.linalg.norm(q2 - ref["q0"], axis=1)
+    diff = np.linalg.norm(q - q2, axis=1)
+    assert np.median(diff / kick) < 1e-2

@@ -446,3 +446,50 @@ def test_pre_initial_transform_reproduces_delta_minus_two_psi():
     slope = np.sum(dens * target) / np.sum(target * target)
     corr = np.corrcoef(dens.ravel(), target.ravel())[0, 1]
     assert slope == pytest.approx(1.0, abs=0.02) and corr > 0.98
+
+
+# ----------------------------------------------------------- super-steps --
+
+def _radmat_cfg(**kw):
+    cfg = _small_cfg(grid_n=8, box_mpc=800.0, model="radmat", omega_m=0.9999, omega_r=1e-4,
+                     z_begin=1e6, z_end=30.0, n_steps=60)
+    cfg.update(kw)
+    return cfg
+
+
+def test_superstep_anchors_follow_the_tolerance():
+    """Sec. 2.1: grids are recomputed when the transfers change by more than
+    1 %.  Between anchors the change stays within the tolerance; at every
+    anchor it exceeds it (closed form of the radiation-matter factor)."""
+    cfg = _radmat_cfg()
+    sched = pipeline.schedule(cfg)
+    tol = 0.01
+    anchors = pipeline.superstep_anchors(cfg, sched, tol)
+    g = field.radmat_growth(sched["a"], cfg["h"], cfg["omega_m"], cfg["omega_r"])[0]
+    assert anchors[0] == 0 and anchors[-1] == len(sched["a"]) - 1
+    for a0, a1 in zip(anchors[:-1], anchors[1:]):
+        assert np.all(np.abs(g[a0:a1] / g[a0] - 1) <= tol)
+        if a1 != anchors[-1]:
+            assert abs(g[a1] / g[a0] - 1) > tol
+    # the total change of the potential (10/9 -> ~1) needs about 10 anchors
+    assert 5 <= len(anchors) <= 20
+
+
+def test_superstep_interpolation_error_and_limits():
+    """Linear interpolation between anchors is exact at the anchors and its
+    error between them is far below the tolerance; tol -> 0 reproduces the
+    rebuild at every step."""
+    cfg = _radmat_cfg(superstep_tol=0.01)
+    sched = pipeline.schedule(cfg)
+    d0 = pipeline.delta0(cfg)
+    interp = pipeline.grids_provider(cfg, d0, sched)
+    exact = pipeline.grids_provider(dict(cfg, superstep_tol=0.0), d0, sched)
+    anchors = pipeline.superstep_anchors(cfg, sched, 0.01)
+    for k in range(0, len(sched["a"]), 7):
+        gi, ge = interp(k), exact(k)
+        rel = np.max(np.abs(gi["gpsi"] - ge["gpsi"])) / np.max(np.abs(ge["gpsi"]))
+        assert rel < (1e-13 if k in anchors else 1e-2)
+    tiny = pipeline.grids_provider(dict(cfg, superstep_tol=1e-15), d0, sched)
+    for k in (3, 17, 40):
+        assert np.allclose(tiny(k)["phidot"], exact(k)["phidot"], rtol=0,
+                           atol=1e-14 * np.abs(exact(k)["phidot"]).max())
