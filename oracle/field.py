@@ -222,12 +222,12 @@ def potential_transfers(kmag, a, model):
     return t_phi, t_phi * slip, t_phidot
 
 
-def potential_grids(delta0, L, a, model, with_psi=False):
+def potential_grids(delta0, L, a, model, with_psi=False, with_phi=False):
     """Real-space gradient grids of psi and phi and the phi-dot grid (sec. 2.1).
 
     Returns dict with float64 arrays on the mesh x_j = j L / G:
       gpsi (3, G, G, G): d psi / d x_a,   gphi (3, G, G, G): d phi / d x_a,
-      phidot (G, G, G), and psi (G, G, G) when with_psi.
+      phidot (G, G, G), and psi / phi (G, G, G) when with_psi / with_phi.
     Gradients are spectral: d/dx_a -> i k_a.  The inverse transform is the
     unnormalised sum of the module docstring, i.e. G^3 * scipy.fft.irfftn.
     """
@@ -254,4 +254,6 @@ def potential_grids(delta0, L, a, model, with_psi=False):
     out["phidot"] = inv(t_phidot * delta0)
     if with_psi:
         out["psi"] = inv(psi_k)
+    if with_phi:
+        out["phi"] = inv(phi_k)
     return out

@@ -66,7 +66,7 @@ def superstep_anchors(cfg, sched, tol):
     return anchors
 
 
-def grids_provider(cfg, d0, sched, with_psi=False):
+def grids_provider(cfg, d0, sched, with_psi=False, with_phi=False):
     """grids_at(k) for the schedule.  Time-independent potentials: one build.
     Time-dependent potentials: a rebuild at every a_k, or, with
     cfg['superstep_tol'] > 0, the super-step scheme of sec. 2.1: grids at the
@@ -75,7 +75,7 @@ def grids_provider(cfg, d0, sched, with_psi=False):
     L = cfg["box_mpc"]
     model = model_of(cfg)
     if model["kind"] == "poisson":
-        g = field.potential_grids(d0, L, sched["a"][0], model, with_psi)
+        g = field.potential_grids(d0, L, sched["a"][0], model, with_psi, with_phi)
         return lambda k: g
     cache = {}
 
@@ -83,7 +83,7 @@ def grids_provider(cfg, d0, sched, with_psi=False):
         if k not in cache:
             if len(cache) > 3:
                 cache.clear()
-            cache[k] = field.potential_grids(d0, L, sched["a"][k], model, with_psi)
+            cache[k] = field.potential_grids(d0, L, sched["a"][k], model, with_psi, with_phi)
         return cache[k]
 
     tol = cfg.get("superstep_tol", 0.0)
@@ -153,18 +153,24 @@ def super_horizon_grids(cfg, d0, a, tau):
 
 def run_particles(cfg, species_index, ids, k_end=None, d0=None, return_all=False):
     """Integrate the selected particle ids of one species; returns dict with
-    x, q (final), q0, p and w (delta-f weights)."""
+    x, q (final), q0, p and w (delta-f weights).  cfg['eom'] selects the
+    equations of motion (push.EOM_*; default the separable form)."""
     sched = schedule(cfg)
     if d0 is None:
         d0 = delta0(cfg, cfg["species"][species_index]["field"])
-    grids_at = grids_provider(cfg, d0, sched)
+    eom = cfg.get("eom", push.EOM_SEPARABLE)
+    potentials = eom in (push.EOM_EXACT, push.EOM_CANONICAL)
+    grids_at = grids_provider(cfg, d0, sched, with_psi=potentials, with_phi=potentials)
     pre = None
     if cfg.get("pre_ic", False):
         tau_i = background.conformal_time(sched["a"][0], *cosmo_args(cfg))
         pre = super_horizon_grids(cfg, d0, sched["a"][0], tau_i)
     x0, q, q0, p = initial_state(cfg, species_index, ids, pre, sched)
     m = cfg["species"][species_index]["m"]
-    x, q = push.kdk(x0, q, q0, m, sched, cfg["box_mpc"], grids_at, 0, k_end)
+    if eom == push.EOM_SEPARABLE:
+        x, q = push.kdk(x0, q, q0, m, sched, cfg["box_mpc"], grids_at, 0, k_end)
+    else:
+        x, q = push.kdk_variant(x0, q, m, sched, cfg["box_mpc"], grids_at, eom, 0, k_end)
     w = stats.deltaf_weights(q, p)
     out = dict(x=x, q=q, q0=q0, p=p, w=w, x0=x0, sched=sched)
     if return_all:

@@ -102,3 +102,74 @@ def reversed_schedule(sched):
                 kick1=-sched["kick2"][::-1], kick2=-sched["kick1"][::-1],
                 drift=-sched["drift"][::-1], tau_k=sched["tau_k"][::-1].copy(),
                 delta_lna=-sched["delta_lna"])
+
+
+# ---------------------------------------------------------------------------
+# Other equations of motion (sec. 3.1, 3.2 and 5), integrated by an explicit
+# kick-drift-kick that evaluates each half-kick with the momentum it starts
+# from and the drift's metric factor at the start of the drift.
+# ---------------------------------------------------------------------------
+EOM_SEPARABLE, EOM_EXACT, EOM_CANONICAL, EOM_SR_NEWTON, EOM_SIMPLE_Q = range(5)
+
+
+def sample_potentials(grids, x, L):
+    """gpsi, gphi (N, 3), phidot, psi, phi (N,) at the particles (absent -> 0)."""
+    gpsi, gphi, phidot = sample_fields(grids, x, L)
+    psi = interpolate(grids["psi"], x, L) if "psi" in grids else np.zeros(len(x))
+    phi = interpolate(grids["phi"], x, L) if "phi" in grids else np.zeros(len(x))
+    return gpsi, gphi, phidot, psi, phi
+
+
+def variant_force(mode, q, m, a, gpsi, gphi, phidot):
+    """Right-hand sides of the momentum equations:
+      EXACT     eq. releq:      -eps grad psi - (q^2/eps) grad phi + q (q.grad phi)/eps + q phidot
+      CANONICAL eq. releq_lag:  -eps grad psi - (P^2/eps) grad phi
+      SR_NEWTON eq. p_eq:       -(2 P^2 + m^2 a^2) / sqrt(P^2 + m^2 a^2) grad psi
+      SIMPLE_Q  eq. q_eq:       -sqrt(q^2 + m^2 a^2) grad psi
+    with eps = sqrt(q^2 + m^2 a^2) of the current momentum (q or P)."""
+    q2 = np.sum(q * q, axis=-1)
+    eps = np.sqrt(q2 + (m * a) ** 2)
+    if mode == EOM_EXACT:
+        qg = np.sum(q * gphi, axis=-1)
+        return (-eps[:, None] * gpsi - (q2 / eps)[:, None] * gphi
+                + q * (qg / eps)[:, None] + q * phidot[:, None])
+    if mode == EOM_CANONICAL:
+        return -eps[:, None] * gpsi - (q2 / eps)[:, None] * gphi
+    if mode == EOM_SR_NEWTON:
+        return -((2.0 * q2 + (m * a) ** 2) / eps)[:, None] * gpsi
+    if mode == EOM_SIMPLE_Q:
+        return -eps[:, None] * gpsi
+    raise ValueError(mode)
+
+
+def variant_velocity(mode, q, m, a, psi, phi):
+    """Right-hand sides of the position equations:
+      EXACT     eq. geodesic:     (q/eps)(1 + phi + psi)
+      CANONICAL eq. geodesic_lag: (P/eps)[1 + psi + (2 - P^2/eps^2) phi]
+      SR_NEWTON, SIMPLE_Q:        q / sqrt(q^2 + m^2 a^2)."""
+    q2 = np.sum(q * q, axis=-1)
+    eps = np.sqrt(q2 + (m * a) ** 2)
+    v = q / eps[:, None]
+    if mode == EOM_EXACT:
+        return v * (1.0 + phi + psi)[:, None]
+    if mode == EOM_CANONICAL:
+        return v * (1.0 + psi + (2.0 - q2 / eps ** 2) * phi)[:, None]
+    return v
+
+
+def kdk_variant(x, q, m, sched, L, grids_at, mode, k_begin=0, k_end=None):
+    """Explicit leapfrog for the non-separable forms: for k = k_begin .. k_end-1
+      q += dtau_k^{k+1/2} F(x_k, q, a_k);
+      x += dtau_k^{k+1} v(q, a_{k+1/2}; phi, psi at x_k)   (mod L);
+      q += dtau_{k+1/2}^{k+1} F(x_{k+1}, q, a_{k+1})."""
+    x = np.array(x, dtype=np.float64)
+    q = np.array(q, dtype=np.float64)
+    n = len(sched["drift"])
+    k_end = n if k_end is None else k_end
+    for k in range(k_begin, k_end):
+        gpsi, gphi, phidot, psi, phi = sample_potentials(grids_at(k), x, L)
+        q = q + sched["kick1"][k] * variant_force(mode, q, m, sched["a"][k], gpsi, gphi, phidot)
+        x = np.mod(x + sched["drift"][k] * variant_velocity(mode, q, m, sched["a_half"][k], psi, phi), L)
+        gpsi, gphi, phidot, _, _ = sample_potentials(grids_at(k + 1), x, L)
+        q = q + sched["kick2"][k] * variant_force(mode, q, m, sched["a"][k + 1], gpsi, gphi, phidot)
+    return x, q

@@ -493,3 +493,61 @@ def test_superstep_interpolation_error_and_limits():
     for k in (3, 17, 40):
         assert np.allclose(tiny(k)["phidot"], exact(k)["phidot"], rtol=0,
                            atol=1e-14 * np.abs(exact(k)["phidot"]).max())
+
+
+# ------------------------------------------------- equations of motion --
+
+def test_eom_newtonian_limit_all_forms():
+    """For m a >> q every form reduces to the Newtonian force -m a grad psi
+    (sec. 3.2 and 5), with corrections O(q^2 / m^2 a^2)."""
+    q = np.array([[3e-4, -4e-4, 1.2e-4]])
+    g = np.array([[1e-6, -2e-6, 5e-7]])
+    q2 = np.sum(q ** 2)
+    for mode in (push.EOM_EXACT, push.EOM_CANONICAL, push.EOM_SR_NEWTON, push.EOM_SIMPLE_Q):
+        for ma in (0.3, 3.0):
+            f = push.variant_force(mode, q, ma, 1.0, g, g, np.zeros(1))
+            assert np.max(np.abs(f + ma * g)) / np.max(np.abs(ma * g)) < 3 * q2 / ma ** 2, mode
+
+
+def test_exact_and_separable_agree_while_q_stays_near_q0():
+    """Sec. 3.3: the separable equations approximate eq. releq/geodesic because
+    q stays close to q0 while particles are fast; with zero potentials in the
+    drift factor (sum phi + psi absent) the two forms agree to O(dq/q)."""
+    cfg = _small_cfg(grid_n=8, box_mpc=400.0, z_begin=1e6, z_end=1e3, n_steps=30)
+    sched = pipeline.schedule(cfg)
+    d0 = pipeline.delta0(cfg)
+    grids = pipeline.grids_provider(cfg, d0, sched)
+    ids = np.arange(200)
+    x0 = particles.positions_f64(5, ids, cfg["box_mpc"])
+    q0 = particles.momenta_f64(5, ids)
+    xs, qs = push.kdk(x0, q0, q0, 0.1, sched, cfg["box_mpc"], grids)
+    xe, qe = push.kdk_variant(x0, q0, 0.1, sched, cfg["box_mpc"], grids, push.EOM_EXACT)
+    dq = np.linalg.norm(qs - q0, axis=1)
+    rel = np.linalg.norm(qe - qs, axis=1) / dq
+    assert np.median(rel) < 1e-3 and np.median(dq / np.linalg.norm(q0, axis=1)) < 1e-2
+
+
+def test_canonical_momentum_is_q_over_one_plus_phi():
+    """Sec. 3.2: the canonical momentum P and the comoving momentum q describe
+    the same geodesic, with q_i / P_i = 1 + phi to first order.  Integrating
+    eq. releq_lag/geodesic_lag in P and eq. releq/geodesic in q through a static
+    weak potential gives q = (1 + phi) P up to second-order terms, while the
+    potential itself changes q at first order."""
+    cfg = _small_cfg(grid_n=8, box_mpc=300.0, z_begin=20.0, z_end=1.0, n_steps=400)
+    sched = pipeline.schedule(cfg)
+    d0 = pipeline.delta0(cfg) * 30.0     # phi ~ 1e-3: first and second order well apart
+    grids = pipeline.grids_provider(cfg, d0, sched, with_psi=True, with_phi=True)
+    L, m = cfg["box_mpc"], 0.05
+    ids = np.arange(100)
+    x0 = particles.positions_f64(11, ids, L)
+    q0 = particles.momenta_f64(11, ids)
+    phi0 = push.interpolate(grids(0)["phi"], x0, L)
+    P0 = q0 / (1.0 + phi0)[:, None]
+    xe, qe = push.kdk_variant(x0, q0, m, sched, L, grids, push.EOM_EXACT)
+    xc, Pc = push.kdk_variant(x0, P0, m, sched, L, grids, push.EOM_CANONICAL)
+    phi_e = push.interpolate(grids(0)["phi"], xe, L)
+    first = np.linalg.norm(qe - q0, axis=1)
+    second = np.linalg.norm(qe - (1.0 + phi_e)[:, None] * Pc, axis=1)
+    assert np.median(second / first) < 2e-2
+    dx = (xe - xc + L / 2) % L - L / 2
+    assert np.max(np.abs(dx)) < 1e-2 * L / cfg["grid_n"]
