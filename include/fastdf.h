@@ -70,6 +70,25 @@ enum { FDF_PREC_FP64 = 0, FDF_PREC_FP32 = 1 };
  * In both, psi = phi (1 - slip_amp exp(-k / slip_k)). */
 enum { FDF_MODEL_POISSON = 0, FDF_MODEL_RADMAT = 1 };
 
+/* Equations of motion of the push (fdf_config.eom).  With eps = sqrt(q^2 + m^2 a^2):
+ *   SEPARABLE: eq. releq_approx / geodesic_approx (sec. 3.3), the force taken at
+ *              the initial momentum q0, velocity q/eps: the fast default.
+ *   EXACT:     eq. releq / geodesic (sec. 3.1) at the current q, with the drift
+ *              factor (1 + phi + psi).
+ *   CANONICAL: eq. releq_lag / geodesic_lag (sec. 3.2) in the canonical momentum
+ *              P, which then takes the place of q everywhere (sampling, weights):
+ *              the substitution of P for q that sec. 4 shows to be biased.
+ *   SR_NEWTON: eq. p_eq (sec. 5), Newtonian gravity with special-relativistic
+ *              velocities in P.
+ *   SIMPLE_Q:  eq. q_eq (sec. 5), F = -eps grad psi.
+ *   NEWTONIAN: F = -m a grad psi with the relativistic velocity (sec. 5).
+ * The non-separable forms integrate an explicit kick-drift-kick whose
+ * half-kicks use the momentum they start from (one mesh gather per step). */
+enum {
+  FDF_EOM_SEPARABLE = 0, FDF_EOM_EXACT = 1, FDF_EOM_CANONICAL = 2,
+  FDF_EOM_SR_NEWTON = 3, FDF_EOM_SIMPLE_Q = 4, FDF_EOM_NEWTONIAN = 5
+};
+
 /* Power-spectrum estimator (sec. 4): CROSS = cross spectrum of the even-id and
  * odd-id halves (no shot-noise plateau); AUTO = auto spectrum of all particles. */
 enum { FDF_PK_CROSS = 0, FDF_PK_AUTO = 1 };
@@ -101,7 +120,7 @@ typedef struct fdf_config {
   int32_t n_steps;         /* number of constant-Delta-log-a steps, >= 1 */
   int32_t precision;       /* FDF_PREC_* */
   int32_t potential_model; /* FDF_MODEL_* */
-  int32_t pad0;
+  int32_t eom;             /* FDF_EOM_* */
   double slip_amp, slip_k; /* psi = phi (1 - slip_amp exp(-k/slip_k)); slip_k in 1/Mpc */
   double ns, sigma8, gamma;/* P(k) = A k^ns T_BBKS(k/(gamma h))^2, sigma(8 Mpc/h) = sigma8 */
   int32_t sort_every;      /* spatial re-sort of particles every this many steps (0: never) */

@@ -153,12 +153,13 @@ def super_horizon_grids(cfg, d0, a, tau):
 
 def run_particles(cfg, species_index, ids, k_end=None, d0=None, return_all=False):
     """Integrate the selected particle ids of one species; returns dict with
-    x, q (final), q0, p and w (delta-f weights).  cfg['eom'] selects the
-    equations of motion (push.EOM_*; default the separable form)."""
+    x, q (final), q0, p and w (delta-f weights).  cfg['eom'] names the
+    equations of motion (a key of push.EOM_BY_NAME; default 'separable')."""
     sched = schedule(cfg)
     if d0 is None:
         d0 = delta0(cfg, cfg["species"][species_index]["field"])
-    eom = cfg.get("eom", push.EOM_SEPARABLE)
+    eom = cfg.get("eom", "separable")
+    eom = push.EOM_BY_NAME[eom] if isinstance(eom, str) else int(eom)
     potentials = eom in (push.EOM_EXACT, push.EOM_CANONICAL)
     grids_at = grids_provider(cfg, d0, sched, with_psi=potentials, with_phi=potentials)
     pre = None

@@ -107,9 +107,13 @@ def reversed_schedule(sched):
 # ---------------------------------------------------------------------------
 # Other equations of motion (sec. 3.1, 3.2 and 5), integrated by an explicit
 # kick-drift-kick that evaluates each half-kick with the momentum it starts
-# from and the drift's metric factor at the start of the drift.
+# from and the drift's metric factor at the start of the drift.  In the
+# canonical form the momentum variable is P, sampled and weighted as if it
+# were q (the substitution of P for q that sec. 4 compares against).
 # ---------------------------------------------------------------------------
-EOM_SEPARABLE, EOM_EXACT, EOM_CANONICAL, EOM_SR_NEWTON, EOM_SIMPLE_Q = range(5)
+EOM_SEPARABLE, EOM_EXACT, EOM_CANONICAL, EOM_SR_NEWTON, EOM_SIMPLE_Q, EOM_NEWTONIAN = range(6)
+EOM_BY_NAME = dict(separable=EOM_SEPARABLE, exact=EOM_EXACT, canonical=EOM_CANONICAL,
+                   sr_newton=EOM_SR_NEWTON, simple_q=EOM_SIMPLE_Q, newtonian=EOM_NEWTONIAN)
 
 
 def sample_potentials(grids, x, L):
@@ -126,6 +130,7 @@ def variant_force(mode, q, m, a, gpsi, gphi, phidot):
       CANONICAL eq. releq_lag:  -eps grad psi - (P^2/eps) grad phi
       SR_NEWTON eq. p_eq:       -(2 P^2 + m^2 a^2) / sqrt(P^2 + m^2 a^2) grad psi
       SIMPLE_Q  eq. q_eq:       -sqrt(q^2 + m^2 a^2) grad psi
+      NEWTONIAN (sec. 5):       -m a grad psi, the q -> 0 limit of eq. q_eq
     with eps = sqrt(q^2 + m^2 a^2) of the current momentum (q or P)."""
     q2 = np.sum(q * q, axis=-1)
     eps = np.sqrt(q2 + (m * a) ** 2)
@@ -139,6 +144,8 @@ def variant_force(mode, q, m, a, gpsi, gphi, phidot):
         return -((2.0 * q2 + (m * a) ** 2) / eps)[:, None] * gpsi
     if mode == EOM_SIMPLE_Q:
         return -eps[:, None] * gpsi
+    if mode == EOM_NEWTONIAN:
+        return -(m * a) * gpsi
     raise ValueError(mode)
 
 
@@ -146,7 +153,7 @@ def variant_velocity(mode, q, m, a, psi, phi):
     """Right-hand sides of the position equations:
       EXACT     eq. geodesic:     (q/eps)(1 + phi + psi)
       CANONICAL eq. geodesic_lag: (P/eps)[1 + psi + (2 - P^2/eps^2) phi]
-      SR_NEWTON, SIMPLE_Q:        q / sqrt(q^2 + m^2 a^2)."""
+      SR_NEWTON, SIMPLE_Q, NEWTONIAN: q / sqrt(q^2 + m^2 a^2)."""
     q2 = np.sum(q * q, axis=-1)
     eps = np.sqrt(q2 + (m * a) ** 2)
     v = q / eps[:, None]

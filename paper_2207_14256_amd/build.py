@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfastdf.so")
 SOURCES = ["fdf_host.cpp", "fdf_init.hip", "fdf_fft.hip", "fdf_push.hip", "fdf_output.hip",
-           "fdf_sort.hip"]
+           "fdf_sort.hip", "fdf_push_eom.hip"]
 ARCH = os.environ.get("FDF_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -153,10 +153,12 @@ __device__ __forceinline__ void slot_multiplier(int kind, int nx, int ny, int nz
   if (k2 == 0.0 || kind == SK_ZERO) return;
   const double tphi = tr.c_phi / k2;
   if (kind == SK_PHIDOT) { re = tr.c_phidot / k2; return; }
+  if (kind == SK_PHI) { re = tphi; return; }
   double t = tphi;
-  if (kind == SK_DX_PSI || kind == SK_DY_PSI || kind == SK_DZ_PSI || kind == SK_PSI)
+  if (kind == SK_DX_PSI || kind == SK_DY_PSI || kind == SK_DZ_PSI || kind == SK_PSI || kind == SK_PHI_PSI)
     t = tphi * (1.0 - tr.slip_amp * exp(-sqrt(k2) / tr.slip_k));
   if (kind == SK_PSI) { re = t; return; }
+  if (kind == SK_PHI_PSI) { re = tphi + t; return; }
   int n = (kind == SK_DX_PSI || kind == SK_DX_PHI) ? nx
         : (kind == SK_DY_PSI || kind == SK_DY_PHI) ? ny : nz;
   im = kf * (double)n * t;   // i k_a T

@@ -152,7 +152,35 @@ struct Layout {
   int nslot;
 };
 
-int slots_for(const fdf_config& c) { return c.slip_amp != 0.0 ? 8 : 4; }
+bool eom_potentials(const fdf_config& c) { return c.eom == FDF_EOM_EXACT || c.eom == FDF_EOM_CANONICAL; }
+int slots_for(const fdf_config& c) {
+  if (c.eom == FDF_EOM_SEPARABLE) return c.slip_amp != 0.0 ? 8 : 4;
+  return eom_potentials(c) ? 8 : 4;
+}
+int fft_planes(const fdf_config& c) { return eom_potentials(c) ? 8 : 7; }
+
+// Stored slot of a grid quantity (0-2 grad psi, 3-5 grad phi, 6 phi-dot,
+// 7 psi, 8 phi, 9 phi + psi): >= 0 the slot, -1 identically zero in this
+// configuration, -2 not stored for this equation of motion.
+int grid_slot(const fdf_config& c, int quantity) {
+  const bool tdep = c.potential_model == FDF_MODEL_RADMAT;
+  const bool same = c.slip_amp == 0.0;   // phi = psi
+  switch (c.eom) {
+    case FDF_EOM_SEPARABLE:
+      if (slots_for(c) == 8) return quantity <= 5 ? quantity : quantity == 6 ? (tdep ? 6 : -1) : -2;
+      if (quantity <= 5) return quantity % 3;
+      return quantity == 6 ? (tdep ? 3 : -1) : -2;
+    case FDF_EOM_EXACT:
+      if (quantity <= 5) return quantity;
+      return quantity == 6 ? (tdep ? 6 : -1) : quantity == 9 ? 7 : -2;
+    case FDF_EOM_CANONICAL:
+      if (quantity <= 5) return quantity;
+      return quantity == 7 ? 6 : quantity == 8 ? 7 : -2;
+    default:
+      if (quantity <= 2) return quantity;
+      return (quantity <= 5 && same) ? quantity - 3 : -2;
+  }
+}
 size_t real_bytes(const fdf_config& c) { return c.precision == FDF_PREC_FP64 ? 8 : 4; }
 size_t slot_bytes(const fdf_config& c) { return c.precision == FDF_PREC_FP64 ? 8 : 2; }
 size_t particle_bytes(const fdf_config& c) { return c.precision == FDF_PREC_FP64 ? 76 : 52; }
@@ -164,7 +192,7 @@ Layout plan(const fdf_config& c) {
   L.nslot = slots_for(c);
   L.field_dk_bytes = align_up(G * G * (G / 2) * cb);
   L.field_grid_bytes = align_up(G * G * G * (size_t)L.nslot * slot_bytes(c));
-  L.scratch_bytes = align_up(7 * G * G * (G / 2) * cb);
+  L.scratch_bytes = align_up((size_t)fft_planes(c) * G * G * (G / 2) * cb);
   L.dens_bytes = align_up(4 * G * G * G * rb);   // two halves, or a 4-slot pre-IC grid
   const int copies = c.sort_every > 0 ? 2 : 1;
   L.parts_bytes = align_up((size_t)c.max_particles * particle_bytes(c) * copies +
@@ -211,6 +239,7 @@ const char* validate(const fdf_config* c) {
   if (c->max_fields < 1 || c->max_species < 1 || c->max_particles < 1) return "capacities must be >= 1";
   if (c->max_particles > ((int64_t)1 << 32)) return "at most 2^32 particles";
   if (!(c->superstep_tol >= 0) || !std::isfinite(c->superstep_tol)) return "superstep_tol must be >= 0";
+  if (c->eom < FDF_EOM_SEPARABLE || c->eom > FDF_EOM_NEWTONIAN) return "unknown equation of motion";
   return nullptr;
 }
 
@@ -425,7 +454,20 @@ GridBuildArgs grid_recipe(fdf_ctx* c, const FieldRec& f, double a, bool pre_ic_g
     g.kind[n] = SK_DX_PSI; g.slot[n++] = 0;
     g.kind[n] = SK_DY_PSI; g.slot[n++] = 1;
     g.kind[n] = SK_DZ_PSI; g.slot[n++] = 2;
-    if (g.nslot == 8) {
+    if (cf.eom != FDF_EOM_SEPARABLE) {
+      if (eom_potentials(cf)) {
+        g.kind[n] = SK_DX_PHI; g.slot[n++] = 3;
+        g.kind[n] = SK_DY_PHI; g.slot[n++] = 4;
+        g.kind[n] = SK_DZ_PHI; g.slot[n++] = 5;
+      }
+      if (cf.eom == FDF_EOM_EXACT) {
+        if (phidot) { g.kind[n] = SK_PHIDOT; g.slot[n++] = 6; }
+        g.kind[n] = SK_PHI_PSI; g.slot[n++] = 7;
+      } else if (cf.eom == FDF_EOM_CANONICAL) {
+        g.kind[n] = SK_PSI; g.slot[n++] = 6;
+        g.kind[n] = SK_PHI; g.slot[n++] = 7;
+      }
+    } else if (g.nslot == 8) {
       g.kind[n] = SK_DX_PHI; g.slot[n++] = 3;
       g.kind[n] = SK_DY_PHI; g.slot[n++] = 4;
       g.kind[n] = SK_DZ_PHI; g.slot[n++] = 5;
@@ -868,18 +910,21 @@ int enqueue_steps(fdf_ctx* c, int32_t n) {
   pa.ppt = c->ppt;
   pa.persistent = c->persistent;
   pa.do_kick = 1;
+  pa.eom = c->cfg.eom;
   for (int j = 0; j <= nabs; ++j) {
     int t;            // integer time of this launch's kick
-    double kick = 0, drift = 0, a_drift = 0;
+    double kclose = 0, kopen = 0, drift = 0, a_drift = 0;   // half-kicks ending / starting at t
     if (n > 0) {
       t = k0 + j;
-      if (j > 0) kick += c->kick2[t - 1];
-      if (j < nabs) { kick += c->kick1[t]; drift = c->drift[t]; a_drift = c->a_half[t]; }
+      if (j > 0) kclose = c->kick2[t - 1];
+      if (j < nabs) { kopen = c->kick1[t]; drift = c->drift[t]; a_drift = c->a_half[t]; }
     } else {
       t = k0 - j;
-      if (j > 0) kick -= c->kick1[t];
-      if (j < nabs) { kick -= c->kick2[t - 1]; drift = -c->drift[t - 1]; a_drift = c->a_half[t - 1]; }
+      if (j > 0) kclose = -c->kick1[t];
+      if (j < nabs) { kopen = -c->kick2[t - 1]; drift = -c->drift[t - 1]; a_drift = c->a_half[t - 1]; }
     }
+    // the separable force does not depend on q: both halves as one kick
+    const double kick = pa.eom == FDF_EOM_SEPARABLE ? kclose + kopen : kclose;
     const double a_kick = c->a[t];
     pa.blend = 0;
     if (!c->anchors.empty()) {
@@ -940,6 +985,7 @@ int enqueue_steps(fdf_ctx* c, int32_t n) {
     }
     pa.seg = (const Segment*)(c->ws + c->lay.seg + c->species[0].cur * table);
     pa.kick = kick;
+    pa.kick_open = pa.eom == FDF_EOM_SEPARABLE ? 0.0 : kopen;
     pa.a_kick = a_kick;
     pa.do_drift = j < nabs;
     pa.drift = drift;
@@ -1184,13 +1230,13 @@ int fdf_read_state(fdf_ctx* c, int32_t sid, double* hx, double* hq) {
 int fdf_read_grid(fdf_ctx* c, int32_t field_id, int32_t slot, double* h) {
   if (!c || !h) return FDF_ERR_ARG;
   if (field_id < 0 || field_id >= (int)c->fields.size()) return fail(c, FDF_ERR_ARG, "bad field id");
-  if (slot < 0 || slot > 6) return fail(c, FDF_ERR_ARG, "slot must be in [0, 6]");
+  if (slot < 0 || slot > 9) return fail(c, FDF_ERR_ARG, "quantity must be in [0, 9]");
   const FieldRec& f = c->fields[field_id];
   if (!f.has_grid) return fail(c, FDF_ERR_STATE, "grid not built");
   const int ns = c->lay.nslot;
-  int s = slot;
-  if (ns == 4) s = slot < 3 ? slot : (slot < 6 ? slot - 3 : 3);
-  if (ns == 4 && slot == 6 && c->cfg.potential_model != FDF_MODEL_RADMAT) {
+  const int s = grid_slot(c->cfg, slot);
+  if (s == -2) return fail(c, FDF_ERR_UNSUPPORTED, "quantity not stored for this equation of motion");
+  if (s == -1) {
     std::fill(h, h + (size_t)c->cfg.grid_n * c->cfg.grid_n * c->cfg.grid_n, 0.0);
     return FDF_OK;
   }

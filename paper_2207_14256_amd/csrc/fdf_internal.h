@@ -16,6 +16,8 @@ enum SlotKind : int32_t {
   SK_DX_PHI = 4, SK_DY_PHI = 5, SK_DZ_PHI = 6,
   SK_PHIDOT = 7,
   SK_PSI = 8,
+  SK_PHI = 9,
+  SK_PHI_PSI = 10,         // phi + psi
 };
 
 // Transfer functions at one scale factor (host evaluates the time factors):
@@ -87,7 +89,9 @@ struct PushArgs {
   int32_t log2g;
   int32_t G;
   int32_t do_kick, do_drift;
-  double kick;             // fused kick coefficient [Mpc]
+  int32_t eom;             // 0: separable form (fdf_config.eom), else a form of fdf_push_eom.hip
+  double kick;             // separable: fused kick coefficient [Mpc]; other forms: closing half-kick
+  double kick_open;        // other forms: opening half-kick of the next step (applied second)
   double a_kick;           // a at the kick
   double drift;            // Delta tau of the drift [Mpc]
   double a_drift;          // a_{k+1/2}
@@ -159,6 +163,7 @@ void launch_sample_species(const SampleArgs& a, hipStream_t s);
 void launch_pre_ic(const PreIcArgs& a, hipStream_t s);
 void launch_build_grids(const GridBuildArgs& a, hipStream_t s);
 void launch_push(const PushArgs& a, hipStream_t s);
+void launch_push_eom(const PushArgs& a, hipStream_t s);
 void launch_weights(const OutputArgs& a, hipStream_t s);
 void launch_deposit(const OutputArgs& a, hipStream_t s);
 void launch_power_spectrum(const PkArgs& a, hipStream_t s);

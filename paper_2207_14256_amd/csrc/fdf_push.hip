@@ -17,32 +17,16 @@
 // are bfloat16 with 8 slots = one 16-byte load per CIC corner.
 // FP64 form: everything binary64; 8 slots = four 16-byte loads per corner.
 //
-// Blocks take contiguous chunks of one species; consecutive block ids are
-// spread over the 8 XCDs, so block ids are remapped to give each XCD (own
-// L2) a contiguous range of chunks, i.e. a compact region of sorted particles.
-#include "fdf_device.h"
-#include "fdf_internal.h"
+// Blocks take contiguous chunks of one species, in an XCD-aware order.
+//
+// The separable form is the one implemented here; the other equations of
+// motion (fdf_push_eom.hip) take over when PushArgs::eom is set.
+#include "fdf_push_common.h"
 
 namespace fdf {
 namespace {
 
-constexpr int kBlock = 256;
-
-__device__ __forceinline__ int64_t xcd_chunk(int64_t b, int64_t nb) {
-  const int64_t full = nb - nb % 8;
-  if (b >= full) return b;
-  const int64_t per = full / 8;
-  return (b % 8) * per + b / 8;
-}
-
-__device__ __forceinline__ int find_segment(const Segment* seg, int nseg, int64_t chunk) {
-  int s = 0;
-  while (s + 1 < nseg && seg[s + 1].chunk_begin <= chunk) ++s;
-  return s;
-}
-
-template <typename T> __device__ __forceinline__ T ldnt(const T* p) { return __builtin_nontemporal_load(p); }
-template <typename T> __device__ __forceinline__ void stnt(T v, T* p) { __builtin_nontemporal_store(v, p); }
+using namespace push_detail;
 
 // Gather of the slots (8-slot: gpsi[3], gphi[3], phidot; 4-slot: gpsi[3], phidot
 // with phi = psi) from a bfloat16 grid.
@@ -318,6 +302,7 @@ void push_ppt(const PushArgs& a, hipStream_t s) {
 int push_chunk_particles(int ppt) { return kBlock * ppt; }
 
 void launch_push(const PushArgs& a, hipStream_t s) {
+  if (a.eom != 0) { launch_push_eom(a, s); return; }
   switch (a.ppt) {
     case 1: push_ppt<1>(a, s); break;
     case 2: push_ppt<2>(a, s); break;

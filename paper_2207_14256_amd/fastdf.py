@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libfastdf.so")
 ABI_VERSION = 1
 PREC_FP64, PREC_FP32 = 0, 1
 MODEL_POISSON, MODEL_RADMAT = 0, 1
+EOMS = dict(separable=0, exact=1, canonical=2, sr_newton=3, simple_q=4, newtonian=5)   # fdf_config.eom
 PK_CROSS, PK_AUTO = 0, 1
 SPECIES_PRE_IC = 1
 KERNEL_PUSH, KERNEL_SORT, KERNEL_GRID, KERNEL_INIT, KERNEL_OUTPUT = range(5)
@@ -40,7 +41,7 @@ class Config(ctypes.Structure):
         ("omega_m", ctypes.c_double), ("omega_r", ctypes.c_double), ("omega_l", ctypes.c_double),
         ("z_begin", ctypes.c_double), ("z_end", ctypes.c_double),
         ("n_steps", ctypes.c_int32), ("precision", ctypes.c_int32),
-        ("potential_model", ctypes.c_int32), ("pad0", ctypes.c_int32),
+        ("potential_model", ctypes.c_int32), ("eom", ctypes.c_int32),
         ("slip_amp", ctypes.c_double), ("slip_k", ctypes.c_double),
         ("ns", ctypes.c_double), ("sigma8", ctypes.c_double), ("gamma", ctypes.c_double),
         ("sort_every", ctypes.c_int32), ("max_fields", ctypes.c_int32),
@@ -148,6 +149,7 @@ def make_config(cfg):
     c.max_species = int(cfg.get("max_species", len(cfg["species"])))
     c.max_particles = int(cfg.get("max_particles", n_particles))
     c.superstep_tol = float(cfg.get("superstep_tol", 0.0))
+    c.eom = EOMS[cfg.get("eom", "separable")]
     return c
 
 

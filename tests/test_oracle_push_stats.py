@@ -503,10 +503,31 @@ def test_eom_newtonian_limit_all_forms():
     q = np.array([[3e-4, -4e-4, 1.2e-4]])
     g = np.array([[1e-6, -2e-6, 5e-7]])
     q2 = np.sum(q ** 2)
-    for mode in (push.EOM_EXACT, push.EOM_CANONICAL, push.EOM_SR_NEWTON, push.EOM_SIMPLE_Q):
+    for mode in (push.EOM_EXACT, push.EOM_CANONICAL, push.EOM_SR_NEWTON, push.EOM_SIMPLE_Q,
+                 push.EOM_NEWTONIAN):
         for ma in (0.3, 3.0):
             f = push.variant_force(mode, q, ma, 1.0, g, g, np.zeros(1))
             assert np.max(np.abs(f + ma * g)) / np.max(np.abs(ma * g)) < 3 * q2 / ma ** 2, mode
+
+
+def test_eom_relativistic_limit_ratios():
+    """For m a -> 0 the Newtonian terms vanish and the psi-force magnitudes
+    scale as |q| (q_eq), 2 |P| (p_eq) and 0 (Newtonian), and with
+    grad phi = grad psi the canonical force is twice the q_eq force."""
+    q = np.array([[3e-4, -4e-4, 1.2e-4]])
+    g = np.array([[1e-6, -2e-6, 5e-7]])
+    qn = np.linalg.norm(q)
+    f = {mode: push.variant_force(mode, q, 0.0, 1.0, g, g, np.zeros(1))
+         for mode in (push.EOM_SIMPLE_Q, push.EOM_SR_NEWTON, push.EOM_CANONICAL, push.EOM_NEWTONIAN)}
+    assert np.allclose(f[push.EOM_SIMPLE_Q], -qn * g, rtol=1e-14)
+    assert np.allclose(f[push.EOM_SR_NEWTON], -2 * qn * g, rtol=1e-14)
+    assert np.allclose(f[push.EOM_CANONICAL], -2 * qn * g, rtol=1e-14)
+    assert np.all(f[push.EOM_NEWTONIAN] == 0)
+    # exact form: the transverse part of grad phi only, plus the time term
+    fe = push.variant_force(push.EOM_EXACT, q, 0.0, 1.0, np.zeros_like(g), g, np.full(1, 2e-6))
+    qh = q / qn
+    g_perp = g - qh * np.sum(qh * g)
+    assert np.allclose(fe, -qn * g_perp + q * 2e-6, rtol=1e-12, atol=1e-24)
 
 
 def test_exact_and_separable_agree_while_q_stays_near_q0():
