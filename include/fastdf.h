@@ -22,7 +22,7 @@
  *     context owns only host tables; all of its device buffers are carved
  *     from the one workspace the caller attaches.
  *   - Calls enqueue work on the context's stream and return.  Calls that
- *     copy to host memory (fdf_read_*, fdf_density_power_spectrum,
+ *     copy to host memory (fdf_read_*, fdf_*_power_spectrum,
  *     fdf_read_timing) and fdf_sync block until the stream has drained;
  *     device faults surface there as FDF_ERR_HIP.
  *   - A context is not thread-safe: use it from one host thread at a time.
@@ -243,6 +243,16 @@ int fdf_weights(struct fdf_ctx* ctx, int32_t species_id, double* d_w);
 int fdf_density_power_spectrum(struct fdf_ctx* ctx, const int32_t* species, int32_t n_species,
                                int32_t n_bins, int32_t mode,
                                double* h_k, double* h_p, double* h_nmodes);
+
+/* Power spectrum of the momentum perturbation (1 + delta) theta (sec. 4): the
+ * delta-f deposit J of w q = w eps v per axis, normalised as the density
+ * contrast, and Theta(k) = sum_a i k_a J_a(k); binned as
+ * fdf_density_power_spectrum (same modes, CROSS or AUTO) in Mpc^3 / Mpc^2.
+ * Uses the density buffers as scratch: fdf_read_density fails afterwards
+ * until the next fdf_density_power_spectrum. */
+int fdf_momentum_power_spectrum(struct fdf_ctx* ctx, const int32_t* species, int32_t n_species,
+                                int32_t n_bins, int32_t mode,
+                                double* h_k, double* h_p, double* h_nmodes);
 
 /* ---- read-back (blocking) -------------------------------------------------- */
 

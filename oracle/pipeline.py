@@ -200,3 +200,23 @@ def density_spectrum(cfg, species_index, res, mode="cross", a=None):
         halves.append(stats.density_contrast(res["x"][s], res["w"][s], eps[s], G, L,
                                              int(s.sum()), mean_eps))
     return stats.binned_power(halves[0], halves[1], L, cfg["pk_bins"]), tuple(halves)
+
+
+def momentum_spectrum(cfg, species_index, res, mode="cross", a=None):
+    """Binned P(k) of the momentum perturbation (1 + delta) theta (sec. 4)
+    from an integrated full sample, halves as in density_spectrum."""
+    G, L = cfg["grid_n"], cfg["box_mpc"]
+    m = cfg["species"][species_index]["m"]
+    a = res["sched"]["a"][-1] if a is None else a
+    mean_eps = background.mean_energy(m, a)
+    n = res["x"].shape[0]
+    ids = np.arange(n)
+    if mode == "auto":
+        t = stats.momentum_divergence(res["x"], res["w"], res["q"], G, L, n, mean_eps)
+        return stats.binned_power_fourier(t, t, L, cfg["pk_bins"])
+    halves = []
+    for par in (0, 1):
+        s = (ids % 2) == par
+        halves.append(stats.momentum_divergence(res["x"][s], res["w"][s], res["q"][s], G, L,
+                                                int(s.sum()), mean_eps))
+    return stats.binned_power_fourier(halves[0], halves[1], L, cfg["pk_bins"])

@@ -77,9 +77,16 @@ def binned_power(delta_a, delta_b, L, nbins):
     empty bin has NaN mean values.
     """
     G = delta_a.shape[0]
-    V = L ** 3
     fa = np.fft.rfftn(delta_a) / float(G) ** 3
     fb = fa if delta_b is delta_a else np.fft.rfftn(delta_b) / float(G) ** 3
+    return binned_power_fourier(fa, fb, L, nbins)
+
+
+def binned_power_fourier(fa, fb, L, nbins):
+    """The binning of binned_power for two half-complex Fourier fields
+    (G, G, G/2 + 1) already normalised as delta_k."""
+    G = fa.shape[0]
+    V = L ** 3
     p = V * np.real(fa * np.conj(fb))
     n = np.arange(G)
     n = np.where(n < G // 2, n, n - G)
@@ -94,3 +101,22 @@ def binned_power(delta_a, delta_b, L, nbins):
     psum = np.bincount(b[sel], weights=(wgt * p)[sel], minlength=nbins)
     with np.errstate(invalid="ignore", divide="ignore"):
         return ksum / cnt, psum / cnt, cnt
+
+
+def momentum_divergence(x, w, q, G, L, n_particles, mean_eps):
+    """Fourier field of the momentum perturbation (1 + delta) theta (sec. 4).
+
+    The delta-f estimate of the energy-weighted velocity field,
+      J(x_j) = G^3 / (N <eps>) sum_k w_k eps_k v_k W_CIC(j, x_k),  v = q / eps,
+    i.e. the density contrast's deposit with w eps replaced by w q, so that
+    (1 + delta) v = J; its divergence in Fourier space is
+      Theta(k) = sum_a i k_a J_a(k)   (J_a(k) normalised as delta_k).
+    Returns the half-complex (G, G, G/2 + 1) array."""
+    from .field import wavevectors
+    kx, ky, kz, _ = wavevectors(G, L)
+    norm = float(G) ** 3 / (n_particles * mean_eps)
+    theta = np.zeros((G, G, G // 2 + 1), dtype=np.complex128)
+    for a, ka in enumerate((kx, ky, kz)):
+        J = cic_deposit(x, w * q[:, a], G, L) * norm
+        theta += 1j * ka * (np.fft.rfftn(J) / float(G) ** 3)
+    return theta

@@ -454,6 +454,76 @@ __global__ void __launch_bounds__(256) k_xpass_bin(PkArgs a) {
     if (hist[e] != 0.0) atomicAdd(&a.bins[e], hist[e]);
 }
 
+// ------------------------- forward X pass + i k_axis, summed over the axes --
+// Momentum spectrum: Theta = sum_a i k_a J_a(k), one axis per call.
+template <typename R, int G>
+__global__ void __launch_bounds__(256) k_xpass_accum(PkArgs a) {
+  using S = Shape<R, G>;
+  constexpr int NB0 = S::NBC / 2 > 0 ? S::NBC / 2 : 1;
+  constexpr int NB = NB0, NT = S::NT, M = S::M;
+  __shared__ cplx<R> buf[G * NB];
+  const int nzb = M / NB;
+  const int halves = a.auto_mode ? 1 : 2;
+  const int h = blockIdx.x / (G * nzb);
+  const int blk = blockIdx.x % (G * nzb);
+  const int iy = blk / nzb, iz0 = (blk % nzb) * NB;
+  const cplx<R>* __restrict__ tw = (const cplx<R>*)a.twiddle;
+  cplx<R>* scr = (cplx<R>*)a.scratch;
+  const size_t plane = (size_t)G * G * M;
+  if (h >= halves) return;
+  for (int e = threadIdx.x; e < G * NB; e += NT) {
+    const int ix = e / NB, b = e % NB;
+    buf[ix * NB + b] = scr[h * plane + ((size_t)ix * G + iy) * M + iz0 + b];
+  }
+  __syncthreads();
+  fft_lines<R, G, NB, NT, false, 1>(buf, tw);
+  const int ny = signed_index(iy, G);
+  cplx<R>* acc = scr + (2 + h) * plane;
+  for (int e = threadIdx.x; e < G * NB; e += NT) {
+    const int ix = e / NB, b = e % NB;
+    const int n = a.deriv_axis == 0 ? signed_index(ix, G) : a.deriv_axis == 1 ? ny : iz0 + b;
+    const R kn = (R)(a.kf * (double)n);
+    const cplx<R> v = buf[ix * NB + b];
+    const cplx<R> t = {-kn * v.y, kn * v.x};          // i k_axis v
+    const size_t gi = ((size_t)ix * G + iy) * M + iz0 + b;
+    if (a.accum_first) acc[gi] = t;
+    else acc[gi] = {acc[gi].x + t.x, acc[gi].y + t.y};
+  }
+}
+
+// Log binning of the accumulated planes 2 (and 3), laid out [kx][ky][kz].
+template <typename R, int G>
+__global__ void __launch_bounds__(256) k_bin_accum(PkArgs a) {
+  constexpr int M = G / 2;
+  __shared__ double hist[3 * 256];
+  const cplx<R>* scr = (const cplx<R>*)a.scratch;
+  const size_t plane = (size_t)G * G * M;
+  const cplx<R>* A = scr + 2 * plane;
+  const cplx<R>* B = a.auto_mode ? A : scr + 3 * plane;
+  for (int e = threadIdx.x; e < 3 * a.nbins; e += blockDim.x) hist[e] = 0.0;
+  __syncthreads();
+  const double norm = a.volume / ((double)G * G * G * (double)G * G * G);
+  const double log2h = (double)(31 - __clz(G / 2));
+  for (size_t gi = blockIdx.x * (size_t)blockDim.x + threadIdx.x; gi < plane;
+       gi += (size_t)gridDim.x * blockDim.x) {
+    const int nz = (int)(gi % M), iy = (int)((gi / M) % G), ix = (int)(gi / ((size_t)M * G));
+    const int nx = signed_index(ix, G), ny = signed_index(iy, G);
+    const long n2 = (long)nx * nx + (long)ny * ny + (long)nz * nz;
+    if (n2 == 0) continue;
+    const int bin = (int)floor((double)a.nbins * log2((double)n2) / (2.0 * log2h));
+    if (bin >= a.nbins) continue;
+    const cplx<R> u = A[gi], v = B[gi];
+    const double p = norm * ((double)u.x * (double)v.x + (double)u.y * (double)v.y);
+    const double w = nz == 0 ? 1.0 : 2.0;
+    atomicAdd(&hist[bin], w);
+    atomicAdd(&hist[a.nbins + bin], w * a.kf * sqrt((double)n2));
+    atomicAdd(&hist[2 * a.nbins + bin], w * p);
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 3 * a.nbins; e += blockDim.x)
+    if (hist[e] != 0.0) atomicAdd(&a.bins[e], hist[e]);
+}
+
 // --------------------------------------------------------------- dispatch --
 template <typename R, int G>
 void build_grids_g(const GridBuildArgs& a, hipStream_t s) {
@@ -488,7 +558,17 @@ void power_spectrum_g(const PkArgs& a, hipStream_t s) {
   hipLaunchKernelGGL((k_ypass<R, G, false>), dim3(halves * G * nzb), dim3(S::NT), 0, s,
                      (cplx<R>*)a.scratch, (const cplx<R>*)a.twiddle);
   constexpr int NBb = S::NBC / 2 > 0 ? S::NBC / 2 : 1;
-  hipLaunchKernelGGL((k_xpass_bin<R, G>), dim3(G * (S::M / NBb)), dim3(S::NT), 0, s, a);
+  if (a.deriv_axis < 0)
+    hipLaunchKernelGGL((k_xpass_bin<R, G>), dim3(G * (S::M / NBb)), dim3(S::NT), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_xpass_accum<R, G>), dim3(halves * G * (S::M / NBb)), dim3(S::NT), 0, s, a);
+}
+
+template <typename R, int G>
+void bin_accum_g(const PkArgs& a, hipStream_t s) {
+  const size_t plane = (size_t)G * G * (G / 2);
+  const size_t blocks = std::min<size_t>((plane + 255) / 256, 2048);
+  hipLaunchKernelGGL((k_bin_accum<R, G>), dim3((unsigned)blocks), dim3(256), 0, s, a);
 }
 
 template <typename R>
@@ -502,6 +582,21 @@ void build_grids_r(const GridBuildArgs& a, hipStream_t s) {
     case 256: build_grids_g<R, 256>(a, s); break;
     case 512: build_grids_g<R, 512>(a, s); break;
     case 1024: build_grids_g<R, 1024>(a, s); break;
+    default: break;
+  }
+}
+
+template <typename R>
+void bin_accum_r(const PkArgs& a, hipStream_t s) {
+  switch (a.G) {
+    case 8: bin_accum_g<R, 8>(a, s); break;
+    case 16: bin_accum_g<R, 16>(a, s); break;
+    case 32: bin_accum_g<R, 32>(a, s); break;
+    case 64: bin_accum_g<R, 64>(a, s); break;
+    case 128: bin_accum_g<R, 128>(a, s); break;
+    case 256: bin_accum_g<R, 256>(a, s); break;
+    case 512: bin_accum_g<R, 512>(a, s); break;
+    case 1024: bin_accum_g<R, 1024>(a, s); break;
     default: break;
   }
 }
@@ -531,6 +626,11 @@ void launch_build_grids(const GridBuildArgs& a, hipStream_t s) {
 void launch_power_spectrum(const PkArgs& a, hipStream_t s) {
   if (a.fp64) power_spectrum_r<double>(a, s);
   else power_spectrum_r<float>(a, s);
+}
+
+void launch_bin_accumulated(const PkArgs& a, hipStream_t s) {
+  if (a.fp64) bin_accum_r<double>(a, s);
+  else bin_accum_r<float>(a, s);
 }
 
 }  // namespace fdf

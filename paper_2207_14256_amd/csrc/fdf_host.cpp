@@ -1118,8 +1118,11 @@ int fdf_weights(fdf_ctx* c, int32_t sid, double* d_w) {
   return launched(c, "weights");
 }
 
-int fdf_density_power_spectrum(fdf_ctx* c, const int32_t* sp, int32_t ns, int32_t nbins, int32_t mode,
-                               double* hk, double* hp, double* hn) {
+// Binned spectrum of the energy-density contrast, or (momentum) of
+// Theta = sum_a i k_a J_a with J the deposit of w q: the three axes are
+// deposited and transformed one after the other and summed in Fourier space.
+static int power_spectrum(fdf_ctx* c, const int32_t* sp, int32_t ns, int32_t nbins, int32_t mode,
+                          bool momentum, double* hk, double* hp, double* hn) {
   if (!c || !sp || ns < 1 || !hk || !hp || !hn) return FDF_ERR_ARG;
   if (!needs_ws(c)) return fail(c, FDF_ERR_WORKSPACE, "no workspace attached");
   if (nbins < 1 || nbins > kMaxBins) return fail(c, FDF_ERR_ARG, "n_bins must be in [1, 256]");
@@ -1136,23 +1139,6 @@ int fdf_density_power_spectrum(fdf_ctx* c, const int32_t* sp, int32_t ns, int32_
   char* dens = c->ws + c->lay.dens;
   std::pair<hipEvent_t, hipEvent_t> ev;
   timing_begin(c, FDF_KERNEL_OUTPUT, &ev);
-  launch_fill_zero(dens, align_up(2 * cells * rb), c->stream);
-  for (int i = 0; i < ns; ++i) {
-    const SpeciesRec& s = c->species[sp[i]];
-    OutputArgs o = output_args(c, s);
-    o.auto_mode = mode == FDF_PK_AUTO;
-    const double g3 = (double)cells;
-    if (o.auto_mode) {
-      o.norm[0] = o.norm[1] = g3 / ((double)s.n * esum);
-    } else {
-      const int64_t ne = (s.n + 1) / 2, no = s.n / 2;
-      o.norm[0] = g3 / ((double)ne * esum);
-      o.norm[1] = no ? g3 / ((double)no * esum) : 0.0;
-    }
-    o.dens[0] = dens;
-    o.dens[1] = dens + cells * rb;
-    launch_deposit(o, c->stream);
-  }
   double* bins = (double*)(c->ws + c->lay.bins);
   launch_fill_zero(bins, align_up(3 * kMaxBins * sizeof(double)), c->stream);
   PkArgs pk{};
@@ -1167,7 +1153,31 @@ int fdf_density_power_spectrum(fdf_ctx* c, const int32_t* sp, int32_t ns, int32_
   pk.twiddle = c->ws + (f64 ? c->lay.twiddle_d : c->lay.twiddle_f);
   pk.bins = bins;
   pk.kf = 2.0 * kPi / c->cfg.box_mpc;
-  launch_power_spectrum(pk, c->stream);
+  pk.deriv_axis = -1;
+  for (int axis = momentum ? 0 : -1; axis < (momentum ? 3 : 0); ++axis) {
+    launch_fill_zero(dens, align_up(2 * cells * rb), c->stream);
+    for (int i = 0; i < ns; ++i) {
+      const SpeciesRec& s = c->species[sp[i]];
+      OutputArgs o = output_args(c, s);
+      o.auto_mode = mode == FDF_PK_AUTO;
+      const double g3 = (double)cells;
+      if (o.auto_mode) {
+        o.norm[0] = o.norm[1] = g3 / ((double)s.n * esum);
+      } else {
+        const int64_t ne = (s.n + 1) / 2, no = s.n / 2;
+        o.norm[0] = g3 / ((double)ne * esum);
+        o.norm[1] = no ? g3 / ((double)no * esum) : 0.0;
+      }
+      o.dens[0] = dens;
+      o.dens[1] = dens + cells * rb;
+      o.quantity = axis;
+      launch_deposit(o, c->stream);
+    }
+    pk.deriv_axis = axis;
+    pk.accum_first = axis == 0;
+    launch_power_spectrum(pk, c->stream);
+  }
+  if (momentum) launch_bin_accumulated(pk, c->stream);
   timing_end(c, FDF_KERNEL_OUTPUT, ev);
   int rc = launched(c, "power spectrum");
   if (rc) return rc;
@@ -1181,9 +1191,19 @@ int fdf_density_power_spectrum(fdf_ctx* c, const int32_t* sp, int32_t ns, int32_
     hk[b] = cnt > 0 ? hb[nbins + b] / cnt : NAN;
     hp[b] = cnt > 0 ? hb[2 * nbins + b] / cnt : NAN;
   }
-  c->have_density = true;
+  c->have_density = !momentum;   // the density buffers now hold the last momentum axis
   c->density_auto = mode == FDF_PK_AUTO;
   return FDF_OK;
+}
+
+int fdf_density_power_spectrum(fdf_ctx* c, const int32_t* sp, int32_t ns, int32_t nbins, int32_t mode,
+                               double* hk, double* hp, double* hn) {
+  return power_spectrum(c, sp, ns, nbins, mode, false, hk, hp, hn);
+}
+
+int fdf_momentum_power_spectrum(fdf_ctx* c, const int32_t* sp, int32_t ns, int32_t nbins, int32_t mode,
+                                double* hk, double* hp, double* hn) {
+  return power_spectrum(c, sp, ns, nbins, mode, true, hk, hp, hn);
 }
 
 int fdf_read_state(fdf_ctx* c, int32_t sid, double* hx, double* hq) {

@@ -59,6 +59,9 @@ struct PkArgs {
   const void* twiddle;
   double* bins;            // [3][nbins]: count, sum |k|, sum P  (zeroed by caller)
   double kf;
+  int32_t deriv_axis;      // -1: bin the transforms; 0-2: multiply by i k_axis and add into
+                           // scratch planes 2 (and 3), which the binning pass then reads
+  int32_t accum_first;     // 1: the first term of the sum (store instead of add)
 };
 
 // Segment of the batched particle state: one species.
@@ -154,6 +157,7 @@ struct OutputArgs {
   double box, a, m;
   double norm[2];          // deposit normalisation per half (even / odd id)
   int32_t auto_mode;
+  int32_t quantity;        // -1: deposit w eps (energy density); 0-2: w q_axis (momentum density)
   double* w_out;           // weights by id (may be null)
   void* dens[2];           // real [G^3] per half (f32 or f64)
 };
@@ -167,6 +171,7 @@ void launch_push_eom(const PushArgs& a, hipStream_t s);
 void launch_weights(const OutputArgs& a, hipStream_t s);
 void launch_deposit(const OutputArgs& a, hipStream_t s);
 void launch_power_spectrum(const PkArgs& a, hipStream_t s);
+void launch_bin_accumulated(const PkArgs& a, hipStream_t s);
 void launch_fill_zero(void* ptr, size_t bytes, hipStream_t s);
 int push_chunk_particles(int ppt);
 void launch_sort(const SortArgs& a, hipStream_t s);

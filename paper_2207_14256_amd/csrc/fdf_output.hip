@@ -52,7 +52,8 @@ __global__ void k_weights(OutputArgs a) {
   }
 }
 
-// CIC deposit of w eps times the per-half normalisation G^3 / (N_half <eps>).
+// CIC deposit of w eps (energy density) or w q_axis = w eps v_axis (momentum
+// density) times the per-half normalisation G^3 / (N_half <eps>).
 template <typename DR>
 __global__ void k_deposit(OutputArgs a) {
   const int G = a.G;
@@ -65,7 +66,7 @@ __global__ void k_deposit(OutputArgs a) {
     const double w = deltaf_weight(q, p, a.t_nu);
     const double eps = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + (a.m * a.a) * (a.m * a.a));
     const int half = a.auto_mode ? 0 : (int)(id & 1u);
-    const double val = w * eps * a.norm[half];
+    const double val = (a.quantity < 0 ? w * eps : w * q[a.quantity]) * a.norm[half];
     int i0[3], i1[3];
     double t[3];
     for (int d = 0; d < 3; ++d) {

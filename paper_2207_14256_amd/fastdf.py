@@ -27,6 +27,7 @@ EXPORTS = [
     "fdf_workspace_size", "fdf_create", "fdf_attach_workspace", "fdf_reset", "fdf_destroy",
     "fdf_add_field", "fdf_set_field", "fdf_init_species", "fdf_set_species_state",
     "fdf_build_potential_grids", "fdf_step", "fdf_weights", "fdf_density_power_spectrum",
+    "fdf_momentum_power_spectrum",
     "fdf_read_state", "fdf_read_grid", "fdf_read_field", "fdf_read_density",
     "fdf_read_schedule", "fdf_get_info", "fdf_sync", "fdf_timing_enable",
     "fdf_read_timing", "fdf_timing_reset", "fdf_status_string", "fdf_last_error",
@@ -99,6 +100,7 @@ def load():
         "fdf_step": [P, I32],
         "fdf_weights": [P, I32, P],
         "fdf_density_power_spectrum": [P, ctypes.POINTER(I32), I32, I32, I32, PD, PD, PD],
+        "fdf_momentum_power_spectrum": [P, ctypes.POINTER(I32), I32, I32, I32, PD, PD, PD],
         "fdf_read_state": [P, I32, PD, PD],
         "fdf_read_grid": [P, I32, I32, PD],
         "fdf_read_field": [P, I32, PD],
@@ -266,15 +268,17 @@ class Context:
                     "fdf_weights")
         return out
 
-    def power_spectrum(self, species, n_bins, mode="cross"):
+    def power_spectrum(self, species, n_bins, mode="cross", quantity="density"):
+        """(mean k, P(k), modes) of the energy density ('density') or of the
+        momentum perturbation (1 + delta) theta ('momentum')."""
         sp = np.asarray(species if hasattr(species, "__len__") else [species], dtype=np.int32)
         k = np.empty(n_bins)
         p = np.empty(n_bins)
         nm = np.empty(n_bins)
-        self._check(self.lib.fdf_density_power_spectrum(
+        name = {"density": "fdf_density_power_spectrum", "momentum": "fdf_momentum_power_spectrum"}[quantity]
+        self._check(getattr(self.lib, name)(
             self.ctx, sp.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), len(sp), int(n_bins),
-            PK_AUTO if mode == "auto" else PK_CROSS, _dptr(k), _dptr(p), _dptr(nm)),
-            "fdf_density_power_spectrum")
+            PK_AUTO if mode == "auto" else PK_CROSS, _dptr(k), _dptr(p), _dptr(nm)), name)
         return k, p, nm
 
     # ------------------------------------------------------------- read-back --

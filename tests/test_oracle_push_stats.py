@@ -572,3 +572,35 @@ def test_canonical_momentum_is_q_over_one_plus_phi():
     assert np.median(second / first) < 2e-2
     dx = (xe - xc + L / 2) % L - L / 2
     assert np.max(np.abs(dx)) < 1e-2 * L / cfg["grid_n"]
+
+
+# --------------------------------------------- momentum power spectrum --
+
+def _lattice(G, L):
+    g = (np.arange(G) * (L / G))
+    X, Y, Z = np.meshgrid(g, g, g, indexing="ij")
+    return np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_momentum_divergence_plane_waves(axis):
+    """One particle on every mesh point (CIC puts it on that point alone),
+    unit weights, momentum A sin(k0 x_axis) e_b: a longitudinal wave (b = axis)
+    has (1 + delta) theta = k0 A cos(k0 x), i.e. Theta(+-k0) = k0 A / 2 and
+    summed power 2 V (k0 A / 2)^2 in the bin of |n| = n0, nothing elsewhere;
+    a transverse wave (b != axis) has zero divergence."""
+    G, L, n0, A = 16, 300.0, 3, 2e-3
+    x = _lattice(G, L)
+    k0 = 2 * np.pi * n0 / L
+    for b in range(3):
+        q = np.zeros_like(x)
+        q[:, b] = A * np.sin(k0 * x[:, axis])
+        theta = stats.momentum_divergence(x, np.ones(len(x)), q, G, L, G ** 3, 1.0)
+        k, p, n = stats.binned_power_fourier(theta, theta, L, 16)
+        total = np.nan_to_num(p) * n
+        if b == axis:
+            b0 = stats.bin_index(n0 ** 2, G, 16)
+            assert np.isclose(total[b0], 2 * L ** 3 * (k0 * A / 2) ** 2, rtol=1e-12)
+            assert np.all(np.abs(np.delete(total, b0)) < 1e-20 * total[b0])
+        else:
+            assert np.all(np.abs(total) < 1e-25)
