@@ -154,7 +154,8 @@ def super_horizon_grids(cfg, d0, a, tau):
 def run_particles(cfg, species_index, ids, k_end=None, d0=None, return_all=False):
     """Integrate the selected particle ids of one species; returns dict with
     x, q (final), q0, p and w (delta-f weights).  cfg['eom'] names the
-    equations of motion (a key of push.EOM_BY_NAME; default 'separable')."""
+    equations of motion (a key of push.EOM_BY_NAME; default 'separable') and
+    cfg['interp_order'] the force interpolation (1 CIC, 2 TSC; default 1)."""
     sched = schedule(cfg)
     if d0 is None:
         d0 = delta0(cfg, cfg["species"][species_index]["field"])
@@ -168,10 +169,11 @@ def run_particles(cfg, species_index, ids, k_end=None, d0=None, return_all=False
         pre = super_horizon_grids(cfg, d0, sched["a"][0], tau_i)
     x0, q, q0, p = initial_state(cfg, species_index, ids, pre, sched)
     m = cfg["species"][species_index]["m"]
+    order = max(1, int(cfg.get("interp_order", 1)))
     if eom == push.EOM_SEPARABLE:
-        x, q = push.kdk(x0, q, q0, m, sched, cfg["box_mpc"], grids_at, 0, k_end)
+        x, q = push.kdk(x0, q, q0, m, sched, cfg["box_mpc"], grids_at, 0, k_end, order)
     else:
-        x, q = push.kdk_variant(x0, q, m, sched, cfg["box_mpc"], grids_at, eom, 0, k_end)
+        x, q = push.kdk_variant(x0, q, m, sched, cfg["box_mpc"], grids_at, eom, 0, k_end, order)
     w = stats.deltaf_weights(q, p)
     out = dict(x=x, q=q, q0=q0, p=p, w=w, x0=x0, sched=sched)
     if return_all:

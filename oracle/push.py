@@ -30,24 +30,48 @@ def cic_corners(x, G, L):
     return np.stack(idx), np.stack(wts)
 
 
-def interpolate(grid, x, L):
-    """Trilinear (CIC) value of a periodic (G, G, G) grid at positions x (N, 3)."""
+def tsc_points(x, G, L):
+    """Triangular-shaped-cloud stencil (interpolation order r = 2, sec. 4).
+
+    u = x G / L, nearest mesh point i = floor(u + 1/2), d = u - i in [-1/2, 1/2)
+    per axis; the 27 points are (i + o) mod G for o in {-1, 0, 1}^3 with the
+    product of the one-dimensional weights (1/2)(1/2 - d)^2, 3/4 - d^2 and
+    (1/2)(1/2 + d)^2.  Returns (idx (27, N, 3) int64, wts (27, N)).
+    """
+    u = np.asarray(x, dtype=np.float64) * (G / L)
+    i = np.floor(u + 0.5)
+    d = u - i
+    i = i.astype(np.int64)
+    w1 = [0.5 * (0.5 - d) ** 2, 0.75 - d ** 2, 0.5 * (0.5 + d) ** 2]
+    idx, wts = [], []
+    for ox in range(3):
+        for oy in range(3):
+            for oz in range(3):
+                o = np.array([ox, oy, oz]) - 1
+                idx.append((i + o) % G)
+                wts.append(w1[ox][:, 0] * w1[oy][:, 1] * w1[oz][:, 2])
+    return np.stack(idx), np.stack(wts)
+
+
+def interpolate(grid, x, L, order=1):
+    """Value of a periodic (G, G, G) grid at positions x (N, 3): trilinear
+    (CIC, order 1) or triangular-shaped cloud (TSC, order 2)."""
     G = grid.shape[0]
-    idx, wts = cic_corners(x, G, L)
+    idx, wts = cic_corners(x, G, L) if order == 1 else tsc_points(x, G, L)
     out = np.zeros(x.shape[0])
-    for c in range(8):
+    for c in range(len(wts)):
         out += wts[c] * grid[idx[c, :, 0], idx[c, :, 1], idx[c, :, 2]]
     return out
 
 
-def sample_fields(grids, x, L):
+def sample_fields(grids, x, L, order=1):
     """Gradients of psi and phi (N, 3) and phi-dot (N,) at the particles."""
-    gpsi = np.stack([interpolate(grids["gpsi"][d], x, L) for d in range(3)], axis=-1)
+    gpsi = np.stack([interpolate(grids["gpsi"][d], x, L, order) for d in range(3)], axis=-1)
     if grids["gphi"] is grids["gpsi"]:
         gphi = gpsi
     else:
-        gphi = np.stack([interpolate(grids["gphi"][d], x, L) for d in range(3)], axis=-1)
-    phidot = interpolate(grids["phidot"], x, L)
+        gphi = np.stack([interpolate(grids["gphi"][d], x, L, order) for d in range(3)], axis=-1)
+    phidot = interpolate(grids["phidot"], x, L, order)
     return gpsi, gphi, phidot
 
 
@@ -72,13 +96,14 @@ def velocity(q, m, a):
     return q / eps[:, None]
 
 
-def kdk(x, q, q0, m, sched, L, grids_at, k_begin=0, k_end=None):
+def kdk(x, q, q0, m, sched, L, grids_at, k_begin=0, k_end=None, order=1):
     """Leapfrog of sec. 3.3 for steps k_begin .. k_end-1 of a schedule.
 
     Each step: q += dtau_k^{k+1/2} F(x_k, a_k); x += dtau_k^{k+1} v(q, a_{k+1/2})
     (mod L); q += dtau_{k+1/2}^{k+1} F(x_{k+1}, a_{k+1}).  The half-kicks are
     kept separate.  grids_at(k) returns the grid set at time a_k.  The drift
-    uses a_{k+1/2}, the midpoint in log a.  Returns new (x, q).
+    uses a_{k+1/2}, the midpoint in log a.  order: force interpolation (1 CIC,
+    2 TSC).  Returns new (x, q).
     """
     x = np.array(x, dtype=np.float64)
     q = np.array(q, dtype=np.float64)
@@ -86,11 +111,11 @@ def kdk(x, q, q0, m, sched, L, grids_at, k_begin=0, k_end=None):
     n = len(sched["drift"])
     k_end = n if k_end is None else k_end
     for k in range(k_begin, k_end):
-        g = sample_fields(grids_at(k), x, L)
+        g = sample_fields(grids_at(k), x, L, order)
         q = q + sched["kick1"][k] * separable_force(q0, m, sched["a"][k], *g)
         x = x + sched["drift"][k] * velocity(q, m, sched["a_half"][k])
         x = np.mod(x, L)
-        g = sample_fields(grids_at(k + 1), x, L)
+        g = sample_fields(grids_at(k + 1), x, L, order)
         q = q + sched["kick2"][k] * separable_force(q0, m, sched["a"][k + 1], *g)
     return x, q
 
@@ -116,11 +141,11 @@ EOM_BY_NAME = dict(separable=EOM_SEPARABLE, exact=EOM_EXACT, canonical=EOM_CANON
                    sr_newton=EOM_SR_NEWTON, simple_q=EOM_SIMPLE_Q, newtonian=EOM_NEWTONIAN)
 
 
-def sample_potentials(grids, x, L):
+def sample_potentials(grids, x, L, order=1):
     """gpsi, gphi (N, 3), phidot, psi, phi (N,) at the particles (absent -> 0)."""
-    gpsi, gphi, phidot = sample_fields(grids, x, L)
-    psi = interpolate(grids["psi"], x, L) if "psi" in grids else np.zeros(len(x))
-    phi = interpolate(grids["phi"], x, L) if "phi" in grids else np.zeros(len(x))
+    gpsi, gphi, phidot = sample_fields(grids, x, L, order)
+    psi = interpolate(grids["psi"], x, L, order) if "psi" in grids else np.zeros(len(x))
+    phi = interpolate(grids["phi"], x, L, order) if "phi" in grids else np.zeros(len(x))
     return gpsi, gphi, phidot, psi, phi
 
 
@@ -164,7 +189,7 @@ def variant_velocity(mode, q, m, a, psi, phi):
     return v
 
 
-def kdk_variant(x, q, m, sched, L, grids_at, mode, k_begin=0, k_end=None):
+def kdk_variant(x, q, m, sched, L, grids_at, mode, k_begin=0, k_end=None, order=1):
     """Explicit leapfrog for the non-separable forms: for k = k_begin .. k_end-1
       q += dtau_k^{k+1/2} F(x_k, q, a_k);
       x += dtau_k^{k+1} v(q, a_{k+1/2}; phi, psi at x_k)   (mod L);
@@ -174,9 +199,9 @@ def kdk_variant(x, q, m, sched, L, grids_at, mode, k_begin=0, k_end=None):
     n = len(sched["drift"])
     k_end = n if k_end is None else k_end
     for k in range(k_begin, k_end):
-        gpsi, gphi, phidot, psi, phi = sample_potentials(grids_at(k), x, L)
+        gpsi, gphi, phidot, psi, phi = sample_potentials(grids_at(k), x, L, order)
         q = q + sched["kick1"][k] * variant_force(mode, q, m, sched["a"][k], gpsi, gphi, phidot)
         x = np.mod(x + sched["drift"][k] * variant_velocity(mode, q, m, sched["a_half"][k], psi, phi), L)
-        gpsi, gphi, phidot, _, _ = sample_potentials(grids_at(k + 1), x, L)
+        gpsi, gphi, phidot, _, _ = sample_potentials(grids_at(k + 1), x, L, order)
         q = q + sched["kick2"][k] * variant_force(mode, q, m, sched["a"][k + 1], gpsi, gphi, phidot)
     return x, q

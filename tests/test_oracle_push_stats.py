@@ -604,3 +604,39 @@ def test_momentum_divergence_plane_waves(axis):
             assert np.all(np.abs(np.delete(total, b0)) < 1e-20 * total[b0])
         else:
             assert np.all(np.abs(total) < 1e-25)
+
+
+# ------------------------------------------------- TSC interpolation --
+
+def test_tsc_weight_moments():
+    """The three one-dimensional TSC weights are fixed by their moments about
+    the particle: sum 1, mean offset 0, mean squared offset 1/4 (the second
+    moment of the triangular cloud convolved with the mesh cell)."""
+    rng = np.random.default_rng(3)
+    G, L = 16, 100.0
+    x = rng.uniform(0, L, size=(500, 3))
+    idx, w = push.tsc_points(x, G, L)
+    assert idx.shape == (27, 500, 3) and np.all(w >= 0)
+    assert np.allclose(w.sum(0), 1.0, rtol=0, atol=1e-14)
+    u = x * G / L
+    off = (idx - u[None] + G / 2) % G - G / 2          # offsets in [-G/2, G/2)
+    for a in range(3):
+        assert np.allclose(np.sum(w * off[..., a], 0), 0.0, atol=1e-13)
+        assert np.allclose(np.sum(w * off[..., a] ** 2, 0), 0.25, atol=1e-13)
+        assert np.all(np.abs(off[..., a]) < 1.5 + 1e-12)
+
+
+def test_tsc_reproduces_linear_and_quadratic_fields():
+    """Away from the periodic seam, TSC interpolation returns a linear field
+    exactly and a quadratic one as u^2 + 1/4; CIC returns u^2 + t (1 - t)."""
+    G, L = 32, 64.0
+    j = np.arange(G, dtype=np.float64)
+    lin = (1.5 + 0.25 * j)[:, None, None] * np.ones((G, G, G))
+    quad = (j ** 2)[None, None, :] * np.ones((G, G, G))
+    rng = np.random.default_rng(9)
+    x = rng.uniform(4 * L / G, 26 * L / G, size=(300, 3))
+    u = x * G / L
+    assert np.allclose(push.interpolate(lin, x, L, 2), 1.5 + 0.25 * u[:, 0], rtol=0, atol=1e-12)
+    assert np.allclose(push.interpolate(quad, x, L, 2), u[:, 2] ** 2 + 0.25, rtol=0, atol=1e-10)
+    t = u[:, 2] - np.floor(u[:, 2])
+    assert np.allclose(push.interpolate(quad, x, L, 1), u[:, 2] ** 2 + t * (1 - t), rtol=0, atol=1e-10)
