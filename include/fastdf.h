@@ -126,7 +126,8 @@ typedef struct fdf_config {
   int32_t sort_every;      /* spatial re-sort of particles every this many steps (0: never) */
   int32_t max_fields;      /* capacity: number of seeded fields (each owns one grid set) */
   int32_t max_species;     /* capacity: number of species */
-  int32_t pad1;
+  int32_t interp_order;    /* force interpolation order r (sec. 4): 0 or 1 CIC (8 points),
+                              2 TSC (27 points); deposits stay CIC */
   int64_t max_particles;   /* capacity: total particles over all species */
   double superstep_tol;    /* time-dependent potentials only.  0: rebuild the grids at
                               every kick time.  > 0: super-steps (sec. 2.1) -- grids are

@@ -240,6 +240,7 @@ const char* validate(const fdf_config* c) {
   if (c->max_particles > ((int64_t)1 << 32)) return "at most 2^32 particles";
   if (!(c->superstep_tol >= 0) || !std::isfinite(c->superstep_tol)) return "superstep_tol must be >= 0";
   if (c->eom < FDF_EOM_SEPARABLE || c->eom > FDF_EOM_NEWTONIAN) return "unknown equation of motion";
+  if (c->interp_order < 0 || c->interp_order > 2) return "interp_order must be 0, 1 (CIC) or 2 (TSC)";
   return nullptr;
 }
 
@@ -911,6 +912,7 @@ int enqueue_steps(fdf_ctx* c, int32_t n) {
   pa.persistent = c->persistent;
   pa.do_kick = 1;
   pa.eom = c->cfg.eom;
+  pa.tsc = c->cfg.interp_order == 2;
   for (int j = 0; j <= nabs; ++j) {
     int t;            // integer time of this launch's kick
     double kclose = 0, kopen = 0, drift = 0, a_drift = 0;   // half-kicks ending / starting at t

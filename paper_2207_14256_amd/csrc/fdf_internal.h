@@ -101,6 +101,7 @@ struct PushArgs {
   double box;              // L
   int32_t ppt;             // particles per thread
   int32_t persistent;      // 0: one block per chunk; > 0: this many blocks (a multiple of 8) loop
+  int32_t tsc;             // 1: TSC (r = 2) force interpolation, 0: CIC
   int32_t blend;           // 1: interpolate two grid sets (super-steps)
   int32_t grid_sel;        // which set holds the earlier anchor: 0 = grid, 1 = grid2
   double blend_t;          // interpolation weight of the later anchor

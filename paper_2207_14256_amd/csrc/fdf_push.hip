@@ -6,7 +6,8 @@
 // then the drift.  The last launch of a call is a kick alone, leaving q at a
 // schedule point.
 //
-// Per particle: CIC (trilinear) interpolation of the gradient grids at x,
+// Per particle: CIC (trilinear; or TSC, 27 points, when PushArgs::tsc is set)
+// interpolation of the gradient grids at x,
 //   F = -eps0 grad psi - (q0^2/eps0) grad phi + q0 (q0 . grad phi)/eps0 + q0 phidot
 //   (eq. releq_approx, eps0 = sqrt(q0^2 + m^2 a^2)),
 //   q += kick * F,  x += drift * q / sqrt(q^2 + m^2 a_{k+1/2}^2)   (eq. discrete_drift).
@@ -30,17 +31,17 @@ using namespace push_detail;
 
 // Gather of the slots (8-slot: gpsi[3], gphi[3], phidot; 4-slot: gpsi[3], phidot
 // with phi = psi) from a bfloat16 grid.
-template <int NSLOT>
+template <int NSLOT, int NPT>
 __device__ __forceinline__ void gather_bf16(const void* grid, const size_t* cell, const float* w,
                                             float* g /* 7, accumulated */) {
 #pragma clang fp contract(off)
   if constexpr (NSLOT == 8) {
     const uint4* gp = (const uint4*)grid;
-    uint4 v[8];
+    uint4 v[NPT];
 #pragma unroll
-    for (int c = 0; c < 8; ++c) v[c] = gp[cell[c]];
+    for (int c = 0; c < NPT; ++c) v[c] = gp[cell[c]];
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
+    for (int c = 0; c < NPT; ++c) {
       g[0] = fmaf(w[c], bf16_lo(v[c].x), g[0]); g[1] = fmaf(w[c], bf16_hi(v[c].x), g[1]);
       g[2] = fmaf(w[c], bf16_lo(v[c].y), g[2]); g[3] = fmaf(w[c], bf16_hi(v[c].y), g[3]);
       g[4] = fmaf(w[c], bf16_lo(v[c].z), g[4]); g[5] = fmaf(w[c], bf16_hi(v[c].z), g[5]);
@@ -48,14 +49,26 @@ __device__ __forceinline__ void gather_bf16(const void* grid, const size_t* cell
     }
   } else {
     const uint2* gp = (const uint2*)grid;
-    uint2 v[8];
+    uint2 v[NPT];
 #pragma unroll
-    for (int c = 0; c < 8; ++c) v[c] = gp[cell[c]];
+    for (int c = 0; c < NPT; ++c) v[c] = gp[cell[c]];
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
+    for (int c = 0; c < NPT; ++c) {
       g[0] = fmaf(w[c], bf16_lo(v[c].x), g[0]); g[1] = fmaf(w[c], bf16_hi(v[c].x), g[1]);
       g[2] = fmaf(w[c], bf16_lo(v[c].y), g[2]); g[6] = fmaf(w[c], bf16_hi(v[c].y), g[6]);
     }
+  }
+}
+
+// Gather over a whole stencil: CIC in one batch of 8 loads, TSC in three
+// batches of 9 (one x-plane of the 27 points each).
+template <int NSLOT, bool TSC>
+__device__ __forceinline__ void gather_stencil_bf16(const void* grid, const size_t* cell, const float* w, float* g) {
+  if constexpr (TSC) {
+#pragma unroll
+    for (int b = 0; b < 3; ++b) gather_bf16<NSLOT, 9>(grid, cell + 9 * b, w + 9 * b, g);
+  } else {
+    gather_bf16<NSLOT, 8>(grid, cell, w, g);
   }
 }
 
@@ -63,16 +76,16 @@ __device__ __forceinline__ void gather_bf16(const void* grid, const size_t* cell
 // (explicit fmaf, no contraction) so that the unrolled copies of the loop are
 // instruction-identical: a particle gets bit-identical results in whichever
 // slot of whichever block it lands after a re-sort.
-template <int NSLOT, int PPT, bool BLEND>
+template <int NSLOT, int PPT, bool BLEND, bool TSC>
 __device__ __forceinline__ void push_chunk_f32(const PushArgs& a, int64_t chunk) {
 #pragma clang fp contract(off)
+  constexpr int NP = Stencil<TSC>::N;
   const int s = find_segment(a.seg, a.nseg, chunk);
   const Segment& sg = a.seg[s];
   const int64_t n = sg.n;
   const int64_t first = (chunk - sg.chunk_begin) * (int64_t)(kBlock * PPT) + threadIdx.x;
   const int shift = 32 - a.log2g;
   const uint32_t gmask = (uint32_t)a.G - 1u;
-  const uint32_t fmask = (1u << shift) - 1u;
   const float finv = __uint_as_float((uint32_t)(127 - shift) << 23);   // 2^-shift
   const float kick = (float)a.kick;
   const float ma = (float)(sg.m * a.a_kick);
@@ -97,33 +110,19 @@ __device__ __forceinline__ void push_chunk_f32(const PushArgs& a, int64_t chunk)
       c[d] = ldnt(&sg.cf[d][i]);
       q0[d] = ldnt(&sg.q0f[d][i]);
     }
-    // CIC corners and weights from the fixed-point position
-    uint32_t i0[3], i1[3];
-    float t[3], u[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      i0[d] = xu[d] >> shift;
-      i1[d] = (i0[d] + 1u) & gmask;
-      t[d] = (float)(xu[d] & fmask) * finv;
-      u[d] = 1.0f - t[d];
-    }
-    size_t cell[8];
-    float w[8];
-#pragma unroll
-    for (int cc = 0; cc < 8; ++cc) {
-      const int cx = cc >> 2, cy = (cc >> 1) & 1, cz = cc & 1;
-      cell[cc] = ((size_t)(cx ? i1[0] : i0[0]) * G + (cy ? i1[1] : i0[1])) * G + (cz ? i1[2] : i0[2]);
-      w[cc] = ((cx ? t[0] : u[0]) * (cy ? t[1] : u[1])) * (cz ? t[2] : u[2]);
-    }
+    // interpolation stencil from the fixed-point position
+    size_t cell[NP];
+    float w[NP];
+    stencil_u32<TSC>(xu, shift, gmask, finv, G, cell, w);
     float g[7] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-    if (BLEND) {   // super-steps: (1 - t) G_A + t G_B folded into the CIC weights
-      float wa[8], wb[8];
+    if (BLEND) {   // super-steps: (1 - t) G_A + t G_B folded into the weights
+      float wa[NP], wb[NP];
 #pragma unroll
-      for (int cc = 0; cc < 8; ++cc) { wa[cc] = ta * w[cc]; wb[cc] = tb * w[cc]; }
-      gather_bf16<NSLOT>(gridA, cell, wa, g);
-      gather_bf16<NSLOT>(gridB, cell, wb, g);
+      for (int cc = 0; cc < NP; ++cc) { wa[cc] = ta * w[cc]; wb[cc] = tb * w[cc]; }
+      gather_stencil_bf16<NSLOT, TSC>(gridA, cell, wa, g);
+      gather_stencil_bf16<NSLOT, TSC>(gridB, cell, wb, g);
     } else {
-      gather_bf16<NSLOT>(gridA, cell, w, g);
+      gather_stencil_bf16<NSLOT, TSC>(gridA, cell, w, g);
     }
     if (NSLOT == 4) { g[3] = g[0]; g[4] = g[1]; g[5] = g[2]; }
     // separable force of eq. releq_approx
@@ -159,13 +158,13 @@ __device__ __forceinline__ void push_chunk_f32(const PushArgs& a, int64_t chunk)
   }
 }
 
-template <int NSLOT>
+template <int NSLOT, int NPT>
 __device__ __forceinline__ void gather_f64(const void* grid, const size_t* cell, const double* w,
                                            double* g /* 7, accumulated */) {
 #pragma clang fp contract(off)
   const double2* gp = (const double2*)grid;
 #pragma unroll
-  for (int c = 0; c < 8; ++c) {
+  for (int c = 0; c < NPT; ++c) {
     if constexpr (NSLOT == 8) {
       const double2 v0 = gp[4 * cell[c]], v1 = gp[4 * cell[c] + 1];
       const double2 v2 = gp[4 * cell[c] + 2], v3 = gp[4 * cell[c] + 3];
@@ -180,9 +179,20 @@ __device__ __forceinline__ void gather_f64(const void* grid, const size_t* cell,
   }
 }
 
-template <int NSLOT, int PPT, bool BLEND>
+template <int NSLOT, bool TSC>
+__device__ __forceinline__ void gather_stencil_f64(const void* grid, const size_t* cell, const double* w, double* g) {
+  if constexpr (TSC) {
+#pragma unroll
+    for (int b = 0; b < 3; ++b) gather_f64<NSLOT, 9>(grid, cell + 9 * b, w + 9 * b, g);
+  } else {
+    gather_f64<NSLOT, 8>(grid, cell, w, g);
+  }
+}
+
+template <int NSLOT, int PPT, bool BLEND, bool TSC>
 __device__ __forceinline__ void push_chunk_f64(const PushArgs& a, int64_t chunk) {
 #pragma clang fp contract(off)
+  constexpr int NP = Stencil<TSC>::N;
   const int s = find_segment(a.seg, a.nseg, chunk);
   const Segment& sg = a.seg[s];
   const int64_t n = sg.n;
@@ -207,33 +217,18 @@ __device__ __forceinline__ void push_chunk_f64(const PushArgs& a, int64_t chunk)
       q[d] = ldnt(&sg.qd[d][i]);
       q0[d] = ldnt(&sg.q0d[d][i]);
     }
-    int i0[3], i1[3];
-    double t[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      const double u = x[d] * ginv;
-      const double fl = floor(u);
-      t[d] = u - fl;
-      i0[d] = ((int)fl) & gm;
-      i1[d] = (i0[d] + 1) & gm;
-    }
-    size_t cell[8];
-    double w[8];
-#pragma unroll
-    for (int cc = 0; cc < 8; ++cc) {
-      const int cx = cc >> 2, cy = (cc >> 1) & 1, cz = cc & 1;
-      cell[cc] = ((size_t)(cx ? i1[0] : i0[0]) * G + (cy ? i1[1] : i0[1])) * G + (cz ? i1[2] : i0[2]);
-      w[cc] = ((cx ? t[0] : 1.0 - t[0]) * (cy ? t[1] : 1.0 - t[1])) * (cz ? t[2] : 1.0 - t[2]);
-    }
+    size_t cell[NP];
+    double w[NP];
+    stencil_f64<TSC>(x, ginv, gm, G, cell, w);
     double g[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     if (BLEND) {
-      double wa[8], wb[8];
+      double wa[NP], wb[NP];
 #pragma unroll
-      for (int cc = 0; cc < 8; ++cc) { wa[cc] = ta * w[cc]; wb[cc] = tb * w[cc]; }
-      gather_f64<NSLOT>(gridA, cell, wa, g);
-      gather_f64<NSLOT>(gridB, cell, wb, g);
+      for (int cc = 0; cc < NP; ++cc) { wa[cc] = ta * w[cc]; wb[cc] = tb * w[cc]; }
+      gather_stencil_f64<NSLOT, TSC>(gridA, cell, wa, g);
+      gather_stencil_f64<NSLOT, TSC>(gridB, cell, wb, g);
     } else {
-      gather_f64<NSLOT>(gridA, cell, w, g);
+      gather_stencil_f64<NSLOT, TSC>(gridA, cell, w, g);
     }
     if (NSLOT == 4) { g[3] = g[0]; g[4] = g[1]; g[5] = g[2]; }
     const double q0sq = fma(q0[0], q0[0], fma(q0[1], q0[1], q0[2] * q0[2]));
@@ -262,39 +257,44 @@ __device__ __forceinline__ void push_chunk_f64(const PushArgs& a, int64_t chunk)
 // Chunk loop.  One block per chunk, or (persistent) a fixed grid whose
 // blocks stride over the chunks; either way each XCD (block id mod 8) walks a
 // contiguous eighth of the chunk range.
-template <int NSLOT, int PPT, bool BLEND>
+template <int NSLOT, int PPT, bool BLEND, bool TSC>
 __global__ void __launch_bounds__(kBlock) k_push_f32(PushArgs a) {
-  if (!a.persistent) { push_chunk_f32<NSLOT, PPT, BLEND>(a, xcd_chunk(blockIdx.x, gridDim.x)); return; }
+  if (!a.persistent) { push_chunk_f32<NSLOT, PPT, BLEND, TSC>(a, xcd_chunk(blockIdx.x, gridDim.x)); return; }
   const int64_t per = (a.total_chunks + 7) / 8, x = blockIdx.x % 8, stride = gridDim.x / 8;
   const int64_t end = min((x + 1) * per, a.total_chunks);
-  for (int64_t c = x * per + blockIdx.x / 8; c < end; c += stride) push_chunk_f32<NSLOT, PPT, BLEND>(a, c);
+  for (int64_t c = x * per + blockIdx.x / 8; c < end; c += stride) push_chunk_f32<NSLOT, PPT, BLEND, TSC>(a, c);
 }
 
-template <int NSLOT, int PPT, bool BLEND>
+template <int NSLOT, int PPT, bool BLEND, bool TSC>
 __global__ void __launch_bounds__(kBlock) k_push_f64(PushArgs a) {
-  if (!a.persistent) { push_chunk_f64<NSLOT, PPT, BLEND>(a, xcd_chunk(blockIdx.x, gridDim.x)); return; }
+  if (!a.persistent) { push_chunk_f64<NSLOT, PPT, BLEND, TSC>(a, xcd_chunk(blockIdx.x, gridDim.x)); return; }
   const int64_t per = (a.total_chunks + 7) / 8, x = blockIdx.x % 8, stride = gridDim.x / 8;
   const int64_t end = min((x + 1) * per, a.total_chunks);
-  for (int64_t c = x * per + blockIdx.x / 8; c < end; c += stride) push_chunk_f64<NSLOT, PPT, BLEND>(a, c);
+  for (int64_t c = x * per + blockIdx.x / 8; c < end; c += stride) push_chunk_f64<NSLOT, PPT, BLEND, TSC>(a, c);
 }
 
-template <int PPT, bool BLEND>
+template <int PPT, bool BLEND, bool TSC>
 void push_launch(const PushArgs& a, hipStream_t s) {
   const int64_t grid_blocks = a.persistent ? a.persistent : a.total_chunks;
   const dim3 grid((unsigned)grid_blocks), block(kBlock);
   if (a.fp64) {
-    if (a.nslot == 8) hipLaunchKernelGGL((k_push_f64<8, PPT, BLEND>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((k_push_f64<4, PPT, BLEND>), grid, block, 0, s, a);
+    if (a.nslot == 8) hipLaunchKernelGGL((k_push_f64<8, PPT, BLEND, TSC>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_push_f64<4, PPT, BLEND, TSC>), grid, block, 0, s, a);
   } else {
-    if (a.nslot == 8) hipLaunchKernelGGL((k_push_f32<8, PPT, BLEND>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((k_push_f32<4, PPT, BLEND>), grid, block, 0, s, a);
+    if (a.nslot == 8) hipLaunchKernelGGL((k_push_f32<8, PPT, BLEND, TSC>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_push_f32<4, PPT, BLEND, TSC>), grid, block, 0, s, a);
   }
 }
 
 template <int PPT>
 void push_ppt(const PushArgs& a, hipStream_t s) {
-  if (a.blend) push_launch<PPT, true>(a, s);
-  else push_launch<PPT, false>(a, s);
+  if (a.tsc) {
+    if (a.blend) push_launch<PPT, true, true>(a, s);
+    else push_launch<PPT, false, true>(a, s);
+  } else {
+    if (a.blend) push_launch<PPT, true, false>(a, s);
+    else push_launch<PPT, false, false>(a, s);
+  }
 }
 
 }  // namespace

@@ -28,5 +28,112 @@ __device__ __forceinline__ int find_segment(const Segment* seg, int nseg, int64_
 template <typename T> __device__ __forceinline__ T ldnt(const T* p) { return __builtin_nontemporal_load(p); }
 template <typename T> __device__ __forceinline__ void stnt(T v, T* p) { __builtin_nontemporal_store(v, p); }
 
+// Interpolation stencil of the force: CIC (r = 1, 8 points) or TSC (r = 2,
+// 27 points).  Every operation is explicit so that each copy of the code is
+// instruction-identical (bitwise results whatever slot a particle lands in).
+template <bool TSC> struct Stencil { static constexpr int N = TSC ? 27 : 8; };
+
+// FP32 form: x is a 32-bit fixed-point fraction of the box per axis.
+template <bool TSC>
+__device__ __forceinline__ void stencil_u32(const uint32_t* xu, int shift, uint32_t gmask, float finv,
+                                            size_t G, size_t* cell, float* w) {
+#pragma clang fp contract(off)
+  const uint32_t fmask = (1u << shift) - 1u;
+  if constexpr (!TSC) {
+    uint32_t i0[3], i1[3];
+    float t[3], u[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      i0[d] = xu[d] >> shift;
+      i1[d] = (i0[d] + 1u) & gmask;
+      t[d] = (float)(xu[d] & fmask) * finv;
+      u[d] = 1.0f - t[d];
+    }
+#pragma unroll
+    for (int cc = 0; cc < 8; ++cc) {
+      const int cx = cc >> 2, cy = (cc >> 1) & 1, cz = cc & 1;
+      cell[cc] = ((size_t)(cx ? i1[0] : i0[0]) * G + (cy ? i1[1] : i0[1])) * G + (cz ? i1[2] : i0[2]);
+      w[cc] = ((cx ? t[0] : u[0]) * (cy ? t[1] : u[1])) * (cz ? t[2] : u[2]);
+    }
+  } else {
+    // nearest point i = floor(u + 1/2); f = u + 1/2 - i = d + 1/2 in [0, 1)
+    uint32_t idx[3][3];
+    float wt[3][3];
+    const uint32_t half = 1u << (shift - 1);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const uint32_t xs = xu[d] + half;                 // wraps with the box
+      const uint32_t i = xs >> shift;
+      const float f = (float)(xs & fmask) * finv;
+      const float g = 1.0f - f, h = f - 0.5f;
+      idx[d][0] = (i - 1u) & gmask;
+      idx[d][1] = i;
+      idx[d][2] = (i + 1u) & gmask;
+      wt[d][0] = 0.5f * (g * g);                        // (1/2 - d)^2 / 2
+      wt[d][1] = 0.75f - h * h;                         // 3/4 - d^2
+      wt[d][2] = 0.5f * (f * f);                        // (1/2 + d)^2 / 2
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          cell[9 * a + 3 * b + c] = ((size_t)idx[0][a] * G + idx[1][b]) * G + idx[2][c];
+          w[9 * a + 3 * b + c] = (wt[0][a] * wt[1][b]) * wt[2][c];
+        }
+  }
+}
+
+// FP64 form: x in [0, L) Mpc.
+template <bool TSC>
+__device__ __forceinline__ void stencil_f64(const double* x, double ginv, int gm, size_t G,
+                                            size_t* cell, double* w) {
+#pragma clang fp contract(off)
+  if constexpr (!TSC) {
+    int i0[3], i1[3];
+    double t[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const double u = x[d] * ginv;
+      const double fl = floor(u);
+      t[d] = u - fl;
+      i0[d] = ((int)fl) & gm;
+      i1[d] = (i0[d] + 1) & gm;
+    }
+#pragma unroll
+    for (int cc = 0; cc < 8; ++cc) {
+      const int cx = cc >> 2, cy = (cc >> 1) & 1, cz = cc & 1;
+      cell[cc] = ((size_t)(cx ? i1[0] : i0[0]) * G + (cy ? i1[1] : i0[1])) * G + (cz ? i1[2] : i0[2]);
+      w[cc] = ((cx ? t[0] : 1.0 - t[0]) * (cy ? t[1] : 1.0 - t[1])) * (cz ? t[2] : 1.0 - t[2]);
+    }
+  } else {
+    int idx[3][3];
+    double wt[3][3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const double u = x[d] * ginv;
+      const double fl = floor(u + 0.5);
+      const double dd = u - fl;                         // in [-1/2, 1/2)
+      const int i = ((int)fl) & gm;
+      idx[d][0] = (i - 1) & gm;
+      idx[d][1] = i;
+      idx[d][2] = (i + 1) & gm;
+      wt[d][0] = 0.5 * ((0.5 - dd) * (0.5 - dd));
+      wt[d][1] = 0.75 - dd * dd;
+      wt[d][2] = 0.5 * ((0.5 + dd) * (0.5 + dd));
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          cell[9 * a + 3 * b + c] = ((size_t)idx[0][a] * G + idx[1][b]) * G + idx[2][c];
+          w[9 * a + 3 * b + c] = (wt[0][a] * wt[1][b]) * wt[2][c];
+        }
+  }
+}
+
 }  // namespace push_detail
 }  // namespace fdf

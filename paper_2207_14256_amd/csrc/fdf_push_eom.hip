@@ -31,17 +31,17 @@ using namespace push_detail;
 
 enum : int32_t { EOM_EXACT = 1, EOM_CANONICAL = 2, EOM_SR_NEWTON = 3, EOM_SIMPLE_Q = 4, EOM_NEWTONIAN = 5 };
 
-// All slots of a cell, accumulated with the CIC weights.
-template <int NSLOT>
+// All slots of a cell, accumulated with the stencil weights.
+template <int NSLOT, int NPT>
 __device__ __forceinline__ void gather_all_bf16(const void* grid, const size_t* cell, const float* w, float* g) {
 #pragma clang fp contract(off)
   if constexpr (NSLOT == 8) {
     const uint4* gp = (const uint4*)grid;
-    uint4 v[8];
+    uint4 v[NPT];
 #pragma unroll
-    for (int c = 0; c < 8; ++c) v[c] = gp[cell[c]];
+    for (int c = 0; c < NPT; ++c) v[c] = gp[cell[c]];
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
+    for (int c = 0; c < NPT; ++c) {
       const uint32_t u[4] = {v[c].x, v[c].y, v[c].z, v[c].w};
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
@@ -51,23 +51,23 @@ __device__ __forceinline__ void gather_all_bf16(const void* grid, const size_t* 
     }
   } else {
     const uint2* gp = (const uint2*)grid;
-    uint2 v[8];
+    uint2 v[NPT];
 #pragma unroll
-    for (int c = 0; c < 8; ++c) v[c] = gp[cell[c]];
+    for (int c = 0; c < NPT; ++c) v[c] = gp[cell[c]];
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
+    for (int c = 0; c < NPT; ++c) {
       g[0] = fmaf(w[c], bf16_lo(v[c].x), g[0]); g[1] = fmaf(w[c], bf16_hi(v[c].x), g[1]);
       g[2] = fmaf(w[c], bf16_lo(v[c].y), g[2]);
     }
   }
 }
 
-template <int NSLOT>
+template <int NSLOT, int NPT>
 __device__ __forceinline__ void gather_all_f64(const void* grid, const size_t* cell, const double* w, double* g) {
 #pragma clang fp contract(off)
   const double2* gp = (const double2*)grid;
 #pragma unroll
-  for (int c = 0; c < 8; ++c) {
+  for (int c = 0; c < NPT; ++c) {
 #pragma unroll
     for (int j = 0; j < NSLOT / 2; ++j) {
       if (NSLOT == 4 && j == 1) {
@@ -78,6 +78,17 @@ __device__ __forceinline__ void gather_all_f64(const void* grid, const size_t* c
         g[2 * j + 1] = fma(w[c], v.y, g[2 * j + 1]);
       }
     }
+  }
+}
+
+// Whole stencil: CIC in one batch, TSC in three x-planes of 9 points.
+template <int NSLOT, bool TSC, typename R>
+__device__ __forceinline__ void gather_stencil(const void* grid, const size_t* cell, const R* w, R* g) {
+  constexpr int B = TSC ? 3 : 1, NPT = TSC ? 9 : 8;
+#pragma unroll
+  for (int b = 0; b < B; ++b) {
+    if constexpr (sizeof(R) == 4) gather_all_bf16<NSLOT, NPT>(grid, cell + NPT * b, w + NPT * b, g);
+    else gather_all_f64<NSLOT, NPT>(grid, cell + NPT * b, w + NPT * b, g);
   }
 }
 
@@ -120,16 +131,16 @@ __device__ __forceinline__ R eom_drift_factor(int eom, R q2, R ie2, const R* g) 
   return (R)0;
 }
 
-template <int NSLOT, int PPT, bool BLEND>
+template <int NSLOT, int PPT, bool BLEND, bool TSC>
 __device__ __forceinline__ void push_chunk_eom_f32(const PushArgs& a, int64_t chunk) {
 #pragma clang fp contract(off)
+  constexpr int NP = Stencil<TSC>::N;
   const int s = find_segment(a.seg, a.nseg, chunk);
   const Segment& sg = a.seg[s];
   const int64_t n = sg.n;
   const int64_t first = (chunk - sg.chunk_begin) * (int64_t)(kBlock * PPT) + threadIdx.x;
   const int shift = 32 - a.log2g;
   const uint32_t gmask = (uint32_t)a.G - 1u;
-  const uint32_t fmask = (1u << shift) - 1u;
   const float finv = __uint_as_float((uint32_t)(127 - shift) << 23);   // 2^-shift
   const float kicks[2] = {(float)a.kick, (float)a.kick_open};
   const float ma = (float)(sg.m * a.a_kick);
@@ -153,32 +164,18 @@ __device__ __forceinline__ void push_chunk_eom_f32(const PushArgs& a, int64_t ch
       q[d] = ldnt(&sg.qf[d][i]);
       c[d] = ldnt(&sg.cf[d][i]);
     }
-    uint32_t i0[3], i1[3];
-    float t[3], u[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      i0[d] = xu[d] >> shift;
-      i1[d] = (i0[d] + 1u) & gmask;
-      t[d] = (float)(xu[d] & fmask) * finv;
-      u[d] = 1.0f - t[d];
-    }
-    size_t cell[8];
-    float w[8];
-#pragma unroll
-    for (int cc = 0; cc < 8; ++cc) {
-      const int cx = cc >> 2, cy = (cc >> 1) & 1, cz = cc & 1;
-      cell[cc] = ((size_t)(cx ? i1[0] : i0[0]) * G + (cy ? i1[1] : i0[1])) * G + (cz ? i1[2] : i0[2]);
-      w[cc] = ((cx ? t[0] : u[0]) * (cy ? t[1] : u[1])) * (cz ? t[2] : u[2]);
-    }
+    size_t cell[NP];
+    float w[NP];
+    stencil_u32<TSC>(xu, shift, gmask, finv, G, cell, w);
     float g[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
     if (BLEND) {
-      float wa[8], wb[8];
+      float wa[NP], wb[NP];
 #pragma unroll
-      for (int cc = 0; cc < 8; ++cc) { wa[cc] = ta * w[cc]; wb[cc] = tb * w[cc]; }
-      gather_all_bf16<NSLOT>(gridA, cell, wa, g);
-      gather_all_bf16<NSLOT>(gridB, cell, wb, g);
+      for (int cc = 0; cc < NP; ++cc) { wa[cc] = ta * w[cc]; wb[cc] = tb * w[cc]; }
+      gather_stencil<NSLOT, TSC>(gridA, cell, wa, g);
+      gather_stencil<NSLOT, TSC>(gridB, cell, wb, g);
     } else {
-      gather_all_bf16<NSLOT>(gridA, cell, w, g);
+      gather_stencil<NSLOT, TSC>(gridA, cell, w, g);
     }
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -213,9 +210,10 @@ __device__ __forceinline__ void push_chunk_eom_f32(const PushArgs& a, int64_t ch
   }
 }
 
-template <int NSLOT, int PPT, bool BLEND>
+template <int NSLOT, int PPT, bool BLEND, bool TSC>
 __device__ __forceinline__ void push_chunk_eom_f64(const PushArgs& a, int64_t chunk) {
 #pragma clang fp contract(off)
+  constexpr int NP = Stencil<TSC>::N;
   const int s = find_segment(a.seg, a.nseg, chunk);
   const Segment& sg = a.seg[s];
   const int64_t n = sg.n;
@@ -240,33 +238,18 @@ __device__ __forceinline__ void push_chunk_eom_f64(const PushArgs& a, int64_t ch
       x[d] = ldnt(&sg.xd[d][i]);
       q[d] = ldnt(&sg.qd[d][i]);
     }
-    int i0[3], i1[3];
-    double t[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      const double u = x[d] * ginv;
-      const double fl = floor(u);
-      t[d] = u - fl;
-      i0[d] = ((int)fl) & gm;
-      i1[d] = (i0[d] + 1) & gm;
-    }
-    size_t cell[8];
-    double w[8];
-#pragma unroll
-    for (int cc = 0; cc < 8; ++cc) {
-      const int cx = cc >> 2, cy = (cc >> 1) & 1, cz = cc & 1;
-      cell[cc] = ((size_t)(cx ? i1[0] : i0[0]) * G + (cy ? i1[1] : i0[1])) * G + (cz ? i1[2] : i0[2]);
-      w[cc] = ((cx ? t[0] : 1.0 - t[0]) * (cy ? t[1] : 1.0 - t[1])) * (cz ? t[2] : 1.0 - t[2]);
-    }
+    size_t cell[NP];
+    double w[NP];
+    stencil_f64<TSC>(x, ginv, gm, G, cell, w);
     double g[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     if (BLEND) {
-      double wa[8], wb[8];
+      double wa[NP], wb[NP];
 #pragma unroll
-      for (int cc = 0; cc < 8; ++cc) { wa[cc] = ta * w[cc]; wb[cc] = tb * w[cc]; }
-      gather_all_f64<NSLOT>(gridA, cell, wa, g);
-      gather_all_f64<NSLOT>(gridB, cell, wb, g);
+      for (int cc = 0; cc < NP; ++cc) { wa[cc] = ta * w[cc]; wb[cc] = tb * w[cc]; }
+      gather_stencil<NSLOT, TSC>(gridA, cell, wa, g);
+      gather_stencil<NSLOT, TSC>(gridB, cell, wb, g);
     } else {
-      gather_all_f64<NSLOT>(gridA, cell, w, g);
+      gather_stencil<NSLOT, TSC>(gridA, cell, w, g);
     }
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -294,39 +277,44 @@ __device__ __forceinline__ void push_chunk_eom_f64(const PushArgs& a, int64_t ch
   }
 }
 
-template <int NSLOT, int PPT, bool BLEND>
+template <int NSLOT, int PPT, bool BLEND, bool TSC>
 __global__ void __launch_bounds__(kBlock) k_push_eom_f32(PushArgs a) {
-  if (!a.persistent) { push_chunk_eom_f32<NSLOT, PPT, BLEND>(a, xcd_chunk(blockIdx.x, gridDim.x)); return; }
+  if (!a.persistent) { push_chunk_eom_f32<NSLOT, PPT, BLEND, TSC>(a, xcd_chunk(blockIdx.x, gridDim.x)); return; }
   const int64_t per = (a.total_chunks + 7) / 8, x = blockIdx.x % 8, stride = gridDim.x / 8;
   const int64_t end = min((x + 1) * per, a.total_chunks);
-  for (int64_t c = x * per + blockIdx.x / 8; c < end; c += stride) push_chunk_eom_f32<NSLOT, PPT, BLEND>(a, c);
+  for (int64_t c = x * per + blockIdx.x / 8; c < end; c += stride) push_chunk_eom_f32<NSLOT, PPT, BLEND, TSC>(a, c);
 }
 
-template <int NSLOT, int PPT, bool BLEND>
+template <int NSLOT, int PPT, bool BLEND, bool TSC>
 __global__ void __launch_bounds__(kBlock) k_push_eom_f64(PushArgs a) {
-  if (!a.persistent) { push_chunk_eom_f64<NSLOT, PPT, BLEND>(a, xcd_chunk(blockIdx.x, gridDim.x)); return; }
+  if (!a.persistent) { push_chunk_eom_f64<NSLOT, PPT, BLEND, TSC>(a, xcd_chunk(blockIdx.x, gridDim.x)); return; }
   const int64_t per = (a.total_chunks + 7) / 8, x = blockIdx.x % 8, stride = gridDim.x / 8;
   const int64_t end = min((x + 1) * per, a.total_chunks);
-  for (int64_t c = x * per + blockIdx.x / 8; c < end; c += stride) push_chunk_eom_f64<NSLOT, PPT, BLEND>(a, c);
+  for (int64_t c = x * per + blockIdx.x / 8; c < end; c += stride) push_chunk_eom_f64<NSLOT, PPT, BLEND, TSC>(a, c);
 }
 
-template <int PPT, bool BLEND>
+template <int PPT, bool BLEND, bool TSC>
 void eom_launch(const PushArgs& a, hipStream_t s) {
   const int64_t grid_blocks = a.persistent ? a.persistent : a.total_chunks;
   const dim3 grid((unsigned)grid_blocks), block(kBlock);
   if (a.fp64) {
-    if (a.nslot == 8) hipLaunchKernelGGL((k_push_eom_f64<8, PPT, BLEND>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((k_push_eom_f64<4, PPT, BLEND>), grid, block, 0, s, a);
+    if (a.nslot == 8) hipLaunchKernelGGL((k_push_eom_f64<8, PPT, BLEND, TSC>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_push_eom_f64<4, PPT, BLEND, TSC>), grid, block, 0, s, a);
   } else {
-    if (a.nslot == 8) hipLaunchKernelGGL((k_push_eom_f32<8, PPT, BLEND>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((k_push_eom_f32<4, PPT, BLEND>), grid, block, 0, s, a);
+    if (a.nslot == 8) hipLaunchKernelGGL((k_push_eom_f32<8, PPT, BLEND, TSC>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_push_eom_f32<4, PPT, BLEND, TSC>), grid, block, 0, s, a);
   }
 }
 
 template <int PPT>
 void eom_ppt(const PushArgs& a, hipStream_t s) {
-  if (a.blend) eom_launch<PPT, true>(a, s);
-  else eom_launch<PPT, false>(a, s);
+  if (a.tsc) {
+    if (a.blend) eom_launch<PPT, true, true>(a, s);
+    else eom_launch<PPT, false, true>(a, s);
+  } else {
+    if (a.blend) eom_launch<PPT, true, false>(a, s);
+    else eom_launch<PPT, false, false>(a, s);
+  }
 }
 
 }  // namespace

@@ -46,7 +46,7 @@ class Config(ctypes.Structure):
         ("slip_amp", ctypes.c_double), ("slip_k", ctypes.c_double),
         ("ns", ctypes.c_double), ("sigma8", ctypes.c_double), ("gamma", ctypes.c_double),
         ("sort_every", ctypes.c_int32), ("max_fields", ctypes.c_int32),
-        ("max_species", ctypes.c_int32), ("pad1", ctypes.c_int32),
+        ("max_species", ctypes.c_int32), ("interp_order", ctypes.c_int32),
         ("max_particles", ctypes.c_int64), ("superstep_tol", ctypes.c_double),
     ]
 
@@ -152,6 +152,7 @@ def make_config(cfg):
     c.max_particles = int(cfg.get("max_particles", n_particles))
     c.superstep_tol = float(cfg.get("superstep_tol", 0.0))
     c.eom = EOMS[cfg.get("eom", "separable")]
+    c.interp_order = int(cfg.get("interp_order", 1))
     return c
 
 

@@ -44,3 +44,53 @@ def test_momentum_spectrum_parity(prec):
     (kdr, pdr, ndr), _ = pipeline.density_spectrum(cfg, 0, ref, "cross")
     ok = ndr > 0
     assert np.allclose(pd[ok], pdr[ok], rtol=rtol, atol=atol * np.abs(pdr[ok]).max())
+
+
+def periodic_diff(a, b, L):
+    return (a - b + L / 2) % L - L / 2
+
+
+def _tsc_cfg(prec, eom="separable", **kw):
+    base = dict(grid_n=16, n_side=13, n_steps=30, precision=prec, box_mpc=500.0, z_begin=1e6,
+                z_end=31.0, slip_amp=0.01, slip_k=1.0, interp_order=2, eom=eom)
+    base.update(kw)
+    return workloads.small("c2", **base)
+
+
+@pytest.mark.parametrize("eom", ["separable", "exact"])
+def test_tsc_parity_fp64(eom):
+    """TSC (r = 2) force interpolation against the oracle's 27-point stencil,
+    and visibly different from CIC."""
+    say("tsc %s fp64" % eom)
+    cfg = _tsc_cfg("fp64", eom)
+    ctx, fields, species = fastdf.setup_workload(cfg)
+    ctx.step(cfg["n_steps"])
+    x, q = ctx.read_state(species[0])
+    ctx.close()
+    n = 13 ** 3
+    ref = pipeline.run_particles(cfg, 0, np.arange(n))
+    L = cfg["box_mpc"]
+    assert np.max(np.abs(periodic_diff(x, ref["x"], L))) < 1e-9 * L
+    assert np.max(np.abs(q - ref["q"])) < 1e-9 * np.max(np.abs(ref["q"]))
+    cic = pipeline.run_particles(dict(cfg, interp_order=1), 0, np.arange(n))
+    assert np.max(np.abs(cic["q"] - ref["q"])) > 1e-5 * np.max(np.abs(ref["q"]))
+
+
+def test_tsc_fp32_error_statement():
+    say("tsc fp32")
+    cfg = _tsc_cfg("fp32", grid_n=32, n_side=24, n_steps=100, box_mpc=1000.0, z_begin=1e9, z_end=3.0,
+                   sort_every=10)
+    ctx, fields, species = fastdf.setup_workload(cfg)
+    ctx.step(cfg["n_steps"])
+    x, q = ctx.read_state(species[0])
+    ctx.close()
+    ids = workloads.sample_ids(24 ** 3, 2000)
+    ref = pipeline.run_particles(cfg, 0, ids)
+    L, G = cfg["box_mpc"], cfg["grid_n"]
+    dx = periodic_diff(x[ids], ref["x"], L) * (G / L)
+    pos_rms = np.sqrt(np.mean(np.sum(dx ** 2, 1)))
+    qn = np.linalg.norm(ref["q"], axis=1)
+    qrel = np.abs(np.linalg.norm(q[ids], axis=1) - qn) / qn
+    say("tsc fp32: pos rms %.3e cells, |q| rel rms %.3e" % (pos_rms, np.sqrt(np.mean(qrel ** 2))))
+    assert pos_rms < 1e-2
+    assert np.sqrt(np.mean(qrel ** 2)) < 1e-3
