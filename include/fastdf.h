@@ -93,6 +93,10 @@ enum {
  * odd-id halves (no shot-noise plateau); AUTO = auto spectrum of all particles. */
 enum { FDF_PK_CROSS = 0, FDF_PK_AUTO = 1 };
 
+/* Quantity of fdf_power_spectrum: the energy-density contrast (eq.
+ * empirical_rho) or the momentum perturbation (1 + delta) theta (sec. 4). */
+enum { FDF_PK_DENSITY = 0, FDF_PK_MOMENTUM = 1 };
+
 /* fdf_init_species flags */
 enum {
   /* apply the pre-initial conditions of sec. 2.1, eq. transform, with the
@@ -254,6 +258,16 @@ int fdf_density_power_spectrum(struct fdf_ctx* ctx, const int32_t* species, int3
 int fdf_momentum_power_spectrum(struct fdf_ctx* ctx, const int32_t* species, int32_t n_species,
                                 int32_t n_bins, int32_t mode,
                                 double* h_k, double* h_p, double* h_nmodes);
+
+/* Either spectrum (quantity FDF_PK_DENSITY or FDF_PK_MOMENTUM) estimated on an
+ * analysis mesh of analysis_n points per side instead of G: a power of two in
+ * [8, G], or 0 for G.  The bins then span [2 pi/L, pi analysis_n/L).  Runs on
+ * different meshes G compared on one analysis mesh differ only through the
+ * force resolution (sec. 4, the mesh-size study), not through the estimator.
+ * fdf_read_density afterwards needs analysis_n = G (or 0) and the density. */
+int fdf_power_spectrum(struct fdf_ctx* ctx, const int32_t* species, int32_t n_species,
+                       int32_t n_bins, int32_t mode, int32_t quantity, int32_t analysis_n,
+                       double* h_k, double* h_p, double* h_nmodes);
 
 /* ---- read-back (blocking) -------------------------------------------------- */
 

@@ -181,11 +181,12 @@ def run_particles(cfg, species_index, ids, k_end=None, d0=None, return_all=False
     return out
 
 
-def density_spectrum(cfg, species_index, res, mode="cross", a=None):
+def density_spectrum(cfg, species_index, res, mode="cross", a=None, analysis_n=0):
     """Binned P(k) of the energy-density contrast from an integrated full sample
     (res from run_particles over all ids).  mode 'cross' uses even and odd ids
-    as the two halves; 'auto' uses all particles."""
-    G, L = cfg["grid_n"], cfg["box_mpc"]
+    as the two halves; 'auto' uses all particles.  analysis_n: deposit mesh
+    (default the configuration's G)."""
+    G, L = analysis_n or cfg["grid_n"], cfg["box_mpc"]
     sp = cfg["species"][species_index]
     m = sp["m"]
     a = res["sched"]["a"][-1] if a is None else a
@@ -204,10 +205,10 @@ def density_spectrum(cfg, species_index, res, mode="cross", a=None):
     return stats.binned_power(halves[0], halves[1], L, cfg["pk_bins"]), tuple(halves)
 
 
-def momentum_spectrum(cfg, species_index, res, mode="cross", a=None):
+def momentum_spectrum(cfg, species_index, res, mode="cross", a=None, analysis_n=0):
     """Binned P(k) of the momentum perturbation (1 + delta) theta (sec. 4)
-    from an integrated full sample, halves as in density_spectrum."""
-    G, L = cfg["grid_n"], cfg["box_mpc"]
+    from an integrated full sample, halves and mesh as in density_spectrum."""
+    G, L = analysis_n or cfg["grid_n"], cfg["box_mpc"]
     m = cfg["species"][species_index]["m"]
     a = res["sched"]["a"][-1] if a is None else a
     mean_eps = background.mean_energy(m, a)

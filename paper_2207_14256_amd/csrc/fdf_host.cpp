@@ -198,8 +198,10 @@ Layout plan(const fdf_config& c) {
   L.parts_bytes = align_up((size_t)c.max_particles * particle_bytes(c) * copies +
                            (size_t)c.max_species * arrays_per_species(c) * copies * kAlign);
   size_t off = 0;
-  L.twiddle_d = off; off += align_up(G * 16);
-  L.twiddle_f = off; off += align_up(G * 8);
+  // twiddles of the G-point transform, then those of G/2, G/4, ... 8 (the
+  // analysis meshes of the spectra): the table of n points starts at entry 2 (G - n)
+  L.twiddle_d = off; off += align_up(2 * G * 16);
+  L.twiddle_f = off; off += align_up(2 * G * 8);
   L.seg = off; off += 2 * align_up((size_t)c.max_species * sizeof(Segment));
   L.bins = off; off += align_up(3 * kMaxBins * sizeof(double));
   L.scratch = off; off += L.scratch_bytes;
@@ -589,16 +591,22 @@ OutputArgs output_args(fdf_ctx* c, const SpeciesRec& s) {
   return o;
 }
 
+// First complex entry of the n-point table in the twiddle regions.
+size_t twiddle_entry(int G, int n) { return 2 * (size_t)(G - n); }
+
 void fill_twiddles(fdf_ctx* c) {
   const int G = c->cfg.grid_n;
-  std::vector<double> td(2 * G);
-  std::vector<float> tf(2 * G);
-  for (int m = 0; m < G; ++m) {
-    const long double ang = -2.0L * 3.141592653589793238462643383279502884L * m / G;
-    td[2 * m] = (double)cosl(ang);
-    td[2 * m + 1] = (double)sinl(ang);
-    tf[2 * m] = (float)cosl(ang);
-    tf[2 * m + 1] = (float)sinl(ang);
+  std::vector<double> td(4 * (size_t)G, 0.0);
+  std::vector<float> tf(4 * (size_t)G, 0.0f);
+  for (int n = G; n >= 8; n /= 2) {
+    const size_t base = 2 * twiddle_entry(G, n);
+    for (int m = 0; m < n; ++m) {
+      const long double ang = -2.0L * 3.141592653589793238462643383279502884L * m / n;
+      td[base + 2 * m] = (double)cosl(ang);
+      td[base + 2 * m + 1] = (double)sinl(ang);
+      tf[base + 2 * m] = (float)cosl(ang);
+      tf[base + 2 * m + 1] = (float)sinl(ang);
+    }
   }
   (void)hipMemcpy(c->ws + c->lay.twiddle_d, td.data(), td.size() * 8, hipMemcpyHostToDevice);
   (void)hipMemcpy(c->ws + c->lay.twiddle_f, tf.data(), tf.size() * 4, hipMemcpyHostToDevice);
@@ -1124,14 +1132,17 @@ int fdf_weights(fdf_ctx* c, int32_t sid, double* d_w) {
 // Theta = sum_a i k_a J_a with J the deposit of w q: the three axes are
 // deposited and transformed one after the other and summed in Fourier space.
 static int power_spectrum(fdf_ctx* c, const int32_t* sp, int32_t ns, int32_t nbins, int32_t mode,
-                          bool momentum, double* hk, double* hp, double* hn) {
+                          bool momentum, int32_t analysis_n, double* hk, double* hp, double* hn) {
   if (!c || !sp || ns < 1 || !hk || !hp || !hn) return FDF_ERR_ARG;
   if (!needs_ws(c)) return fail(c, FDF_ERR_WORKSPACE, "no workspace attached");
   if (nbins < 1 || nbins > kMaxBins) return fail(c, FDF_ERR_ARG, "n_bins must be in [1, 256]");
   if (mode != FDF_PK_CROSS && mode != FDF_PK_AUTO) return fail(c, FDF_ERR_ARG, "unknown mode");
   for (int i = 0; i < ns; ++i)
     if (sp[i] < 0 || sp[i] >= (int)c->species.size()) return fail(c, FDF_ERR_ARG, "bad species id");
-  const int G = c->cfg.grid_n;
+  const int Gm = c->cfg.grid_n;
+  if (analysis_n != 0 && (!is_pow2(analysis_n) || analysis_n < 8 || analysis_n > Gm))
+    return fail(c, FDF_ERR_ARG, "analysis_n must be 0 or a power of two in [8, grid_n]");
+  const int G = analysis_n ? analysis_n : Gm;
   const bool f64 = c->cfg.precision == FDF_PREC_FP64;
   const size_t rb = f64 ? 8 : 4, cells = (size_t)G * G * G;
   const double a = c->a[c->step_index];
@@ -1152,7 +1163,8 @@ static int power_spectrum(fdf_ctx* c, const int32_t* sp, int32_t ns, int32_t nbi
   pk.grid_a = dens;
   pk.grid_b = dens + cells * rb;
   pk.scratch = c->ws + c->lay.scratch;
-  pk.twiddle = c->ws + (f64 ? c->lay.twiddle_d : c->lay.twiddle_f);
+  pk.twiddle = c->ws + (f64 ? c->lay.twiddle_d + twiddle_entry(Gm, G) * 16
+                            : c->lay.twiddle_f + twiddle_entry(Gm, G) * 8);
   pk.bins = bins;
   pk.kf = 2.0 * kPi / c->cfg.box_mpc;
   pk.deriv_axis = -1;
@@ -1170,6 +1182,7 @@ static int power_spectrum(fdf_ctx* c, const int32_t* sp, int32_t ns, int32_t nbi
         o.norm[0] = g3 / ((double)ne * esum);
         o.norm[1] = no ? g3 / ((double)no * esum) : 0.0;
       }
+      o.G = G;
       o.dens[0] = dens;
       o.dens[1] = dens + cells * rb;
       o.quantity = axis;
@@ -1193,19 +1206,26 @@ static int power_spectrum(fdf_ctx* c, const int32_t* sp, int32_t ns, int32_t nbi
     hk[b] = cnt > 0 ? hb[nbins + b] / cnt : NAN;
     hp[b] = cnt > 0 ? hb[2 * nbins + b] / cnt : NAN;
   }
-  c->have_density = !momentum;   // the density buffers now hold the last momentum axis
+  c->have_density = !momentum && G == Gm;   // else the buffers hold another quantity or mesh
   c->density_auto = mode == FDF_PK_AUTO;
   return FDF_OK;
 }
 
 int fdf_density_power_spectrum(fdf_ctx* c, const int32_t* sp, int32_t ns, int32_t nbins, int32_t mode,
                                double* hk, double* hp, double* hn) {
-  return power_spectrum(c, sp, ns, nbins, mode, false, hk, hp, hn);
+  return power_spectrum(c, sp, ns, nbins, mode, false, 0, hk, hp, hn);
 }
 
 int fdf_momentum_power_spectrum(fdf_ctx* c, const int32_t* sp, int32_t ns, int32_t nbins, int32_t mode,
                                 double* hk, double* hp, double* hn) {
-  return power_spectrum(c, sp, ns, nbins, mode, true, hk, hp, hn);
+  return power_spectrum(c, sp, ns, nbins, mode, true, 0, hk, hp, hn);
+}
+
+int fdf_power_spectrum(fdf_ctx* c, const int32_t* sp, int32_t ns, int32_t nbins, int32_t mode,
+                       int32_t quantity, int32_t analysis_n, double* hk, double* hp, double* hn) {
+  if (quantity != FDF_PK_DENSITY && quantity != FDF_PK_MOMENTUM)
+    return c ? fail(c, FDF_ERR_ARG, "unknown quantity") : FDF_ERR_ARG;
+  return power_spectrum(c, sp, ns, nbins, mode, quantity == FDF_PK_MOMENTUM, analysis_n, hk, hp, hn);
 }
 
 int fdf_read_state(fdf_ctx* c, int32_t sid, double* hx, double* hq) {

@@ -18,6 +18,7 @@ PREC_FP64, PREC_FP32 = 0, 1
 MODEL_POISSON, MODEL_RADMAT = 0, 1
 EOMS = dict(separable=0, exact=1, canonical=2, sr_newton=3, simple_q=4, newtonian=5)   # fdf_config.eom
 PK_CROSS, PK_AUTO = 0, 1
+PK_DENSITY, PK_MOMENTUM = 0, 1
 SPECIES_PRE_IC = 1
 KERNEL_PUSH, KERNEL_SORT, KERNEL_GRID, KERNEL_INIT, KERNEL_OUTPUT = range(5)
 KERNEL_CLASSES = {"push": 0, "sort": 1, "grid": 2, "init": 3, "output": 4}
@@ -27,7 +28,7 @@ EXPORTS = [
     "fdf_workspace_size", "fdf_create", "fdf_attach_workspace", "fdf_reset", "fdf_destroy",
     "fdf_add_field", "fdf_set_field", "fdf_init_species", "fdf_set_species_state",
     "fdf_build_potential_grids", "fdf_step", "fdf_weights", "fdf_density_power_spectrum",
-    "fdf_momentum_power_spectrum",
+    "fdf_momentum_power_spectrum", "fdf_power_spectrum",
     "fdf_read_state", "fdf_read_grid", "fdf_read_field", "fdf_read_density",
     "fdf_read_schedule", "fdf_get_info", "fdf_sync", "fdf_timing_enable",
     "fdf_read_timing", "fdf_timing_reset", "fdf_status_string", "fdf_last_error",
@@ -101,6 +102,7 @@ def load():
         "fdf_weights": [P, I32, P],
         "fdf_density_power_spectrum": [P, ctypes.POINTER(I32), I32, I32, I32, PD, PD, PD],
         "fdf_momentum_power_spectrum": [P, ctypes.POINTER(I32), I32, I32, I32, PD, PD, PD],
+        "fdf_power_spectrum": [P, ctypes.POINTER(I32), I32, I32, I32, I32, I32, PD, PD, PD],
         "fdf_read_state": [P, I32, PD, PD],
         "fdf_read_grid": [P, I32, I32, PD],
         "fdf_read_field": [P, I32, PD],
@@ -269,17 +271,25 @@ class Context:
                     "fdf_weights")
         return out
 
-    def power_spectrum(self, species, n_bins, mode="cross", quantity="density"):
+    def power_spectrum(self, species, n_bins, mode="cross", quantity="density", analysis_n=0):
         """(mean k, P(k), modes) of the energy density ('density') or of the
-        momentum perturbation (1 + delta) theta ('momentum')."""
+        momentum perturbation (1 + delta) theta ('momentum'), on the mesh G or
+        an analysis mesh of analysis_n points per side."""
         sp = np.asarray(species if hasattr(species, "__len__") else [species], dtype=np.int32)
         k = np.empty(n_bins)
         p = np.empty(n_bins)
         nm = np.empty(n_bins)
-        name = {"density": "fdf_density_power_spectrum", "momentum": "fdf_momentum_power_spectrum"}[quantity]
-        self._check(getattr(self.lib, name)(
-            self.ctx, sp.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), len(sp), int(n_bins),
-            PK_AUTO if mode == "auto" else PK_CROSS, _dptr(k), _dptr(p), _dptr(nm)), name)
+        spp = sp.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        md = PK_AUTO if mode == "auto" else PK_CROSS
+        if analysis_n:
+            qn = {"density": PK_DENSITY, "momentum": PK_MOMENTUM}[quantity]
+            self._check(self.lib.fdf_power_spectrum(self.ctx, spp, len(sp), int(n_bins), md, qn,
+                                                    int(analysis_n), _dptr(k), _dptr(p), _dptr(nm)),
+                        "fdf_power_spectrum")
+        else:
+            name = {"density": "fdf_density_power_spectrum", "momentum": "fdf_momentum_power_spectrum"}[quantity]
+            self._check(getattr(self.lib, name)(self.ctx, spp, len(sp), int(n_bins), md,
+                                                _dptr(k), _dptr(p), _dptr(nm)), name)
         return k, p, nm
 
     # ------------------------------------------------------------- read-back --

@@ -115,3 +115,22 @@ def test_calls_without_workspace_fail_cleanly(lib):
     assert lib.fdf_status_string(-5) == b"capacity exceeded"
     assert lib.fdf_attach_workspace(ctx, ctypes.c_void_p(12345), 10) == -3
     lib.fdf_destroy(ctx)
+
+
+def test_truncate_field_is_spectral_restriction():
+    """A band-limited fine field and its truncation describe the same function:
+    the coarse field equals the fine one sampled on the coarse mesh."""
+    from paper_2207_14256_amd.convergence import truncate_field
+    rng = np.random.default_rng(4)
+    G, Gc = 32, 8
+    real = rng.normal(size=(G, G, G))
+    dk = np.fft.rfftn(real) / G ** 3
+    n = np.arange(G)
+    s = np.where(n < G // 2, n, n - G)
+    keep = (np.abs(s)[:, None, None] < Gc // 2) & (np.abs(s)[None, :, None] < Gc // 2) \
+        & (np.arange(G // 2 + 1)[None, None, :] < Gc // 2)
+    dk = np.where(keep, dk, 0)
+    fine = np.fft.irfftn(dk, s=(G, G, G), axes=(0, 1, 2)) * G ** 3
+    coarse = np.fft.irfftn(truncate_field(dk, Gc), s=(Gc, Gc, Gc), axes=(0, 1, 2)) * Gc ** 3
+    step = G // Gc
+    assert np.allclose(coarse, fine[::step, ::step, ::step], rtol=0, atol=1e-12 * np.abs(fine).max())
