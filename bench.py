@@ -7,7 +7,8 @@ C2R FFT), the full leapfrog schedule (one push launch per step), delta-f
 weights, and the CIC-deposit + binned cross power spectrum.  The default
 workload is the precision form: 512^3 neutrinos (m = 0.1 eV) on a 512^3
 bfloat16 gradient mesh in a 1 Gpc box, 1000 steps from z = 1e9 to z = 0,
-FP32 push with 32-bit fixed-point positions and Kahan-compensated momenta.
+FP32 push with 32-bit fixed-point positions and momenta kept as the initial
+momentum plus the accumulated kicks.
 
 Printed: one JSON line with particle-updates/s over the whole job, the push
 kernel's achieved HBM bandwidth against the 8 TB/s peak (from HIP events on
@@ -37,13 +38,13 @@ def log(msg):
 
 def bytes_per_launch(cfg, n_particles, drift):
     """Algorithmic HBM bytes of one push launch: state read + write per
-    particle, plus one read of the gradient mesh.  FP32 form: read x, q, c, q0
-    (48 B), write x, q, c (36 B; 24 B without the drift); FP64 form: read x, q,
+    particle, plus one read of the gradient mesh.  FP32 form: read x, q0, dq
+    (36 B), write x, dq (24 B; 12 B without the drift); FP64 form: read x, q,
     q0 (72 B), write x, q (48 B; 24 B without the drift)."""
     G = cfg["grid_n"]
     nslot = 8 if cfg.get("slip_amp", 0.0) else 4
     if cfg["precision"] == "fp32":
-        per = 48 + (36 if drift else 24)
+        per = 36 + (24 if drift else 12)
         grid = G ** 3 * nslot * 2
     else:
         per = 72 + (48 if drift else 24)
@@ -247,7 +248,7 @@ def main():
                             args.workload, cfg["species"][0]["n_side"], cfg["species"][0]["m"],
                             cfg["grid_n"], "bf16" if cfg["precision"] == "fp32" else "f64",
                             cfg["box_mpc"], cfg["n_steps"], cfg["z_begin"], cfg["z_end"],
-                            "FP32 push, uint32 fixed-point x, Kahan q" if cfg["precision"] == "fp32"
+                            "FP32 push, uint32 fixed-point x, q = q0 + dq" if cfg["precision"] == "fp32"
                             else "FP64 push"),
             "particles": main_leg["n_particles"], "grid_n": cfg["grid_n"],
             "push_steps_per_job": cfg["n_steps"],

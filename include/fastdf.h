@@ -57,8 +57,10 @@ typedef enum fdf_status {
 /* Arithmetic of the push (sec. 3.3 integrator):
  *   FP64: positions, momenta and grids in binary64.
  *   FP32: positions as 32-bit fixed-point fractions of the box (periodic wrap
- *         is the integer overflow), momenta in binary32 with Kahan-compensated
- *         kicks, gradient grids in bfloat16; schedule and weights in binary64. */
+ *         is the integer overflow), momenta as the binary32 initial momentum
+ *         q0 plus the binary32 sum of the kicks dq (so rounding scales with
+ *         dq, not q), gradient grids in bfloat16; schedule and weights in
+ *         binary64. */
 enum { FDF_PREC_FP64 = 0, FDF_PREC_FP32 = 1 };
 
 /* Linear potentials (see fdf_config.potential_model):
@@ -171,6 +173,10 @@ typedef struct fdf_tuning {
   int32_t use_graph;             /* 1: fdf_step captures its launch sequence into
                                     a hipGraph (once per distinct starting state)
                                     and replays it; per-kernel timing is then off */
+  int32_t sort_predict;          /* 1: order by the positions extrapolated to the
+                                    middle of the interval until the next re-sort
+                                    (halves the spread of neighbours); 0: by the
+                                    current positions */
 } fdf_tuning;
 
 /* ---- lifetime -------------------------------------------------------------- */

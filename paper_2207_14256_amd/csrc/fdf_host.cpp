@@ -183,8 +183,8 @@ int grid_slot(const fdf_config& c, int quantity) {
 }
 size_t real_bytes(const fdf_config& c) { return c.precision == FDF_PREC_FP64 ? 8 : 4; }
 size_t slot_bytes(const fdf_config& c) { return c.precision == FDF_PREC_FP64 ? 8 : 2; }
-size_t particle_bytes(const fdf_config& c) { return c.precision == FDF_PREC_FP64 ? 76 : 52; }
-int arrays_per_species(const fdf_config& c) { return c.precision == FDF_PREC_FP64 ? 10 : 13; }
+size_t particle_bytes(const fdf_config& c) { return c.precision == FDF_PREC_FP64 ? 76 : 40; }
+int arrays_per_species(const fdf_config& c) { return c.precision == FDF_PREC_FP64 ? 10 : 10; }
 
 Layout plan(const fdf_config& c) {
   Layout L{};
@@ -324,6 +324,7 @@ struct fdf_ctx {
   float sort_cells = 0;     // adaptive cadence threshold in cells (0: fixed cadence)
   int persistent = 0;       // push grid size when > 0 (a multiple of 8)
   bool use_graph = false;   // capture step sequences into hipGraphs
+  bool sort_predict = true; // sort keys from positions extrapolated to mid-interval
   hipStream_t cap_stream = nullptr;   // private stream used only for graph capture
   hipStream_t launch_stream = nullptr;  // stream kernels are enqueued on right now
   std::vector<GraphRec> graphs;       // captured step sequences
@@ -415,10 +416,9 @@ bool carve_species(fdf_ctx* c, Segment& s, int64_t n) {
       if (!s.xd[d] || !s.qd[d] || !s.q0d[d]) return false;
     } else {
       s.xu[d] = (uint32_t*)take(n * 4);
-      s.qf[d] = (float*)take(n * 4);
-      s.cf[d] = (float*)take(n * 4);
       s.q0f[d] = (float*)take(n * 4);
-      if (!s.xu[d] || !s.qf[d] || !s.cf[d] || !s.q0f[d]) return false;
+      s.dqf[d] = (float*)take(n * 4);
+      if (!s.xu[d] || !s.q0f[d] || !s.dqf[d]) return false;
     }
   }
   s.id = (uint32_t*)take(n * 4);
@@ -543,8 +543,9 @@ double typical_drift_cells(fdf_ctx* c, double dt, double a) {
   return std::fabs(dt) * v * c->cfg.grid_n / c->cfg.box_mpc;
 }
 
-// Spatial re-sort of every species into its other buffer copy.
-int sort_species(fdf_ctx* c) {
+// Spatial re-sort of every species into its other buffer copy, ordered by
+// the positions extrapolated by predict_tau at scale factor a_pred.
+int sort_species(fdf_ctx* c, double predict_tau, double a_pred) {
   const int tiles = sort_tiles_of(c);
   std::pair<hipEvent_t, hipEvent_t> ev;
   timing_begin(c, FDF_KERNEL_SORT, &ev);
@@ -552,6 +553,8 @@ int sort_species(fdf_ctx* c) {
     SortArgs a{};
     a.seg = s.seg[s.cur];
     a.dst = s.seg[s.cur ^ 1];
+    a.predict_tau = predict_tau;
+    a.ma = s.m * a_pred;
     a.fp64 = c->cfg.precision == FDF_PREC_FP64;
     a.grid_n = c->cfg.grid_n;
     a.cell_shift = 32 - ilog2(c->cfg.grid_n);
@@ -876,9 +879,8 @@ int fdf_set_species_state(fdf_ctx* c, int32_t field_id, double m, int64_t n, con
     } else {
       for (int64_t i = 0; i < n; ++i) { uu[i] = xu[3 * i + d]; ff[i] = q[3 * i + d]; }
       rc = put(s.xu[d], uu.data(), n * 4);
-      if (!rc) rc = put(s.qf[d], ff.data(), n * 4);
       if (!rc) rc = put(s.q0f[d], ff.data(), n * 4);
-      if (!rc) rc = put(s.cf[d], zero.data(), n * 4);
+      if (!rc) rc = put(s.dqf[d], zero.data(), n * 4);
     }
   }
   if (!rc) rc = put(s.id, ids.data(), n * 4);
@@ -985,8 +987,31 @@ int enqueue_steps(fdf_ctx* c, int32_t n) {
         do_sort = t % sort_every == 0;
       }
       if (do_sort) {
-        rc = sort_species(c);
-        if (!rc && !c->sorted_once) rc = sort_species(c);   // second pass orders cells in buckets
+        // the interval until the next re-sort (as the cadence will decide
+        // it) and the conformal time and scale factor at its middle
+        double span = 0.0, cells = 0.0;
+        int steps = 0;
+        std::vector<std::pair<double, double>> iv;   // (drift, a) of the steps in the interval
+        for (int u = t; ; u += n > 0 ? 1 : -1) {
+          const bool fwd = n > 0;
+          if (fwd ? u >= c->cfg.n_steps : u <= 0) break;
+          const double dr = fwd ? c->drift[u] : -c->drift[u - 1];
+          const double ah = fwd ? c->a_half[u] : c->a_half[u - 1];
+          iv.push_back({dr, ah});
+          span += dr;
+          cells += typical_drift_cells(c, dr, ah);
+          ++steps;
+          if (c->sort_cells > 0 ? cells >= c->sort_cells : steps >= std::max(sort_every, 1)) break;
+        }
+        double half = 0.0, a_mid = c->a[t];
+        for (const auto& e : iv) {
+          if (std::fabs(half + e.first) > 0.5 * std::fabs(span)) { a_mid = e.second; break; }
+          half += e.first;
+          a_mid = e.second;
+        }
+        const double tau_pred = c->sort_predict ? 0.5 * span : 0.0;
+        rc = sort_species(c, tau_pred, a_mid);
+        if (!rc && !c->sorted_once) rc = sort_species(c, tau_pred, a_mid);   // second pass orders cells in buckets
         if (rc) return rc;
         c->sorted_once = true;
         c->drift_cells = 0;
@@ -1259,9 +1284,9 @@ int fdf_read_state(fdf_ctx* c, int32_t sid, double* hx, double* hq) {
         rc = hip_check(c, hipMemcpy(bd.data(), g.qd[d], n * 8, hipMemcpyDeviceToHost), "read q");
         for (int64_t i = 0; i < n && !rc; ++i) hq[3 * (size_t)id[i] + d] = bd[i];
       } else {
-        rc = hip_check(c, hipMemcpy(bf.data(), g.qf[d], n * 4, hipMemcpyDeviceToHost), "read q");
-        if (!rc) rc = hip_check(c, hipMemcpy(bc.data(), g.cf[d], n * 4, hipMemcpyDeviceToHost), "read c");
-        for (int64_t i = 0; i < n && !rc; ++i) hq[3 * (size_t)id[i] + d] = (double)bf[i] - (double)bc[i];
+        rc = hip_check(c, hipMemcpy(bf.data(), g.q0f[d], n * 4, hipMemcpyDeviceToHost), "read q0");
+        if (!rc) rc = hip_check(c, hipMemcpy(bc.data(), g.dqf[d], n * 4, hipMemcpyDeviceToHost), "read dq");
+        for (int64_t i = 0; i < n && !rc; ++i) hq[3 * (size_t)id[i] + d] = (double)bf[i] + (double)bc[i];
       }
     }
     if (rc) return rc;
@@ -1380,6 +1405,7 @@ int fdf_get_tuning(const fdf_ctx* c, fdf_tuning* t) {
   t->sort_cells = c->sort_cells;
   t->persistent_blocks = c->persistent;
   t->use_graph = c->use_graph ? 1 : 0;
+  t->sort_predict = c->sort_predict ? 1 : 0;
   return FDF_OK;
 }
 
@@ -1397,6 +1423,7 @@ int fdf_set_tuning(fdf_ctx* c, const fdf_tuning* t) {
   if (t->persistent_blocks < 0 || t->persistent_blocks % 8 != 0 || t->persistent_blocks > (1 << 20))
     return fail(c, FDF_ERR_ARG, "persistent_blocks must be 0 or a positive multiple of 8");
   if (t->use_graph != 0 && t->use_graph != 1) return fail(c, FDF_ERR_ARG, "use_graph must be 0 or 1");
+  if (t->sort_predict != 0 && t->sort_predict != 1) return fail(c, FDF_ERR_ARG, "sort_predict must be 0 or 1");
   if (p != c->ppt) c->seg_dirty = true;   // chunk boundaries depend on the block size
   clear_graphs(c);
   c->persistent = t->persistent_blocks;
@@ -1405,6 +1432,7 @@ int fdf_set_tuning(fdf_ctx* c, const fdf_tuning* t) {
   c->sort_tiles = t->sort_tiles;
   c->sort_every = t->sort_every;
   c->sort_cells = t->sort_cells;
+  c->sort_predict = t->sort_predict != 0;
   return FDF_OK;
 }
 

@@ -78,9 +78,8 @@ __global__ void k_sample(SampleArgs a) {
     } else {
       for (int d = 0; d < 3; ++d) {
         a.seg.xu[d][i] = xu[d];
-        a.seg.qf[d][i] = qf[d];
-        a.seg.cf[d][i] = 0.0f;
         a.seg.q0f[d][i] = qf[d];
+        a.seg.dqf[d][i] = 0.0f;
       }
     }
     a.seg.id[i] = (uint32_t)i;
@@ -102,7 +101,10 @@ __global__ void k_pre_ic(PreIcArgs a) {
     double x[3], q[3];
     for (int d = 0; d < 3; ++d) {
       if (a.fp64) { x[d] = a.seg.xd[d][i]; q[d] = a.seg.qd[d][i]; }
-      else { x[d] = (double)a.seg.xu[d][i] * (a.box * 0x1p-32); q[d] = (double)a.seg.qf[d][i]; }
+      else {
+        x[d] = (double)a.seg.xu[d][i] * (a.box * 0x1p-32);
+        q[d] = (double)a.seg.q0f[d][i] + (double)a.seg.dqf[d][i];
+      }
     }
     int i0[3], i1[3];
     double t[3];
@@ -124,7 +126,7 @@ __global__ void k_pre_ic(PreIcArgs a) {
     for (int d = 0; d < 3; ++d) {
       const float qn = (float)(q[d] * (1.0 - 0.5 * acc[3]) - (eps * a.tau / 6.0) * acc[d]);
       if (a.fp64) { a.seg.qd[d][i] = qn; a.seg.q0d[d][i] = qn; }
-      else { a.seg.qf[d][i] = qn; a.seg.q0f[d][i] = qn; a.seg.cf[d][i] = 0.0f; }
+      else { a.seg.q0f[d][i] = qn; a.seg.dqf[d][i] = 0.0f; }
     }
   }
 }

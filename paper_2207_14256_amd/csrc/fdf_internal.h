@@ -66,11 +66,11 @@ struct PkArgs {
 
 // Segment of the batched particle state: one species.
 struct Segment {
-  // FP32 form: positions as uint32 fixed point, q and Kahan residual c in f32
+  // FP32 form: positions as uint32 fixed point; the momentum is q0 + dq with
+  // q0 the momentum at the start (binary32) and dq the accumulated kicks
   uint32_t* xu[3];
-  float* qf[3];
-  float* cf[3];
   float* q0f[3];
+  float* dqf[3];
   // FP64 form
   double* xd[3];
   double* qd[3];
@@ -110,6 +110,8 @@ struct PushArgs {
 struct SortArgs {
   Segment seg;             // source copy
   Segment dst;             // destination copy
+  double predict_tau;      // order by x + v * predict_tau (conformal time, Mpc; 0: by x)
+  double ma;               // m a for the velocity v = q / sqrt(q^2 + (m a)^2)
   int32_t fp64;
   int32_t grid_n;          // G
   int32_t cell_shift;      // 32 - log2(G): cell index of a fixed-point position

@@ -12,10 +12,10 @@ __device__ __forceinline__ void momenta(const OutputArgs& a, int64_t i, uint32_t
   if (a.fp64) {
     for (int d = 0; d < 3; ++d) { q[d] = a.seg.qd[d][i]; p[d] = a.seg.q0d[d][i]; }
   } else {
-    // Kahan pair: the accumulated momentum is q - c
+    // q = q0 + dq, exact in binary64
     for (int d = 0; d < 3; ++d) {
-      q[d] = (double)a.seg.qf[d][i] - (double)a.seg.cf[d][i];
       p[d] = (double)a.seg.q0f[d][i];
+      q[d] = p[d] + (double)a.seg.dqf[d][i];
     }
   }
   if (a.pre_ic) {  // q0 carries the transformed momentum; p is the raw sample

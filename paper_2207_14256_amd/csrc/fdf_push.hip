@@ -14,8 +14,9 @@
 //
 // FP32 form: x is a uint32 fixed-point fraction of the box per axis, so the
 // periodic wrap is integer overflow and the cell index is the top log2(G)
-// bits; q is binary32 with a Kahan residual c (true momentum q - c); grids
-// are bfloat16 with 8 slots = one 16-byte load per CIC corner.
+// bits; the momentum is q = q0 + dq with the accumulated kicks dq in binary32
+// (the kicks only ever add to dq, whose rounding is relative to dq, not q);
+// grids are bfloat16 with 8 slots = one 16-byte load per CIC corner.
 // FP64 form: everything binary64; 8 slots = four 16-byte loads per corner.
 //
 // Blocks take contiguous chunks of one species, in an XCD-aware order.
@@ -31,15 +32,27 @@ using namespace push_detail;
 
 // Gather of the slots (8-slot: gpsi[3], gphi[3], phidot; 4-slot: gpsi[3], phidot
 // with phi = psi) from a bfloat16 grid.
-template <int NSLOT, int NPT>
-__device__ __forceinline__ void gather_bf16(const void* grid, const size_t* cell, const float* w,
+// OFF32: the mesh spans less than 4 GiB, so a corner is addressed as a
+// uniform base plus a 32-bit byte offset (one VGPR per corner instead of a
+// 64-bit address).
+template <typename V, bool OFF32>
+__device__ __forceinline__ V load_cell(const void* grid, uint32_t cell) {
+  if constexpr (OFF32) {
+    const char FDF_GLOBAL* b = (const char FDF_GLOBAL*)grid;
+    return *(const FDF_GLOBAL V*)(b + cell * (uint32_t)sizeof(V));
+  } else {
+    return ((const FDF_GLOBAL V*)grid)[(size_t)cell];
+  }
+}
+
+template <int NSLOT, int NPT, bool OFF32>
+__device__ __forceinline__ void gather_bf16(const void* grid, const uint32_t* cell, const float* w,
                                             float* g /* 7, accumulated */) {
 #pragma clang fp contract(off)
   if constexpr (NSLOT == 8) {
-    const uint4* gp = (const uint4*)grid;
     uint4 v[NPT];
 #pragma unroll
-    for (int c = 0; c < NPT; ++c) v[c] = gp[cell[c]];
+    for (int c = 0; c < NPT; ++c) v[c] = load_cell<uint4, OFF32>(grid, cell[c]);
 #pragma unroll
     for (int c = 0; c < NPT; ++c) {
       g[0] = fmaf(w[c], bf16_lo(v[c].x), g[0]); g[1] = fmaf(w[c], bf16_hi(v[c].x), g[1]);
@@ -48,10 +61,9 @@ __device__ __forceinline__ void gather_bf16(const void* grid, const size_t* cell
       g[6] = fmaf(w[c], bf16_lo(v[c].w), g[6]);
     }
   } else {
-    const uint2* gp = (const uint2*)grid;
     uint2 v[NPT];
 #pragma unroll
-    for (int c = 0; c < NPT; ++c) v[c] = gp[cell[c]];
+    for (int c = 0; c < NPT; ++c) v[c] = load_cell<uint2, OFF32>(grid, cell[c]);
 #pragma unroll
     for (int c = 0; c < NPT; ++c) {
       g[0] = fmaf(w[c], bf16_lo(v[c].x), g[0]); g[1] = fmaf(w[c], bf16_hi(v[c].x), g[1]);
@@ -62,13 +74,13 @@ __device__ __forceinline__ void gather_bf16(const void* grid, const size_t* cell
 
 // Gather over a whole stencil: CIC in one batch of 8 loads, TSC in three
 // batches of 9 (one x-plane of the 27 points each).
-template <int NSLOT, bool TSC>
-__device__ __forceinline__ void gather_stencil_bf16(const void* grid, const size_t* cell, const float* w, float* g) {
+template <int NSLOT, bool TSC, bool OFF32>
+__device__ __forceinline__ void gather_stencil_bf16(const void* grid, const uint32_t* cell, const float* w, float* g) {
   if constexpr (TSC) {
 #pragma unroll
-    for (int b = 0; b < 3; ++b) gather_bf16<NSLOT, 9>(grid, cell + 9 * b, w + 9 * b, g);
+    for (int b = 0; b < 3; ++b) gather_bf16<NSLOT, 9, OFF32>(grid, cell + 9 * b, w + 9 * b, g);
   } else {
-    gather_bf16<NSLOT, 8>(grid, cell, w, g);
+    gather_bf16<NSLOT, 8, OFF32>(grid, cell, w, g);
   }
 }
 
@@ -76,7 +88,7 @@ __device__ __forceinline__ void gather_stencil_bf16(const void* grid, const size
 // (explicit fmaf, no contraction) so that the unrolled copies of the loop are
 // instruction-identical: a particle gets bit-identical results in whichever
 // slot of whichever block it lands after a re-sort.
-template <int NSLOT, int PPT, bool BLEND, bool TSC>
+template <int NSLOT, int PPT, bool BLEND, bool TSC, bool OFF32>
 __device__ __forceinline__ void push_chunk_f32(const PushArgs& a, int64_t chunk) {
 #pragma clang fp contract(off)
   constexpr int NP = Stencil<TSC>::N;
@@ -92,26 +104,33 @@ __device__ __forceinline__ void push_chunk_f32(const PushArgs& a, int64_t chunk)
   const float mah = (float)(sg.m * a.a_drift);
   const float ma2 = ma * ma, mah2 = mah * mah;
   const float dscale = (float)(a.drift * 4294967296.0 / a.box);
-  const size_t G = (size_t)a.G;
+  const uint32_t G = (uint32_t)a.G;
   const void* gridA = (BLEND && a.grid_sel) ? sg.grid2 : sg.grid;
   const void* gridB = (BLEND && a.grid_sel) ? sg.grid : sg.grid2;
   const float tb = (float)a.blend_t, ta = 1.0f - tb;
+  // chunk-relative arrays: a uniform base and a 32-bit lane index
+  const int64_t c0 = first - threadIdx.x;
+  const int64_t left = n - c0;
+  uint32_t* X[3];
+  const float* Q0[3];
+  float* DQ[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) { X[d] = sg.xu[d] + c0; Q0[d] = sg.q0f[d] + c0; DQ[d] = sg.dqf[d] + c0; }
 
 #pragma unroll
   for (int p = 0; p < PPT; ++p) {
-    const int64_t i = first + (int64_t)p * kBlock;
-    if (i >= n) break;
+    const uint32_t i = threadIdx.x + (uint32_t)(p * kBlock);
+    if ((int64_t)i >= left) break;
     uint32_t xu[3];
-    float q[3], c[3], q0[3];
+    float dq[3], q0[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      xu[d] = ldnt(&sg.xu[d][i]);
-      q[d] = ldnt(&sg.qf[d][i]);
-      c[d] = ldnt(&sg.cf[d][i]);
-      q0[d] = ldnt(&sg.q0f[d][i]);
+      xu[d] = ldnt(&X[d][i]);
+      q0[d] = ldnt(&Q0[d][i]);
+      dq[d] = ldnt(&DQ[d][i]);
     }
     // interpolation stencil from the fixed-point position
-    size_t cell[NP];
+    uint32_t cell[NP];
     float w[NP];
     stencil_u32<TSC>(xu, shift, gmask, finv, G, cell, w);
     float g[7] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
@@ -119,10 +138,10 @@ __device__ __forceinline__ void push_chunk_f32(const PushArgs& a, int64_t chunk)
       float wa[NP], wb[NP];
 #pragma unroll
       for (int cc = 0; cc < NP; ++cc) { wa[cc] = ta * w[cc]; wb[cc] = tb * w[cc]; }
-      gather_stencil_bf16<NSLOT, TSC>(gridA, cell, wa, g);
-      gather_stencil_bf16<NSLOT, TSC>(gridB, cell, wb, g);
+      gather_stencil_bf16<NSLOT, TSC, OFF32>(gridA, cell, wa, g);
+      gather_stencil_bf16<NSLOT, TSC, OFF32>(gridB, cell, wb, g);
     } else {
-      gather_stencil_bf16<NSLOT, TSC>(gridA, cell, w, g);
+      gather_stencil_bf16<NSLOT, TSC, OFF32>(gridA, cell, w, g);
     }
     if (NSLOT == 4) { g[3] = g[0]; g[4] = g[1]; g[5] = g[2]; }
     // separable force of eq. releq_approx
@@ -135,61 +154,70 @@ __device__ __forceinline__ void push_chunk_f32(const PushArgs& a, int64_t chunk)
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       const float F = fmaf(q0[d], qg, fmaf(-cphi, g[3 + d], -(e0 * g[d])));
-      // Kahan-compensated q += kick * F
-      const float y = fmaf(kick, F, -c[d]);
-      const float tq = q[d] + y;
-      c[d] = (tq - q[d]) - y;
-      q[d] = tq;
+      dq[d] = fmaf(kick, F, dq[d]);
     }
     if (a.do_drift) {
+      float q[3];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) q[d] = q0[d] + dq[d];
       const float qq = fmaf(q[0], q[0], fmaf(q[1], q[1], q[2] * q[2]));
       const float ie = 1.0f / sqrtf(qq + mah2);
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         const int disp = __float2int_rn(dscale * (q[d] * ie));
-        stnt(xu[d] + (uint32_t)disp, &sg.xu[d][i]);
+        stnt(xu[d] + (uint32_t)disp, &X[d][i]);
       }
     }
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      stnt(q[d], &sg.qf[d][i]);
-      stnt(c[d], &sg.cf[d][i]);
-    }
+    for (int d = 0; d < 3; ++d) stnt(dq[d], &DQ[d][i]);
   }
 }
 
-template <int NSLOT, int NPT>
-__device__ __forceinline__ void gather_f64(const void* grid, const size_t* cell, const double* w,
+// 16-byte piece j of the NSLOT-double cell `cell`.
+template <int NSLOT, bool OFF32>
+__device__ __forceinline__ double2 load_piece_f64(const void* grid, uint32_t cell, int j) {
+  if constexpr (OFF32) {
+    const char FDF_GLOBAL* b = (const char FDF_GLOBAL*)grid;
+    return *(const FDF_GLOBAL double2*)(b + cell * (uint32_t)(8 * NSLOT) + 16 * j);
+  } else {
+    return ((const FDF_GLOBAL double2*)grid)[(size_t)cell * (NSLOT / 2) + j];
+  }
+}
+
+template <int NSLOT, int NPT, bool OFF32>
+__device__ __forceinline__ void gather_f64(const void* grid, const uint32_t* cell, const double* w,
                                            double* g /* 7, accumulated */) {
 #pragma clang fp contract(off)
-  const double2* gp = (const double2*)grid;
 #pragma unroll
   for (int c = 0; c < NPT; ++c) {
     if constexpr (NSLOT == 8) {
-      const double2 v0 = gp[4 * cell[c]], v1 = gp[4 * cell[c] + 1];
-      const double2 v2 = gp[4 * cell[c] + 2], v3 = gp[4 * cell[c] + 3];
+      const double2 v0 = load_piece_f64<8, OFF32>(grid, cell[c], 0);
+      const double2 v1 = load_piece_f64<8, OFF32>(grid, cell[c], 1);
+      const double2 v2 = load_piece_f64<8, OFF32>(grid, cell[c], 2);
+      const double2 v3 = load_piece_f64<8, OFF32>(grid, cell[c], 3);
       g[0] = fma(w[c], v0.x, g[0]); g[1] = fma(w[c], v0.y, g[1]); g[2] = fma(w[c], v1.x, g[2]);
       g[3] = fma(w[c], v1.y, g[3]); g[4] = fma(w[c], v2.x, g[4]); g[5] = fma(w[c], v2.y, g[5]);
       g[6] = fma(w[c], v3.x, g[6]);
     } else {
-      const double2 v0 = gp[2 * cell[c]], v1 = gp[2 * cell[c] + 1];
+      const double2 v0 = load_piece_f64<4, OFF32>(grid, cell[c], 0);
+      const double2 v1 = load_piece_f64<4, OFF32>(grid, cell[c], 1);
       g[0] = fma(w[c], v0.x, g[0]); g[1] = fma(w[c], v0.y, g[1]); g[2] = fma(w[c], v1.x, g[2]);
       g[6] = fma(w[c], v1.y, g[6]);
     }
   }
 }
 
-template <int NSLOT, bool TSC>
-__device__ __forceinline__ void gather_stencil_f64(const void* grid, const size_t* cell, const double* w, double* g) {
+template <int NSLOT, bool TSC, bool OFF32>
+__device__ __forceinline__ void gather_stencil_f64(const void* grid, const uint32_t* cell, const double* w, double* g) {
   if constexpr (TSC) {
 #pragma unroll
-    for (int b = 0; b < 3; ++b) gather_f64<NSLOT, 9>(grid, cell + 9 * b, w + 9 * b, g);
+    for (int b = 0; b < 3; ++b) gather_f64<NSLOT, 9, OFF32>(grid, cell + 9 * b, w + 9 * b, g);
   } else {
-    gather_f64<NSLOT, 8>(grid, cell, w, g);
+    gather_f64<NSLOT, 8, OFF32>(grid, cell, w, g);
   }
 }
 
-template <int NSLOT, int PPT, bool BLEND, bool TSC>
+template <int NSLOT, int PPT, bool BLEND, bool TSC, bool OFF32>
 __device__ __forceinline__ void push_chunk_f64(const PushArgs& a, int64_t chunk) {
 #pragma clang fp contract(off)
   constexpr int NP = Stencil<TSC>::N;
@@ -201,23 +229,31 @@ __device__ __forceinline__ void push_chunk_f64(const PushArgs& a, int64_t chunk)
   const double ginv = (double)a.G / a.box;
   const double ma = sg.m * a.a_kick;
   const double mah = sg.m * a.a_drift;
-  const size_t G = (size_t)a.G;
+  const uint32_t G = (uint32_t)a.G;
   const void* gridA = (BLEND && a.grid_sel) ? sg.grid2 : sg.grid;
   const void* gridB = (BLEND && a.grid_sel) ? sg.grid : sg.grid2;
   const double tb = a.blend_t, ta = 1.0 - tb;
+  // chunk-relative arrays: a uniform base and a 32-bit lane index
+  const int64_t c0 = first - threadIdx.x;
+  const int64_t left = n - c0;
+  double* X[3];
+  double* Q[3];
+  const double* Q0[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) { X[d] = sg.xd[d] + c0; Q[d] = sg.qd[d] + c0; Q0[d] = sg.q0d[d] + c0; }
 
 #pragma unroll
   for (int p = 0; p < PPT; ++p) {
-    const int64_t i = first + (int64_t)p * kBlock;
-    if (i >= n) break;
+    const uint32_t i = threadIdx.x + (uint32_t)(p * kBlock);
+    if ((int64_t)i >= left) break;
     double x[3], q[3], q0[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      x[d] = ldnt(&sg.xd[d][i]);
-      q[d] = ldnt(&sg.qd[d][i]);
-      q0[d] = ldnt(&sg.q0d[d][i]);
+      x[d] = ldnt(&X[d][i]);
+      q[d] = ldnt(&Q[d][i]);
+      q0[d] = ldnt(&Q0[d][i]);
     }
-    size_t cell[NP];
+    uint32_t cell[NP];
     double w[NP];
     stencil_f64<TSC>(x, ginv, gm, G, cell, w);
     double g[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -225,10 +261,10 @@ __device__ __forceinline__ void push_chunk_f64(const PushArgs& a, int64_t chunk)
       double wa[NP], wb[NP];
 #pragma unroll
       for (int cc = 0; cc < NP; ++cc) { wa[cc] = ta * w[cc]; wb[cc] = tb * w[cc]; }
-      gather_stencil_f64<NSLOT, TSC>(gridA, cell, wa, g);
-      gather_stencil_f64<NSLOT, TSC>(gridB, cell, wb, g);
+      gather_stencil_f64<NSLOT, TSC, OFF32>(gridA, cell, wa, g);
+      gather_stencil_f64<NSLOT, TSC, OFF32>(gridB, cell, wb, g);
     } else {
-      gather_stencil_f64<NSLOT, TSC>(gridA, cell, w, g);
+      gather_stencil_f64<NSLOT, TSC, OFF32>(gridA, cell, w, g);
     }
     if (NSLOT == 4) { g[3] = g[0]; g[4] = g[1]; g[5] = g[2]; }
     const double q0sq = fma(q0[0], q0[0], fma(q0[1], q0[1], q0[2] * q0[2]));
@@ -246,43 +282,55 @@ __device__ __forceinline__ void push_chunk_f64(const PushArgs& a, int64_t chunk)
       for (int d = 0; d < 3; ++d) {
         double xn = fmod(fma(a.drift, q[d] / e, x[d]), a.box);   // floor-mod as numpy.mod
         if (xn < 0.0) xn += a.box;
-        stnt(xn, &sg.xd[d][i]);
+        stnt(xn, &X[d][i]);
       }
     }
 #pragma unroll
-    for (int d = 0; d < 3; ++d) stnt(q[d], &sg.qd[d][i]);
+    for (int d = 0; d < 3; ++d) stnt(q[d], &Q[d][i]);
   }
 }
 
 // Chunk loop.  One block per chunk, or (persistent) a fixed grid whose
 // blocks stride over the chunks; either way each XCD (block id mod 8) walks a
 // contiguous eighth of the chunk range.
-template <int NSLOT, int PPT, bool BLEND, bool TSC>
+template <int NSLOT, int PPT, bool BLEND, bool TSC, bool OFF32>
 __global__ void __launch_bounds__(kBlock) k_push_f32(PushArgs a) {
-  if (!a.persistent) { push_chunk_f32<NSLOT, PPT, BLEND, TSC>(a, xcd_chunk(blockIdx.x, gridDim.x)); return; }
+  if (!a.persistent) { push_chunk_f32<NSLOT, PPT, BLEND, TSC, OFF32>(a, xcd_chunk(blockIdx.x, gridDim.x)); return; }
   const int64_t per = (a.total_chunks + 7) / 8, x = blockIdx.x % 8, stride = gridDim.x / 8;
   const int64_t end = min((x + 1) * per, a.total_chunks);
-  for (int64_t c = x * per + blockIdx.x / 8; c < end; c += stride) push_chunk_f32<NSLOT, PPT, BLEND, TSC>(a, c);
+  for (int64_t c = x * per + blockIdx.x / 8; c < end; c += stride) push_chunk_f32<NSLOT, PPT, BLEND, TSC, OFF32>(a, c);
 }
 
-template <int NSLOT, int PPT, bool BLEND, bool TSC>
+template <int NSLOT, int PPT, bool BLEND, bool TSC, bool OFF32>
 __global__ void __launch_bounds__(kBlock) k_push_f64(PushArgs a) {
-  if (!a.persistent) { push_chunk_f64<NSLOT, PPT, BLEND, TSC>(a, xcd_chunk(blockIdx.x, gridDim.x)); return; }
+  if (!a.persistent) { push_chunk_f64<NSLOT, PPT, BLEND, TSC, OFF32>(a, xcd_chunk(blockIdx.x, gridDim.x)); return; }
   const int64_t per = (a.total_chunks + 7) / 8, x = blockIdx.x % 8, stride = gridDim.x / 8;
   const int64_t end = min((x + 1) * per, a.total_chunks);
-  for (int64_t c = x * per + blockIdx.x / 8; c < end; c += stride) push_chunk_f64<NSLOT, PPT, BLEND, TSC>(a, c);
+  for (int64_t c = x * per + blockIdx.x / 8; c < end; c += stride) push_chunk_f64<NSLOT, PPT, BLEND, TSC, OFF32>(a, c);
 }
 
 template <int PPT, bool BLEND, bool TSC>
 void push_launch(const PushArgs& a, hipStream_t s) {
   const int64_t grid_blocks = a.persistent ? a.persistent : a.total_chunks;
   const dim3 grid((unsigned)grid_blocks), block(kBlock);
+  // byte offsets of the mesh fit 32 bits?
+  const bool off32 = (uint64_t)a.G * a.G * a.G * (uint64_t)(a.nslot * (a.fp64 ? 8 : 2)) <= (1ull << 32);
   if (a.fp64) {
-    if (a.nslot == 8) hipLaunchKernelGGL((k_push_f64<8, PPT, BLEND, TSC>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((k_push_f64<4, PPT, BLEND, TSC>), grid, block, 0, s, a);
+    if (off32) {
+      if (a.nslot == 8) hipLaunchKernelGGL((k_push_f64<8, PPT, BLEND, TSC, true>), grid, block, 0, s, a);
+      else hipLaunchKernelGGL((k_push_f64<4, PPT, BLEND, TSC, true>), grid, block, 0, s, a);
+    } else {
+      if (a.nslot == 8) hipLaunchKernelGGL((k_push_f64<8, PPT, BLEND, TSC, false>), grid, block, 0, s, a);
+      else hipLaunchKernelGGL((k_push_f64<4, PPT, BLEND, TSC, false>), grid, block, 0, s, a);
+    }
   } else {
-    if (a.nslot == 8) hipLaunchKernelGGL((k_push_f32<8, PPT, BLEND, TSC>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((k_push_f32<4, PPT, BLEND, TSC>), grid, block, 0, s, a);
+    if (off32) {
+      if (a.nslot == 8) hipLaunchKernelGGL((k_push_f32<8, PPT, BLEND, TSC, true>), grid, block, 0, s, a);
+      else hipLaunchKernelGGL((k_push_f32<4, PPT, BLEND, TSC, true>), grid, block, 0, s, a);
+    } else {
+      if (a.nslot == 8) hipLaunchKernelGGL((k_push_f32<8, PPT, BLEND, TSC, false>), grid, block, 0, s, a);
+      else hipLaunchKernelGGL((k_push_f32<4, PPT, BLEND, TSC, false>), grid, block, 0, s, a);
+    }
   }
 }
 

@@ -25,8 +25,24 @@ __device__ __forceinline__ int find_segment(const Segment* seg, int nseg, int64_
   return s;
 }
 
-template <typename T> __device__ __forceinline__ T ldnt(const T* p) { return __builtin_nontemporal_load(p); }
-template <typename T> __device__ __forceinline__ void stnt(T v, T* p) { __builtin_nontemporal_store(v, p); }
+// The state arrays live in device global memory.  Their pointers come from a
+// device-side segment table, so the compiler cannot infer the address space
+// and would emit flat instructions; naming the global space gives global
+// loads/stores with a scalar base and a 32-bit lane offset.
+// (The host pass parses device code too; HIP's vector classes cannot bind
+// address-space-qualified references there, and no code is emitted for it.)
+#if defined(__HIP_DEVICE_COMPILE__)
+#define FDF_GLOBAL __attribute__((address_space(1)))
+#else
+#define FDF_GLOBAL
+#endif
+template <typename T> __device__ __forceinline__ const FDF_GLOBAL T* gptr(const T* p) {
+  return (const FDF_GLOBAL T*)p;
+}
+template <typename T> __device__ __forceinline__ T ldnt(const T* p) { return __builtin_nontemporal_load(gptr(p)); }
+template <typename T> __device__ __forceinline__ void stnt(T v, T* p) {
+  __builtin_nontemporal_store(v, (FDF_GLOBAL T*)p);
+}
 
 // Interpolation stencil of the force: CIC (r = 1, 8 points) or TSC (r = 2,
 // 27 points).  Every operation is explicit so that each copy of the code is
@@ -34,9 +50,9 @@ template <typename T> __device__ __forceinline__ void stnt(T v, T* p) { __builti
 template <bool TSC> struct Stencil { static constexpr int N = TSC ? 27 : 8; };
 
 // FP32 form: x is a 32-bit fixed-point fraction of the box per axis.
-template <bool TSC>
+template <bool TSC, typename I>
 __device__ __forceinline__ void stencil_u32(const uint32_t* xu, int shift, uint32_t gmask, float finv,
-                                            size_t G, size_t* cell, float* w) {
+                                            I G, I* cell, float* w) {
 #pragma clang fp contract(off)
   const uint32_t fmask = (1u << shift) - 1u;
   if constexpr (!TSC) {
@@ -52,7 +68,7 @@ __device__ __forceinline__ void stencil_u32(const uint32_t* xu, int shift, uint3
 #pragma unroll
     for (int cc = 0; cc < 8; ++cc) {
       const int cx = cc >> 2, cy = (cc >> 1) & 1, cz = cc & 1;
-      cell[cc] = ((size_t)(cx ? i1[0] : i0[0]) * G + (cy ? i1[1] : i0[1])) * G + (cz ? i1[2] : i0[2]);
+      cell[cc] = ((I)(cx ? i1[0] : i0[0]) * G + (cy ? i1[1] : i0[1])) * G + (cz ? i1[2] : i0[2]);
       w[cc] = ((cx ? t[0] : u[0]) * (cy ? t[1] : u[1])) * (cz ? t[2] : u[2]);
     }
   } else {
@@ -79,16 +95,16 @@ __device__ __forceinline__ void stencil_u32(const uint32_t* xu, int shift, uint3
       for (int b = 0; b < 3; ++b)
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          cell[9 * a + 3 * b + c] = ((size_t)idx[0][a] * G + idx[1][b]) * G + idx[2][c];
+          cell[9 * a + 3 * b + c] = ((I)idx[0][a] * G + idx[1][b]) * G + idx[2][c];
           w[9 * a + 3 * b + c] = (wt[0][a] * wt[1][b]) * wt[2][c];
         }
   }
 }
 
 // FP64 form: x in [0, L) Mpc.
-template <bool TSC>
-__device__ __forceinline__ void stencil_f64(const double* x, double ginv, int gm, size_t G,
-                                            size_t* cell, double* w) {
+template <bool TSC, typename I>
+__device__ __forceinline__ void stencil_f64(const double* x, double ginv, int gm, I G,
+                                            I* cell, double* w) {
 #pragma clang fp contract(off)
   if constexpr (!TSC) {
     int i0[3], i1[3];
@@ -104,7 +120,7 @@ __device__ __forceinline__ void stencil_f64(const double* x, double ginv, int gm
 #pragma unroll
     for (int cc = 0; cc < 8; ++cc) {
       const int cx = cc >> 2, cy = (cc >> 1) & 1, cz = cc & 1;
-      cell[cc] = ((size_t)(cx ? i1[0] : i0[0]) * G + (cy ? i1[1] : i0[1])) * G + (cz ? i1[2] : i0[2]);
+      cell[cc] = ((I)(cx ? i1[0] : i0[0]) * G + (cy ? i1[1] : i0[1])) * G + (cz ? i1[2] : i0[2]);
       w[cc] = ((cx ? t[0] : 1.0 - t[0]) * (cy ? t[1] : 1.0 - t[1])) * (cz ? t[2] : 1.0 - t[2]);
     }
   } else {
@@ -129,7 +145,7 @@ __device__ __forceinline__ void stencil_f64(const double* x, double ginv, int gm
       for (int b = 0; b < 3; ++b)
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          cell[9 * a + 3 * b + c] = ((size_t)idx[0][a] * G + idx[1][b]) * G + idx[2][c];
+          cell[9 * a + 3 * b + c] = ((I)idx[0][a] * G + idx[1][b]) * G + idx[2][c];
           w[9 * a + 3 * b + c] = (wt[0][a] * wt[1][b]) * wt[2][c];
         }
   }

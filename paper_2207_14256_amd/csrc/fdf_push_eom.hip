@@ -21,7 +21,7 @@
 // Grid slots per cell: EXACT   gpsi[3] gphi[3] phidot (phi + psi)
 //                      CANONICAL gpsi[3] gphi[3] psi phi
 //                      others  gpsi[3] 0           (4 slots)
-// Storage forms as in the separable push (fixed-point x and Kahan q in FP32).
+// Storage forms as in the separable push (fixed-point x and q = q0 + dq in FP32).
 #include "fdf_push_common.h"
 
 namespace fdf {
@@ -36,7 +36,7 @@ template <int NSLOT, int NPT>
 __device__ __forceinline__ void gather_all_bf16(const void* grid, const size_t* cell, const float* w, float* g) {
 #pragma clang fp contract(off)
   if constexpr (NSLOT == 8) {
-    const uint4* gp = (const uint4*)grid;
+    const FDF_GLOBAL uint4* gp = (const FDF_GLOBAL uint4*)grid;
     uint4 v[NPT];
 #pragma unroll
     for (int c = 0; c < NPT; ++c) v[c] = gp[cell[c]];
@@ -50,7 +50,7 @@ __device__ __forceinline__ void gather_all_bf16(const void* grid, const size_t* 
       }
     }
   } else {
-    const uint2* gp = (const uint2*)grid;
+    const FDF_GLOBAL uint2* gp = (const FDF_GLOBAL uint2*)grid;
     uint2 v[NPT];
 #pragma unroll
     for (int c = 0; c < NPT; ++c) v[c] = gp[cell[c]];
@@ -65,7 +65,7 @@ __device__ __forceinline__ void gather_all_bf16(const void* grid, const size_t* 
 template <int NSLOT, int NPT>
 __device__ __forceinline__ void gather_all_f64(const void* grid, const size_t* cell, const double* w, double* g) {
 #pragma clang fp contract(off)
-  const double2* gp = (const double2*)grid;
+  const FDF_GLOBAL double2* gp = (const FDF_GLOBAL double2*)grid;
 #pragma unroll
   for (int c = 0; c < NPT; ++c) {
 #pragma unroll
@@ -157,12 +157,13 @@ __device__ __forceinline__ void push_chunk_eom_f32(const PushArgs& a, int64_t ch
     const int64_t i = first + (int64_t)p * kBlock;
     if (i >= n) break;
     uint32_t xu[3];
-    float q[3], c[3];
+    float q0[3], dq[3], q[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       xu[d] = ldnt(&sg.xu[d][i]);
-      q[d] = ldnt(&sg.qf[d][i]);
-      c[d] = ldnt(&sg.cf[d][i]);
+      q0[d] = ldnt(&sg.q0f[d][i]);
+      dq[d] = ldnt(&sg.dqf[d][i]);
+      q[d] = q0[d] + dq[d];
     }
     size_t cell[NP];
     float w[NP];
@@ -183,11 +184,9 @@ __device__ __forceinline__ void push_chunk_eom_f32(const PushArgs& a, int64_t ch
       float F[3];
       eom_force<float>(a.eom, q, g, ma, ma2, F);
 #pragma unroll
-      for (int d = 0; d < 3; ++d) {   // Kahan-compensated q += kick * F
-        const float y = fmaf(kicks[h], F[d], -c[d]);
-        const float tq = q[d] + y;
-        c[d] = (tq - q[d]) - y;
-        q[d] = tq;
+      for (int d = 0; d < 3; ++d) {
+        dq[d] = fmaf(kicks[h], F[d], dq[d]);
+        q[d] = q0[d] + dq[d];
       }
     }
     if (a.do_drift) {
@@ -203,10 +202,7 @@ __device__ __forceinline__ void push_chunk_eom_f32(const PushArgs& a, int64_t ch
       }
     }
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      stnt(q[d], &sg.qf[d][i]);
-      stnt(c[d], &sg.cf[d][i]);
-    }
+    for (int d = 0; d < 3; ++d) stnt(dq[d], &sg.dqf[d][i]);
   }
 }
 

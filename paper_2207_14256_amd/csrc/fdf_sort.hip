@@ -25,14 +25,34 @@ __device__ __forceinline__ uint32_t part1by2(uint32_t v) {   // spread 10 bits t
 }
 
 // Full key of particle i: Morton index of its coarse tile (the counting-sort
-// bucket) above the Morton index of its cell inside the tile.
+// bucket) above the Morton index of its cell inside the tile.  The position
+// is extrapolated along the particle's current velocity to the middle of the
+// interval until the next re-sort: neighbours in that order stay within half
+// an interval's drift of each other over the whole interval, instead of a
+// whole interval's drift by its end.
 __device__ __forceinline__ uint32_t full_key(const SortArgs& a, int64_t i) {
   uint32_t c[3];
   if (a.fp64) {
     const double s = (double)a.grid_n / a.box;
-    for (int d = 0; d < 3; ++d) c[d] = (uint32_t)(int64_t)floor(a.seg.xd[d][i] * s) & (uint32_t)(a.grid_n - 1);
+    double v[3] = {0.0, 0.0, 0.0};
+    if (a.predict_tau != 0.0) {
+      const double q[3] = {a.seg.qd[0][i], a.seg.qd[1][i], a.seg.qd[2][i]};
+      const double f = a.predict_tau / sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + a.ma * a.ma);
+      for (int d = 0; d < 3; ++d) v[d] = q[d] * f;
+    }
+    for (int d = 0; d < 3; ++d)
+      c[d] = (uint32_t)(int64_t)floor((a.seg.xd[d][i] + v[d]) * s) & (uint32_t)(a.grid_n - 1);
   } else {
-    for (int d = 0; d < 3; ++d) c[d] = a.seg.xu[d][i] >> a.cell_shift;
+    uint32_t x[3] = {a.seg.xu[0][i], a.seg.xu[1][i], a.seg.xu[2][i]};
+    if (a.predict_tau != 0.0) {
+      float q[3];
+      for (int d = 0; d < 3; ++d) q[d] = a.seg.q0f[d][i] + a.seg.dqf[d][i];
+      const float ma = (float)a.ma;
+      const float f = (float)(a.predict_tau * 4294967296.0 / a.box) /
+                      sqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + ma * ma);
+      for (int d = 0; d < 3; ++d) x[d] += (uint32_t)__float2int_rn(q[d] * f);   // wraps with the box
+    }
+    for (int d = 0; d < 3; ++d) c[d] = x[d] >> a.cell_shift;
   }
   const int fb = a.fine_bits;                       // log2 of the tile side in cells
   const uint32_t fm = (1u << fb) - 1u;
@@ -186,9 +206,8 @@ __global__ void __launch_bounds__(256) k_sort_move(SortArgs a) {
     uint32_t* l = (uint32_t*)lds_raw;
     for (int k = 0; k < 3; ++k) {
       move_array(s.xu[k], d.xu[k], l, i0, cnt, sidx, pos);
-      move_array((const uint32_t*)s.qf[k], (uint32_t*)d.qf[k], l, i0, cnt, sidx, pos);
-      move_array((const uint32_t*)s.cf[k], (uint32_t*)d.cf[k], l, i0, cnt, sidx, pos);
       move_array((const uint32_t*)s.q0f[k], (uint32_t*)d.q0f[k], l, i0, cnt, sidx, pos);
+      move_array((const uint32_t*)s.dqf[k], (uint32_t*)d.dqf[k], l, i0, cnt, sidx, pos);
     }
   }
   move_array(s.id, d.id, (uint32_t*)lds_raw, i0, cnt, sidx, pos);

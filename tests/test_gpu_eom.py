@@ -90,7 +90,7 @@ def test_eom_potential_slots(eom, quantities):
 
 @pytest.mark.parametrize("eom", ["exact", "simple_q"])
 def test_eom_fp32_error_statement(eom):
-    """Precision form (fixed-point x, Kahan q, bf16 mesh) against the FP64 oracle."""
+    """Precision form (fixed-point x, q = q0 + dq, bf16 mesh) against the FP64 oracle."""
     say("eom %s fp32" % eom)
     cfg = _cfg(eom, "fp32", grid_n=32, n_side=24, n_steps=40)
     ctx, fields, species, x, q, w = _run(cfg)

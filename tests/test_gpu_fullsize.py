@@ -76,7 +76,7 @@ def test_c2_full_fp64_sampled():
 
 def test_c3_full_fp32_error_statement():
     """Precision form at full size (512^3, 1000 steps z = 1e9 -> 0, bf16 mesh,
-    fixed-point x, Kahan q) against the FP64 oracle on sampled ids, and its
+    fixed-point x, q = q0 + dq) against the FP64 oracle on sampled ids, and its
     P(k) against the FP64 path at the same size on k <= k_N / 2."""
     print("[gpu-case] c3 full fp32 + fp64", flush=True)
     cfg = workloads.preset("c3")

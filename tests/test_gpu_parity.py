@@ -4,7 +4,7 @@ inputs, through the C ABI (ctypes binding).
 Tolerances: the FP64 path must match to 1e-5 relative (positions and momenta);
 it agrees far better in practice since both evaluate the same formulas in
 binary64 and differ only in rounding order (fused half-kicks, FMA, libm).
-The FP32 form (fixed-point x, Kahan q, bfloat16 grids) is held to stated
+The FP32 form (fixed-point x, q = q0 + dq, bfloat16 grids) is held to stated
 error bounds.
 """
 import sys
