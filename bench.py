@@ -106,14 +106,21 @@ def traffic_from_profile(workload):
     """HBM bytes per push launch from committed rocprofv3 counter summaries,
     if they were taken on the current push kernel source."""
     path = os.path.join(ROOT, "profiles", "push_%s_traffic.json" % workload)
-    src = os.path.join(ROOT, "paper_2207_14256_amd", "csrc", "fdf_push.hip")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if rec.get("push_source_sha256") != sha:
+    if rec.get("push_source_sha256") != push_source_sha():
         return None
     return rec.get("hbm_bytes_per_launch")
+
+
+def push_source_sha():
+    """SHA-256 over the sources of the separable push kernel."""
+    h = hashlib.sha256()
+    for name in ("fdf_push.hip", "fdf_push_common.h"):
+        with open(os.path.join(ROOT, "paper_2207_14256_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def _cpu_worker(cfg, queue):
