@@ -205,3 +205,22 @@ def kdk_variant(x, q, m, sched, L, grids_at, mode, k_begin=0, k_end=None, order=
         gpsi, gphi, phidot, _, _ = sample_potentials(grids_at(k + 1), x, L, order)
         q = q + sched["kick2"][k] * variant_force(mode, q, m, sched["a"][k + 1], gpsi, gphi, phidot)
     return x, q
+
+
+def geodesic_force_terms(q, m, a, gpsi, gphi, phidot):
+    """The four contributions to dq/dtau of eq. releq (sec. 3.1, Fig. 2), each
+    (N, 3): -eps grad psi, -(q^2/eps) grad phi, q (q . grad phi)/eps and
+    q phidot, with eps = sqrt(q^2 + m^2 a^2) of the current momentum."""
+    q2 = np.sum(q * q, axis=-1)
+    eps = np.sqrt(q2 + (m * a) ** 2)
+    qg = np.sum(q * gphi, axis=-1)
+    return (-eps[:, None] * gpsi, -(q2 / eps)[:, None] * gphi,
+            q * (qg / eps)[:, None], q * phidot[:, None])
+
+
+def force_term_rms(grids, x, q, m, a, L, order=1):
+    """Root mean square over particles of the magnitude of each term of
+    geodesic_force_terms at positions x (4 values)."""
+    gpsi, gphi, phidot = sample_fields(grids, x, L, order)
+    terms = geodesic_force_terms(q, m, a, gpsi, gphi, phidot)
+    return np.array([np.sqrt(np.mean(np.sum(t * t, axis=-1))) for t in terms])

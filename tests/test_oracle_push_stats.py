@@ -640,3 +640,24 @@ def test_tsc_reproduces_linear_and_quadratic_fields():
     assert np.allclose(push.interpolate(quad, x, L, 2), u[:, 2] ** 2 + 0.25, rtol=0, atol=1e-10)
     t = u[:, 2] - np.floor(u[:, 2])
     assert np.allclose(push.interpolate(quad, x, L, 1), u[:, 2] ** 2 + t * (1 - t), rtol=0, atol=1e-10)
+
+
+# ------------------------------------------- Fig. 2 acceleration terms --
+
+def test_force_terms_sum_to_the_exact_force_and_cancel_along_grad_phi():
+    """The four terms add up to eq. releq's right-hand side; for q parallel to
+    grad phi the two quadratic terms cancel exactly; with m = 0 and phi = psi
+    the Newtonian and first quadratic term have equal size |q| |grad psi|."""
+    rng = np.random.default_rng(21)
+    q = rng.normal(size=(50, 3)) * 4e-4
+    gpsi = rng.normal(size=(50, 3)) * 1e-6
+    gphi = rng.normal(size=(50, 3)) * 1e-6
+    phidot = rng.normal(size=50) * 1e-7
+    terms = push.geodesic_force_terms(q, 0.07, 0.01, gpsi, gphi, phidot)
+    total = push.variant_force(push.EOM_EXACT, q, 0.07, 0.01, gpsi, gphi, phidot)
+    assert np.allclose(sum(terms), total, rtol=0, atol=1e-13 * np.abs(total).max())
+    par = q * 2.5e-3                                   # grad phi parallel to q
+    t = push.geodesic_force_terms(q, 0.07, 0.01, gpsi, par, phidot)
+    assert np.allclose(t[1] + t[2], 0.0, atol=1e-14 * np.abs(t[1]).max())
+    t0 = push.geodesic_force_terms(q, 0.0, 1.0, gpsi, gpsi, phidot)
+    assert np.allclose(np.linalg.norm(t0[0], axis=1), np.linalg.norm(t0[1], axis=1), rtol=1e-14)
