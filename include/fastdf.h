@@ -275,6 +275,16 @@ int fdf_power_spectrum(struct fdf_ctx* ctx, const int32_t* species, int32_t n_sp
                        int32_t n_bins, int32_t mode, int32_t quantity, int32_t analysis_n,
                        double* h_k, double* h_p, double* h_nmodes);
 
+/* Fig. 2 diagnostic (sec. 3.1): root mean square over the species' particles
+ * of the magnitude of each term of eq. releq at the current state and a_k --
+ * h_rms[0] = |eps grad psi|, [1] = |(q^2/eps) grad phi|, [2] = |q (q.grad phi)/eps|,
+ * [3] = |q phidot| [eV/Mpc] -- with eps from the current momentum and the
+ * mesh values interpolated by CIC.  Builds the grids at a_k when they are not
+ * current (with super-steps this replaces the first grid set).  Blocking.
+ * FDF_ERR_UNSUPPORTED when the equation of motion's layout lacks grad phi or
+ * phi-dot (canonical, SR-Newtonian, simple-q and Newtonian forms). */
+int fdf_force_terms(struct fdf_ctx* ctx, int32_t species_id, double* h_rms);
+
 /* ---- read-back (blocking) -------------------------------------------------- */
 
 /* Current state in binary64, indexed by id: h_x[n][3] in [0, L) Mpc,

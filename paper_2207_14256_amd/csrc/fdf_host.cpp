@@ -1141,6 +1141,48 @@ int fdf_step(fdf_ctx* c, int32_t n) {
   return enqueue_steps(c, n);
 }
 
+int fdf_force_terms(fdf_ctx* c, int32_t sid, double* h_rms) {
+  if (!c || !h_rms) return FDF_ERR_ARG;
+  if (!needs_ws(c)) return fail(c, FDF_ERR_WORKSPACE, "no workspace attached");
+  if (sid < 0 || sid >= (int)c->species.size()) return fail(c, FDF_ERR_ARG, "bad species id");
+  const int s_gpsi = grid_slot(c->cfg, 0), s_gphi = grid_slot(c->cfg, 3), s_dot = grid_slot(c->cfg, 6);
+  if (s_gpsi < 0 || s_gphi < 0 || s_dot == -2)
+    return fail(c, FDF_ERR_UNSUPPORTED, "grad psi, grad phi and phi-dot are not all stored for this equation of motion");
+  SpeciesRec& sp = c->species[sid];
+  FieldRec& f = c->fields[sp.field];
+  const double a = c->a[c->step_index];
+  const bool tdep = c->cfg.potential_model == FDF_MODEL_RADMAT;
+  if (!f.has_grid || (tdep && f.grid_a != a) || !c->anchors.empty()) {
+    f.tag[0] = -1;   // buffer 0 no longer holds a super-step anchor
+    const int rc = build_grid(c, sp.field, a);
+    if (rc) return rc;
+  }
+  TermArgs t{};
+  t.seg = sp.seg[sp.cur];
+  t.fp64 = c->cfg.precision == FDF_PREC_FP64;
+  t.G = c->cfg.grid_n;
+  t.nslot = c->lay.nslot;
+  t.slot_gpsi = s_gpsi;
+  t.slot_gphi = s_gphi;
+  t.slot_phidot = s_dot;
+  t.box = c->cfg.box_mpc;
+  t.ma = sp.m * a;
+  t.grid = f.grid;
+  t.out = (double*)(c->ws + c->lay.bins);
+  launch_fill_zero(t.out, align_up(3 * kMaxBins * sizeof(double)), c->stream);
+  std::pair<hipEvent_t, hipEvent_t> ev;
+  timing_begin(c, FDF_KERNEL_OUTPUT, &ev);
+  launch_force_terms(t, c->stream);
+  timing_end(c, FDF_KERNEL_OUTPUT, ev);
+  int rc = launched(c, "force terms");
+  double sums[4];
+  if (!rc) rc = hip_check(c, hipMemcpyAsync(sums, t.out, sizeof(sums), hipMemcpyDeviceToHost, c->stream), "terms");
+  if (!rc) rc = hip_check(c, hipStreamSynchronize(c->stream), "terms");
+  if (rc) return rc;
+  for (int k = 0; k < 4; ++k) h_rms[k] = sp.n ? std::sqrt(sums[k] / (double)sp.n) : 0.0;
+  return FDF_OK;
+}
+
 int fdf_weights(fdf_ctx* c, int32_t sid, double* d_w) {
   if (!c || !d_w) return FDF_ERR_ARG;
   if (sid < 0 || sid >= (int)c->species.size()) return fail(c, FDF_ERR_ARG, "bad species id");

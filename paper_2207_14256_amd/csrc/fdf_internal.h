@@ -165,7 +165,23 @@ struct OutputArgs {
   void* dens[2];           // real [G^3] per half (f32 or f64)
 };
 
+// Acceleration terms of eq. releq (Fig. 2 diagnostic): sums over particles of
+// the squared magnitude of each of the four terms.
+struct TermArgs {
+  Segment seg;
+  int32_t fp64;
+  int32_t G;
+  int32_t nslot;
+  int32_t slot_gpsi;       // first of three slots of grad psi
+  int32_t slot_gphi;       // first of three slots of grad phi
+  int32_t slot_phidot;     // slot of phi-dot, or -1 when it is zero
+  double box, ma;
+  const void* grid;        // [G^3][nslot], bf16 (FP32 form) or f64
+  double* out;             // [4], zeroed by the caller
+};
+
 void launch_field_gen(const FieldGenArgs& a, hipStream_t s);
+void launch_force_terms(const TermArgs& a, hipStream_t s);
 void launch_sample_species(const SampleArgs& a, hipStream_t s);
 void launch_pre_ic(const PreIcArgs& a, hipStream_t s);
 void launch_build_grids(const GridBuildArgs& a, hipStream_t s);

@@ -1,5 +1,7 @@
 // Outputs of the push: delta-f weights (sec. 2.2) and the energy-density
 // deposit of eq. empirical_rho, gfx950.
+#include <algorithm>
+
 #include "fdf_device.h"
 #include "fdf_internal.h"
 
@@ -87,6 +89,70 @@ __global__ void k_deposit(OutputArgs a) {
   }
 }
 
+// Squared magnitudes of -eps grad psi, -(q^2/eps) grad phi, q (q . grad phi)/eps
+// and q phidot at the particle's CIC-interpolated mesh values, summed per
+// block in LDS and added to a.out.
+__device__ __forceinline__ double term_slot(const TermArgs& a, size_t cell, int slot) {
+  if (a.fp64) return ((const double*)a.grid)[cell * a.nslot + slot];
+  const uint16_t b = ((const uint16_t*)a.grid)[cell * a.nslot + slot];
+  return (double)__uint_as_float((uint32_t)b << 16);
+}
+
+__global__ void __launch_bounds__(256) k_force_terms(TermArgs a) {
+  __shared__ double red[4][256];
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  const int G = a.G;
+  const double ginv = (double)G / a.box;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < a.seg.n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    double x[3], q[3];
+    for (int d = 0; d < 3; ++d) {
+      if (a.fp64) { x[d] = a.seg.xd[d][i]; q[d] = a.seg.qd[d][i]; }
+      else {
+        x[d] = (double)a.seg.xu[d][i] * (a.box * 0x1p-32);
+        q[d] = (double)a.seg.q0f[d][i] + (double)a.seg.dqf[d][i];
+      }
+    }
+    int i0[3], i1[3];
+    double t[3];
+    for (int d = 0; d < 3; ++d) {
+      const double u = x[d] * ginv;
+      const double fl = floor(u);
+      t[d] = u - fl;
+      i0[d] = ((int)fl) & (G - 1);
+      i1[d] = (i0[d] + 1) & (G - 1);
+    }
+    double gpsi[3] = {0, 0, 0}, gphi[3] = {0, 0, 0}, phidot = 0.0;
+    for (int c = 0; c < 8; ++c) {
+      const int cx = c >> 2, cy = (c >> 1) & 1, cz = c & 1;
+      const double w = (cx ? t[0] : 1 - t[0]) * (cy ? t[1] : 1 - t[1]) * (cz ? t[2] : 1 - t[2]);
+      const size_t cell = ((size_t)(cx ? i1[0] : i0[0]) * G + (cy ? i1[1] : i0[1])) * G + (cz ? i1[2] : i0[2]);
+      for (int d = 0; d < 3; ++d) {
+        gpsi[d] += w * term_slot(a, cell, a.slot_gpsi + d);
+        gphi[d] += w * term_slot(a, cell, a.slot_gphi + d);
+      }
+      if (a.slot_phidot >= 0) phidot += w * term_slot(a, cell, a.slot_phidot);
+    }
+    const double q2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2];
+    const double eps = sqrt(q2 + a.ma * a.ma);
+    const double qg = q[0] * gphi[0] + q[1] * gphi[1] + q[2] * gphi[2];
+    const double g2psi = gpsi[0] * gpsi[0] + gpsi[1] * gpsi[1] + gpsi[2] * gpsi[2];
+    const double g2phi = gphi[0] * gphi[0] + gphi[1] * gphi[1] + gphi[2] * gphi[2];
+    acc[0] += eps * eps * g2psi;
+    acc[1] += (q2 / eps) * (q2 / eps) * g2phi;
+    acc[2] += q2 * (qg / eps) * (qg / eps);
+    acc[3] += q2 * phidot * phidot;
+  }
+  for (int k = 0; k < 4; ++k) red[k][threadIdx.x] = acc[k];
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s)
+      for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) atomicAdd(&a.out[threadIdx.x], red[threadIdx.x][0]);
+}
+
 __global__ void k_fill_zero(uint4* p, size_t n16) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n16;
        i += (size_t)gridDim.x * blockDim.x)
@@ -102,6 +168,10 @@ int grid_for(size_t n, int block) {
 
 void launch_weights(const OutputArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_weights, dim3(grid_for((size_t)a.seg.n, 256)), dim3(256), 0, s, a);
+}
+
+void launch_force_terms(const TermArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_force_terms, dim3(std::min(grid_for((size_t)a.seg.n, 256), 4096)), dim3(256), 0, s, a);
 }
 
 void launch_deposit(const OutputArgs& a, hipStream_t s) {

@@ -28,7 +28,7 @@ EXPORTS = [
     "fdf_workspace_size", "fdf_create", "fdf_attach_workspace", "fdf_reset", "fdf_destroy",
     "fdf_add_field", "fdf_set_field", "fdf_init_species", "fdf_set_species_state",
     "fdf_build_potential_grids", "fdf_step", "fdf_weights", "fdf_density_power_spectrum",
-    "fdf_momentum_power_spectrum", "fdf_power_spectrum",
+    "fdf_momentum_power_spectrum", "fdf_force_terms", "fdf_power_spectrum",
     "fdf_read_state", "fdf_read_grid", "fdf_read_field", "fdf_read_density",
     "fdf_read_schedule", "fdf_get_info", "fdf_sync", "fdf_timing_enable",
     "fdf_read_timing", "fdf_timing_reset", "fdf_status_string", "fdf_last_error",
@@ -103,6 +103,7 @@ def load():
         "fdf_weights": [P, I32, P],
         "fdf_density_power_spectrum": [P, ctypes.POINTER(I32), I32, I32, I32, PD, PD, PD],
         "fdf_momentum_power_spectrum": [P, ctypes.POINTER(I32), I32, I32, I32, PD, PD, PD],
+        "fdf_force_terms": [P, I32, PD],
         "fdf_power_spectrum": [P, ctypes.POINTER(I32), I32, I32, I32, I32, I32, PD, PD, PD],
         "fdf_read_state": [P, I32, PD, PD],
         "fdf_read_grid": [P, I32, I32, PD],
@@ -292,6 +293,13 @@ class Context:
             self._check(getattr(self.lib, name)(self.ctx, spp, len(sp), int(n_bins), md,
                                                 _dptr(k), _dptr(p), _dptr(nm)), name)
         return k, p, nm
+
+    def force_terms(self, species):
+        """rms magnitudes of the four terms of eq. releq at the current state:
+        (Newtonian, q^2 grad phi, q (q.grad phi), q phidot) in eV/Mpc."""
+        out = np.empty(4)
+        self._check(self.lib.fdf_force_terms(self.ctx, int(species), _dptr(out)), "fdf_force_terms")
+        return out
 
     # ------------------------------------------------------------- read-back --
     def info(self):

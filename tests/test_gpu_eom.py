@@ -145,3 +145,28 @@ def test_separable_vs_exact_power_spectrum():
     rel = np.abs(pe[ok] / ps[ok] - 1)
     say("separable vs exact: max |dP/P| = %.3e, median %.3e" % (rel.max(), np.median(rel)))
     assert np.median(rel) < 1e-3
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_force_terms_parity(prec):
+    """Fig. 2 diagnostic: rms of the four terms of eq. releq over the species,
+    at the start and after the run, against the oracle's at its own state."""
+    say("force terms %s" % prec)
+    cfg = _cfg("separable", prec)
+    ctx, fields, species = fastdf.setup_workload(cfg)
+    start = ctx.force_terms(species[0])
+    ctx.step(cfg["n_steps"])
+    end = ctx.force_terms(species[0])
+    ctx.close()
+    n = cfg["species"][0]["n_side"] ** 3
+    ref = pipeline.run_particles(cfg, 0, np.arange(n))
+    sched = pipeline.schedule(cfg)
+    grids = pipeline.grids_provider(cfg, pipeline.delta0(cfg), sched)
+    m, L = cfg["species"][0]["m"], cfg["box_mpc"]
+    from oracle import push as opush
+    r0 = opush.force_term_rms(grids(0), ref["x0"], ref["q0"], m, sched["a"][0], L)
+    r1 = opush.force_term_rms(grids(cfg["n_steps"]), ref["x"], ref["q"], m, sched["a"][-1], L)
+    tol = 1e-9 if prec == "fp64" else 1e-2
+    say("terms start %s / %s, end %s / %s" % (start, r0, end, r1))
+    assert np.all(r0 > 0) and np.all(r1 > 0)
+    assert np.allclose(start, r0, rtol=tol) and np.allclose(end, r1, rtol=tol)
