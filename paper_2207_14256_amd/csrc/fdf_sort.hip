@@ -76,13 +76,23 @@ constexpr uint64_t kIdxMask = kRankBlock - 1;
 
 
 
-// Rank pass.  A block sorts its 1024 particles by full key in LDS (bitonic
-// network), cuts the sorted run into segments of equal bucket, and reserves
-// one contiguous range per segment with a single atomicAdd on the bucket
-// count.  Each particle's rank inside its bucket and its bucket are written
-// in source order.  The fragment a block writes into a bucket is therefore
-// contiguous and ordered by cell.
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int mask) {
+  const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, mask, 64);
+  const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), mask, 64);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Rank pass.  A block sorts its 1024 particles by full key (bitonic network:
+// thread t holds sorted positions 4t .. 4t + 3 in registers; partners within
+// a thread swap in registers, partners within a wave meet through lane
+// shuffles, and only the three stages that cross waves go through LDS), cuts
+// the sorted run into segments of equal bucket, and reserves one contiguous
+// range per segment with a single atomicAdd on the bucket count.  Each
+// particle's rank inside its bucket and its bucket are written in source
+// order.  The fragment a block writes into a bucket is therefore contiguous
+// and ordered by cell.
 __global__ void __launch_bounds__(kRankThreads) k_sort_rank(SortArgs a) {
+  static_assert(kRankBlock == 4 * kRankThreads, "four elements per thread");
   __shared__ uint64_t kv[kRankBlock];
   __shared__ uint32_t seg_start[kRankBlock];
   __shared__ uint32_t seg_base[kRankBlock];
@@ -90,23 +100,56 @@ __global__ void __launch_bounds__(kRankThreads) k_sort_rank(SortArgs a) {
   const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
   const int64_t i0 = blk * kRankBlock;
   const int tid = threadIdx.x;
-  for (int e = tid; e < kRankBlock; e += kRankThreads) {
+  uint64_t v[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int e = 4 * tid + r;
     const int64_t i = i0 + e;
     const uint64_t key = i < a.seg.n ? (uint64_t)full_key(a, i) : 0xFFFFFFFFull;
-    kv[e] = (key << 10) | (uint64_t)e;
+    v[r] = (key << 10) | (uint64_t)e;
   }
-  __syncthreads();
+  // element e = 4 tid + r keeps the smaller of its pair exactly when it is the
+  // lower index of an ascending pair or the upper index of a descending one
+#pragma unroll
   for (int k = 2; k <= kRankBlock; k <<= 1) {
+#pragma unroll
     for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int t = tid; t < kRankBlock / 2; t += kRankThreads) {
-        const int p = (t / j) * 2 * j + (t % j);
-        const uint64_t x = kv[p], y = kv[p + j];
-        const bool up = (p & k) == 0;
-        if ((x > y) == up) { kv[p] = y; kv[p + j] = x; }
+      if (j >= 4 * 64) {                 // partner in another wave
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 4; ++r) kv[4 * tid + r] = v[r];
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int e = 4 * tid + r;
+          const uint64_t w = kv[e ^ j];
+          const bool keep_min = ((e & j) == 0) == ((e & k) == 0);
+          v[r] = keep_min ? min(v[r], w) : max(v[r], w);
+        }
+      } else if (j >= 4) {               // partner in another lane of the wave
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int e = 4 * tid + r;
+          const uint64_t w = shfl_xor_u64(v[r], j >> 2);
+          const bool keep_min = ((e & j) == 0) == ((e & k) == 0);
+          v[r] = keep_min ? min(v[r], w) : max(v[r], w);
+        }
+      } else {                           // partner in this thread
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          if (r & j) continue;
+          const int e = 4 * tid + r;
+          const bool up = (e & k) == 0;
+          const uint64_t x = v[r], y = v[r + j];
+          if ((x > y) == up) { v[r] = y; v[r + j] = x; }
+        }
       }
-      __syncthreads();
     }
   }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < 4; ++r) kv[4 * tid + r] = v[r];
+  __syncthreads();
   // segment starts: inclusive max-scan of head positions over the sorted run;
   // thread tid owns sorted elements 4 tid .. 4 tid + 3
   const int sh = 10 + 3 * a.fine_bits;   // key bits below the bucket index
