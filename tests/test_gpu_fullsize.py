@@ -117,3 +117,54 @@ def test_c3_full_fp32_error_statement():
     assert es32["pos_rms_cells"] < 1e-2
     assert es32["q_rel_rms"] < 1e-2
     assert es32["pk_rel_err_vs_fp64_path_max"] < 1e-2
+
+
+def test_c4_full_batched_fp32_sampled():
+    """The batched workload at full size (3 masses on one field at 128^3 /
+    256^3 / 384^3 plus 16 seeds x 128^3, 256^3 meshes, 300 steps z = 1e9 ->
+    31), one launch per step, against the FP64 oracle on sampled ids of three
+    members: the lightest and heaviest mass and one extra seed."""
+    print("[gpu-case] c4 full batched fp32", flush=True)
+    cfg = workloads.preset("c4")
+    ctx, fields, species = fastdf.setup_workload(cfg, tuning=autotune.cached_tuning(cfg))
+    ctx.step(cfg["n_steps"])
+    states = {i: ctx.read_state(species[i]) + (ctx.weights(species[i]).cpu().numpy(),) for i in (0, 2, 5)}
+    ctx.close()
+    import torch
+    torch.cuda.empty_cache()
+    report = {}
+    for i, (x, q, w) in states.items():
+        n = cfg["species"][i]["n_side"] ** 3
+        ids = workloads.sample_ids(n, 1024, seed=100 + i)
+        ref = pipeline.run_particles(cfg, i, ids)
+        es = _error_statement(cfg, x, q, w, ref, ids)
+        report["species_%d_m%g" % (i, cfg["species"][i]["m"])] = es
+        assert es["pos_rms_cells"] < 1e-2 and es["q_rel_rms"] < 1e-2, (i, es)
+    _report("error_statement_c4_fp32.json", report)
+
+
+def test_c5_full_fp32_sampled():
+    """The scale workload at full size: 1024^3 particles (m = 0.15 eV) on a
+    512^3 bf16 mesh, 2 Gpc, 1000 steps z = 1e9 -> 0, re-sort every 20 steps,
+    against the FP64 oracle on sampled ids."""
+    print("[gpu-case] c5 full fp32", flush=True)
+    cfg = workloads.preset("c5")
+    ctx, fields, species = fastdf.setup_workload(cfg, tuning=autotune.cached_tuning(cfg))
+    ctx.step(cfg["n_steps"])
+    ids = workloads.sample_ids(1024 ** 3, N_SAMPLE)
+    x, q = ctx.read_state(species[0])
+    x, q = x[ids], q[ids]
+    w = ctx.weights(species[0]).cpu().numpy()[ids]
+    k, p, nm = ctx.power_spectrum(species, cfg["pk_bins"])
+    ctx.close()
+    import torch
+    torch.cuda.empty_cache()
+    ref = pipeline.run_particles(cfg, 0, ids)
+    sel = np.arange(len(ids))
+    es = _error_statement(cfg, x, q, w, ref, sel)
+    _report("error_statement_c5_fp32.json", es)
+    assert es["pos_rms_cells"] < 1e-2 and es["q_rel_rms"] < 1e-2
+    kr, nr = _mode_counts(cfg)
+    assert np.array_equal(nm, nr)
+    ok = nr > 0
+    assert np.all(np.isfinite(p[ok]))
