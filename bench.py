@@ -38,11 +38,17 @@ def log(msg):
 
 def bytes_per_launch(cfg, n_particles, drift):
     """Algorithmic HBM bytes of one push launch: state read + write per
-    particle, plus one read of the gradient mesh.  FP32 form: read x, q0, dq
-    (36 B), write x, dq (24 B; 12 B without the drift); FP64 form: read x, q,
-    q0 (72 B), write x, q (48 B; 24 B without the drift)."""
+    particle, plus one read of the gradient mesh (4, 6 or 8 slots per cell).
+    FP32 form: read x, q0, dq (36 B), write x, dq (24 B; 12 B without the
+    drift); FP64 form: read x, q, q0 (72 B), write x, q (48 B; 24 B without
+    the drift)."""
     G = cfg["grid_n"]
-    nslot = 8 if cfg.get("slip_amp", 0.0) else 4
+    if not cfg.get("slip_amp", 0.0):
+        nslot = 4                                  # grad psi, phi-dot
+    elif cfg["precision"] == "fp64" and cfg.get("model") != "radmat":
+        nslot = 6                                  # grad psi, grad phi
+    else:
+        nslot = 8                                  # grad psi, grad phi, phi-dot, pad
     if cfg["precision"] == "fp32":
         per = 36 + (24 if drift else 12)
         grid = G ** 3 * nslot * 2

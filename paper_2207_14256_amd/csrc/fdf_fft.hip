@@ -259,6 +259,12 @@ template <> __device__ __forceinline__ void store_cell<8, GT_BF16, float>(void* 
   w.w = f32_to_bf16_bits(v[6]) | (f32_to_bf16_bits(v[7]) << 16);
   ((uint4*)out)[cell] = w;
 }
+template <> __device__ __forceinline__ void store_cell<6, GT_BF16, float>(void* out, size_t cell, const float* v) {
+  uint32_t* o = (uint32_t*)out + 3 * cell;   // 12-byte cell
+  o[0] = f32_to_bf16_bits(v[0]) | (f32_to_bf16_bits(v[1]) << 16);
+  o[1] = f32_to_bf16_bits(v[2]) | (f32_to_bf16_bits(v[3]) << 16);
+  o[2] = f32_to_bf16_bits(v[4]) | (f32_to_bf16_bits(v[5]) << 16);
+}
 template <> __device__ __forceinline__ void store_cell<4, GT_BF16, float>(void* out, size_t cell, const float* v) {
   uint2 w;
   w.x = f32_to_bf16_bits(v[0]) | (f32_to_bf16_bits(v[1]) << 16);
@@ -276,6 +282,12 @@ template <> __device__ __forceinline__ void store_cell<4, GT_F64, double>(void* 
   double2* o = (double2*)out + 2 * cell;
   o[0] = make_double2(v[0], v[1]);
   o[1] = make_double2(v[2], v[3]);
+}
+template <> __device__ __forceinline__ void store_cell<6, GT_F64, double>(void* out, size_t cell, const double* v) {
+  double2* o = (double2*)out + 3 * cell;
+  o[0] = make_double2(v[0], v[1]);
+  o[1] = make_double2(v[2], v[3]);
+  o[2] = make_double2(v[4], v[5]);
 }
 template <> __device__ __forceinline__ void store_cell<8, GT_F64, double>(void* out, size_t cell, const double* v) {
   double2* o = (double2*)out + 4 * cell;
@@ -537,6 +549,7 @@ void build_grids_g(const GridBuildArgs& a, hipStream_t s) {
   if constexpr (std::is_same<R, float>::value) {
     if (a.out_type == GT_BF16) {
       if (a.nslot == 8) hipLaunchKernelGGL((k_zpass_c2r<R, G, 8, GT_BF16>), zg, dim3(S::NT), 0, s, a);
+      else if (a.nslot == 6) hipLaunchKernelGGL((k_zpass_c2r<R, G, 6, GT_BF16>), zg, dim3(S::NT), 0, s, a);
       else hipLaunchKernelGGL((k_zpass_c2r<R, G, 4, GT_BF16>), zg, dim3(S::NT), 0, s, a);
     } else {
       if (a.nslot == 8) hipLaunchKernelGGL((k_zpass_c2r<R, G, 8, GT_F32>), zg, dim3(S::NT), 0, s, a);
@@ -544,6 +557,7 @@ void build_grids_g(const GridBuildArgs& a, hipStream_t s) {
     }
   } else {
     if (a.nslot == 8) hipLaunchKernelGGL((k_zpass_c2r<R, G, 8, GT_F64>), zg, dim3(S::NT), 0, s, a);
+    else if (a.nslot == 6) hipLaunchKernelGGL((k_zpass_c2r<R, G, 6, GT_F64>), zg, dim3(S::NT), 0, s, a);
     else hipLaunchKernelGGL((k_zpass_c2r<R, G, 4, GT_F64>), zg, dim3(S::NT), 0, s, a);
   }
 }

@@ -153,8 +153,17 @@ struct Layout {
 };
 
 bool eom_potentials(const fdf_config& c) { return c.eom == FDF_EOM_EXACT || c.eom == FDF_EOM_CANONICAL; }
+// Slots per mesh cell.  Separable form: grad psi and phi-dot (4) when
+// psi = phi; else grad psi, grad phi and phi-dot (8).  Binary64 meshes drop
+// the phi-dot slot when it is zero (6 slots = three 16-byte loads per
+// corner); bfloat16 meshes keep 8, whose 16-byte cells never straddle a
+// cache line (12-byte cells measured slower).
 int slots_for(const fdf_config& c) {
-  if (c.eom == FDF_EOM_SEPARABLE) return c.slip_amp != 0.0 ? 8 : 4;
+  if (c.eom == FDF_EOM_SEPARABLE) {
+    if (c.slip_amp == 0.0) return 4;
+    const bool f64 = c.precision == FDF_PREC_FP64;
+    return (f64 && c.potential_model != FDF_MODEL_RADMAT) ? 6 : 8;
+  }
   return eom_potentials(c) ? 8 : 4;
 }
 int fft_planes(const fdf_config& c) { return eom_potentials(c) ? 8 : 7; }
@@ -168,6 +177,7 @@ int grid_slot(const fdf_config& c, int quantity) {
   switch (c.eom) {
     case FDF_EOM_SEPARABLE:
       if (slots_for(c) == 8) return quantity <= 5 ? quantity : quantity == 6 ? (tdep ? 6 : -1) : -2;
+      if (slots_for(c) == 6) return quantity <= 5 ? quantity : quantity == 6 ? -1 : -2;
       if (quantity <= 5) return quantity % 3;
       return quantity == 6 ? (tdep ? 3 : -1) : -2;
     case FDF_EOM_EXACT:
@@ -470,7 +480,7 @@ GridBuildArgs grid_recipe(fdf_ctx* c, const FieldRec& f, double a, bool pre_ic_g
         g.kind[n] = SK_PSI; g.slot[n++] = 6;
         g.kind[n] = SK_PHI; g.slot[n++] = 7;
       }
-    } else if (g.nslot == 8) {
+    } else if (g.nslot >= 6) {
       g.kind[n] = SK_DX_PHI; g.slot[n++] = 3;
       g.kind[n] = SK_DY_PHI; g.slot[n++] = 4;
       g.kind[n] = SK_DZ_PHI; g.slot[n++] = 5;

@@ -16,7 +16,8 @@
 // periodic wrap is integer overflow and the cell index is the top log2(G)
 // bits; the momentum is q = q0 + dq with the accumulated kicks dq in binary32
 // (the kicks only ever add to dq, whose rounding is relative to dq, not q);
-// grids are bfloat16 with 8 slots = one 16-byte load per CIC corner.
+// grids are bfloat16 with 8, 6 or 4 slots = one 16-, 12- or 8-byte load per
+// CIC corner.
 // FP64 form: everything binary64; 8 slots = four 16-byte loads per corner.
 //
 // Blocks take contiguous chunks of one species, in an XCD-aware order.
@@ -30,8 +31,14 @@ namespace {
 
 using namespace push_detail;
 
-// Gather of the slots (8-slot: gpsi[3], gphi[3], phidot; 4-slot: gpsi[3], phidot
-// with phi = psi) from a bfloat16 grid.
+// Gather of the slots from a bfloat16 grid: 8-slot cells hold gpsi[3],
+// gphi[3], phidot and a pad (16 bytes), 6-slot cells gpsi[3], gphi[3] with
+// phidot = 0 (12 bytes), 4-slot cells gpsi[3], phidot with phi = psi (8 bytes).
+struct Cell12 { uint32_t x, y, z; };
+template <int NSLOT> struct CellType { using T = uint4; };
+template <> struct CellType<6> { using T = Cell12; };
+template <> struct CellType<4> { using T = uint2; };
+
 // OFF32: the mesh spans less than 4 GiB, so a corner is addressed as a
 // uniform base plus a 32-bit byte offset (one VGPR per corner instead of a
 // 64-bit address).
@@ -49,23 +56,22 @@ template <int NSLOT, int NPT, bool OFF32>
 __device__ __forceinline__ void gather_bf16(const void* grid, const uint32_t* cell, const float* w,
                                             float* g /* 7, accumulated */) {
 #pragma clang fp contract(off)
-  if constexpr (NSLOT == 8) {
-    uint4 v[NPT];
+  using V = typename CellType<NSLOT>::T;
+  V v[NPT];
 #pragma unroll
-    for (int c = 0; c < NPT; ++c) v[c] = load_cell<uint4, OFF32>(grid, cell[c]);
+  for (int c = 0; c < NPT; ++c) v[c] = load_cell<V, OFF32>(grid, cell[c]);
 #pragma unroll
-    for (int c = 0; c < NPT; ++c) {
+  for (int c = 0; c < NPT; ++c) {
+    if constexpr (NSLOT == 8) {
       g[0] = fmaf(w[c], bf16_lo(v[c].x), g[0]); g[1] = fmaf(w[c], bf16_hi(v[c].x), g[1]);
       g[2] = fmaf(w[c], bf16_lo(v[c].y), g[2]); g[3] = fmaf(w[c], bf16_hi(v[c].y), g[3]);
       g[4] = fmaf(w[c], bf16_lo(v[c].z), g[4]); g[5] = fmaf(w[c], bf16_hi(v[c].z), g[5]);
       g[6] = fmaf(w[c], bf16_lo(v[c].w), g[6]);
-    }
-  } else {
-    uint2 v[NPT];
-#pragma unroll
-    for (int c = 0; c < NPT; ++c) v[c] = load_cell<uint2, OFF32>(grid, cell[c]);
-#pragma unroll
-    for (int c = 0; c < NPT; ++c) {
+    } else if constexpr (NSLOT == 6) {
+      g[0] = fmaf(w[c], bf16_lo(v[c].x), g[0]); g[1] = fmaf(w[c], bf16_hi(v[c].x), g[1]);
+      g[2] = fmaf(w[c], bf16_lo(v[c].y), g[2]); g[3] = fmaf(w[c], bf16_hi(v[c].y), g[3]);
+      g[4] = fmaf(w[c], bf16_lo(v[c].z), g[4]); g[5] = fmaf(w[c], bf16_hi(v[c].z), g[5]);
+    } else {
       g[0] = fmaf(w[c], bf16_lo(v[c].x), g[0]); g[1] = fmaf(w[c], bf16_hi(v[c].x), g[1]);
       g[2] = fmaf(w[c], bf16_lo(v[c].y), g[2]); g[6] = fmaf(w[c], bf16_hi(v[c].y), g[6]);
     }
@@ -190,7 +196,13 @@ __device__ __forceinline__ void gather_f64(const void* grid, const uint32_t* cel
 #pragma clang fp contract(off)
 #pragma unroll
   for (int c = 0; c < NPT; ++c) {
-    if constexpr (NSLOT == 8) {
+    if constexpr (NSLOT == 6) {
+      const double2 v0 = load_piece_f64<6, OFF32>(grid, cell[c], 0);
+      const double2 v1 = load_piece_f64<6, OFF32>(grid, cell[c], 1);
+      const double2 v2 = load_piece_f64<6, OFF32>(grid, cell[c], 2);
+      g[0] = fma(w[c], v0.x, g[0]); g[1] = fma(w[c], v0.y, g[1]); g[2] = fma(w[c], v1.x, g[2]);
+      g[3] = fma(w[c], v1.y, g[3]); g[4] = fma(w[c], v2.x, g[4]); g[5] = fma(w[c], v2.y, g[5]);
+    } else if constexpr (NSLOT == 8) {
       const double2 v0 = load_piece_f64<8, OFF32>(grid, cell[c], 0);
       const double2 v1 = load_piece_f64<8, OFF32>(grid, cell[c], 1);
       const double2 v2 = load_piece_f64<8, OFF32>(grid, cell[c], 2);
@@ -318,17 +330,21 @@ void push_launch(const PushArgs& a, hipStream_t s) {
   if (a.fp64) {
     if (off32) {
       if (a.nslot == 8) hipLaunchKernelGGL((k_push_f64<8, PPT, BLEND, TSC, true>), grid, block, 0, s, a);
+      else if (a.nslot == 6) hipLaunchKernelGGL((k_push_f64<6, PPT, BLEND, TSC, true>), grid, block, 0, s, a);
       else hipLaunchKernelGGL((k_push_f64<4, PPT, BLEND, TSC, true>), grid, block, 0, s, a);
     } else {
       if (a.nslot == 8) hipLaunchKernelGGL((k_push_f64<8, PPT, BLEND, TSC, false>), grid, block, 0, s, a);
+      else if (a.nslot == 6) hipLaunchKernelGGL((k_push_f64<6, PPT, BLEND, TSC, false>), grid, block, 0, s, a);
       else hipLaunchKernelGGL((k_push_f64<4, PPT, BLEND, TSC, false>), grid, block, 0, s, a);
     }
   } else {
     if (off32) {
       if (a.nslot == 8) hipLaunchKernelGGL((k_push_f32<8, PPT, BLEND, TSC, true>), grid, block, 0, s, a);
+      else if (a.nslot == 6) hipLaunchKernelGGL((k_push_f32<6, PPT, BLEND, TSC, true>), grid, block, 0, s, a);
       else hipLaunchKernelGGL((k_push_f32<4, PPT, BLEND, TSC, true>), grid, block, 0, s, a);
     } else {
       if (a.nslot == 8) hipLaunchKernelGGL((k_push_f32<8, PPT, BLEND, TSC, false>), grid, block, 0, s, a);
+      else if (a.nslot == 6) hipLaunchKernelGGL((k_push_f32<6, PPT, BLEND, TSC, false>), grid, block, 0, s, a);
       else hipLaunchKernelGGL((k_push_f32<4, PPT, BLEND, TSC, false>), grid, block, 0, s, a);
     }
   }
