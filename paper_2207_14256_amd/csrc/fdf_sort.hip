@@ -100,14 +100,19 @@ __global__ void __launch_bounds__(kRankThreads) k_sort_rank(SortArgs a) {
   const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
   const int64_t i0 = blk * kRankBlock;
   const int tid = threadIdx.x;
-  uint64_t v[4];
+  // keys read coalesced (element tid + 256 r), then regrouped through LDS so
+  // that thread t holds elements 4t .. 4t + 3
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    const int e = 4 * tid + r;
+    const int e = tid + kRankThreads * r;
     const int64_t i = i0 + e;
     const uint64_t key = i < a.seg.n ? (uint64_t)full_key(a, i) : 0xFFFFFFFFull;
-    v[r] = (key << 10) | (uint64_t)e;
+    kv[e] = (key << 10) | (uint64_t)e;
   }
+  __syncthreads();
+  uint64_t v[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) v[r] = kv[4 * tid + r];
   // element e = 4 tid + r keeps the smaller of its pair exactly when it is the
   // lower index of an ascending pair or the upper index of a descending one
 #pragma unroll
@@ -220,6 +225,27 @@ __device__ __forceinline__ void move_array(const T* __restrict__ src, T* __restr
   __syncthreads();
 }
 
+// Two 4-byte arrays per LDS round (the same 8 KB as one 8-byte array).
+__device__ __forceinline__ void move_pair(const uint32_t* __restrict__ s0, uint32_t* __restrict__ d0,
+                                          const uint32_t* __restrict__ s1, uint32_t* __restrict__ d1,
+                                          uint32_t* lds, int64_t i0, int cnt, const int* sidx,
+                                          const uint32_t* pos) {
+  for (int e = threadIdx.x; e < cnt; e += 256) {
+    lds[e] = s0[i0 + e];
+    lds[kRankBlock + e] = s1[i0 + e];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kRankBlock / 256; ++r) {
+    const int e = threadIdx.x + r * 256;
+    if (e < cnt) {
+      d0[pos[r]] = lds[sidx[r]];
+      d1[pos[r]] = lds[kRankBlock + sidx[r]];
+    }
+  }
+  __syncthreads();
+}
+
 __global__ void __launch_bounds__(256) k_sort_move(SortArgs a) {
   __shared__ uint64_t lds_raw[kRankBlock];
   const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
@@ -245,15 +271,17 @@ __global__ void __launch_bounds__(256) k_sort_move(SortArgs a) {
       move_array(s.qd[k], d.qd[k], l, i0, cnt, sidx, pos);
       move_array(s.q0d[k], d.q0d[k], l, i0, cnt, sidx, pos);
     }
+    move_array(s.id, d.id, (uint32_t*)lds_raw, i0, cnt, sidx, pos);
   } else {
     uint32_t* l = (uint32_t*)lds_raw;
-    for (int k = 0; k < 3; ++k) {
-      move_array(s.xu[k], d.xu[k], l, i0, cnt, sidx, pos);
-      move_array((const uint32_t*)s.q0f[k], (uint32_t*)d.q0f[k], l, i0, cnt, sidx, pos);
-      move_array((const uint32_t*)s.dqf[k], (uint32_t*)d.dqf[k], l, i0, cnt, sidx, pos);
-    }
+    const uint32_t* sa[10] = {s.xu[0], s.xu[1], s.xu[2],
+                              (const uint32_t*)s.q0f[0], (const uint32_t*)s.q0f[1], (const uint32_t*)s.q0f[2],
+                              (const uint32_t*)s.dqf[0], (const uint32_t*)s.dqf[1], (const uint32_t*)s.dqf[2], s.id};
+    uint32_t* da[10] = {d.xu[0], d.xu[1], d.xu[2], (uint32_t*)d.q0f[0], (uint32_t*)d.q0f[1],
+                        (uint32_t*)d.q0f[2], (uint32_t*)d.dqf[0], (uint32_t*)d.dqf[1], (uint32_t*)d.dqf[2], d.id};
+#pragma unroll
+    for (int k = 0; k < 10; k += 2) move_pair(sa[k], da[k], sa[k + 1], da[k + 1], l, i0, cnt, sidx, pos);
   }
-  move_array(s.id, d.id, (uint32_t*)lds_raw, i0, cnt, sidx, pos);
 }
 
 // ------------------------------------------------- exclusive scan (uint32) --
