@@ -177,6 +177,12 @@ typedef struct fdf_tuning {
                                     middle of the interval until the next re-sort
                                     (halves the spread of neighbours); 0: by the
                                     current positions */
+  int32_t sort_fused;            /* 1: FP32 separable form -- a re-sort after the
+                                    first is carried out by the push of that step,
+                                    which writes the updated state in sorted order
+                                    (no separate move pass; results bit-identical;
+                                    the default); 0: rank + move passes, then
+                                    the push */
 } fdf_tuning;
 
 /* ---- lifetime -------------------------------------------------------------- */

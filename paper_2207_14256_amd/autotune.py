@@ -64,7 +64,8 @@ def autotune(cfg, path=CACHE_PATH, log=print, full_schedule=True):
     ctx = fastdf.Context(cfg)
     sorting = cfg.get("sort_every", 0) > 0
     base = dict(particles_per_thread=4, sort_tiles=0, sort_every=cfg.get("sort_every", 0),
-                sort_cells=2.0 if sorting else 0.0, persistent_blocks=0, use_graph=0, sort_predict=1)
+                sort_cells=2.0 if sorting else 0.0, persistent_blocks=0, use_graph=0, sort_predict=1,
+                sort_fused=1)
     # 1. launch shape
     best, best_ms = None, float("inf")
     short = min(40, cfg["n_steps"])
@@ -81,7 +82,7 @@ def autotune(cfg, path=CACHE_PATH, log=print, full_schedule=True):
         best_wall = float("inf")
         chosen = best
         for tiles in sorted({max(1, G // 8), max(1, G // 4), min(256, max(1, G // 2))}):
-            for cells in (2.0, 4.0, 6.0):
+            for cells in (2.0, 3.0, 4.0, 6.0):
                 t = dict(best, sort_tiles=min(tiles, 256), sort_cells=cells)
                 r = _run(ctx, cfg, t, cfg["n_steps"])
                 log("[autotune] tiles=%d cells=%.1f: %.3f s (push %.3f ms, %d sorts, %.0f ms sorting)" % (

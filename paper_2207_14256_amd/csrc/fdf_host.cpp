@@ -335,6 +335,7 @@ struct fdf_ctx {
   int persistent = 0;       // push grid size when > 0 (a multiple of 8)
   bool use_graph = false;   // capture step sequences into hipGraphs
   bool sort_predict = true; // sort keys from positions extrapolated to mid-interval
+  bool sort_fused = true;   // FP32 separable: re-sorts after the first ride on the push
   hipStream_t cap_stream = nullptr;   // private stream used only for graph capture
   hipStream_t launch_stream = nullptr;  // stream kernels are enqueued on right now
   std::vector<GraphRec> graphs;       // captured step sequences
@@ -555,32 +556,64 @@ double typical_drift_cells(fdf_ctx* c, double dt, double a) {
 
 // Spatial re-sort of every species into its other buffer copy, ordered by
 // the positions extrapolated by predict_tau at scale factor a_pred.
-int sort_species(fdf_ctx* c, double predict_tau, double a_pred) {
+SortArgs sort_args(fdf_ctx* c, const SpeciesRec& s, double predict_tau, double a_pred) {
   const int tiles = sort_tiles_of(c);
+  SortArgs a{};
+  a.seg = s.seg[s.cur];
+  a.dst = s.seg[s.cur ^ 1];
+  a.predict_tau = predict_tau;
+  a.ma = s.m * a_pred;
+  a.fp64 = c->cfg.precision == FDF_PREC_FP64;
+  a.grid_n = c->cfg.grid_n;
+  a.cell_shift = 32 - ilog2(c->cfg.grid_n);
+  a.fine_bits = ilog2(c->cfg.grid_n / tiles);
+  a.box = c->cfg.box_mpc;
+  a.nkeys = (int64_t)tiles * tiles * tiles;
+  a.count = (uint32_t*)(c->ws + c->lay.sort_count);
+  a.scan_scratch = (uint32_t*)(c->ws + c->lay.sort_scan);
+  a.rank = (uint32_t*)(c->ws + c->lay.sort_rank);
+  a.bucket = (uint32_t*)(c->ws + c->lay.sort_bucket);
+  a.src = (uint32_t*)(c->ws + c->lay.sort_src);
+  return a;
+}
+
+int sort_species(fdf_ctx* c, double predict_tau, double a_pred) {
   std::pair<hipEvent_t, hipEvent_t> ev;
   timing_begin(c, FDF_KERNEL_SORT, &ev);
   for (auto& s : c->species) {
-    SortArgs a{};
-    a.seg = s.seg[s.cur];
-    a.dst = s.seg[s.cur ^ 1];
-    a.predict_tau = predict_tau;
-    a.ma = s.m * a_pred;
-    a.fp64 = c->cfg.precision == FDF_PREC_FP64;
-    a.grid_n = c->cfg.grid_n;
-    a.cell_shift = 32 - ilog2(c->cfg.grid_n);
-    a.fine_bits = ilog2(c->cfg.grid_n / tiles);
-    a.box = c->cfg.box_mpc;
-    a.nkeys = (int64_t)tiles * tiles * tiles;
-    a.count = (uint32_t*)(c->ws + c->lay.sort_count);
-    a.scan_scratch = (uint32_t*)(c->ws + c->lay.sort_scan);
-    a.rank = (uint32_t*)(c->ws + c->lay.sort_rank);
-    a.bucket = (uint32_t*)(c->ws + c->lay.sort_bucket);
-    a.src = (uint32_t*)(c->ws + c->lay.sort_src);
-    launch_sort(a, stream_of(c));
+    launch_sort(sort_args(c, s, predict_tau, a_pred), stream_of(c));
     s.cur ^= 1;
   }
   timing_end(c, FDF_KERNEL_SORT, ev);
   return launched(c, "sort");
+}
+
+// A re-sort carried out by the push of the step: per species, the rank pass
+// and scan, then the push that writes the updated state in sorted order into
+// the other copy (pa describes the step's push; its segment tables are
+// indexed per species here).  Timed as a sort.
+int sort_push_species(fdf_ctx* c, double predict_tau, double a_pred, const PushArgs& pa, size_t table) {
+  std::pair<hipEvent_t, hipEvent_t> ev;
+  timing_begin(c, FDF_KERNEL_SORT, &ev);
+  for (size_t i = 0; i < c->species.size(); ++i) {
+    SpeciesRec& s = c->species[i];
+    const SortArgs a = sort_args(c, s, predict_tau, a_pred);
+    launch_sort_rank(a, stream_of(c));
+    PushArgs p = pa;
+    p.seg = (const Segment*)(c->ws + c->lay.seg + s.cur * table) + i;
+    p.dseg = (const Segment*)(c->ws + c->lay.seg + (s.cur ^ 1) * table) + i;
+    p.nseg = 1;
+    p.total_chunks = (s.n + kSortBlock - 1) / kSortBlock;
+    p.persistent = 0;
+    p.sort_src = a.src;
+    p.sort_rank = a.rank;
+    p.sort_bucket = a.bucket;
+    p.sort_start = a.count;
+    launch_push_sort(p, stream_of(c));
+    s.cur ^= 1;
+  }
+  timing_end(c, FDF_KERNEL_SORT, ev);
+  return launched(c, "sort + push");
 }
 
 int64_t total_chunks(fdf_ctx* c) {
@@ -933,6 +966,37 @@ int enqueue_steps(fdf_ctx* c, int32_t n) {
   pa.do_kick = 1;
   pa.eom = c->cfg.eom;
   pa.tsc = c->cfg.interp_order == 2;
+  // does the launch at integer time u re-sort first?
+  auto sort_due = [&](int u) {
+    if (c->sort_cells > 0) return !c->sorted_once || c->drift_cells >= c->sort_cells;
+    return sort_every > 0 && u % sort_every == 0;
+  };
+  // the interval until the next re-sort after one at u (as the cadence will
+  // decide it): half its conformal time and the scale factor at its middle
+  auto sort_prediction = [&](int u0, double* tau, double* amid) {
+    double span = 0.0, cells = 0.0;
+    int steps = 0;
+    std::vector<std::pair<double, double>> iv;   // (drift, a) of the steps in the interval
+    const bool fwd = n > 0;
+    for (int u = u0; ; u += fwd ? 1 : -1) {
+      if (fwd ? u >= c->cfg.n_steps : u <= 0) break;
+      const double dr = fwd ? c->drift[u] : -c->drift[u - 1];
+      const double ah = fwd ? c->a_half[u] : c->a_half[u - 1];
+      iv.push_back({dr, ah});
+      span += dr;
+      cells += typical_drift_cells(c, dr, ah);
+      ++steps;
+      if (c->sort_cells > 0 ? cells >= c->sort_cells : steps >= std::max(sort_every, 1)) break;
+    }
+    double half = 0.0;
+    *amid = c->a[u0];
+    for (const auto& e : iv) {
+      if (std::fabs(half + e.first) > 0.5 * std::fabs(span)) { *amid = e.second; break; }
+      half += e.first;
+      *amid = e.second;
+    }
+    *tau = c->sort_predict ? 0.5 * span : 0.0;
+  };
   for (int j = 0; j <= nabs; ++j) {
     int t;            // integer time of this launch's kick
     double kclose = 0, kopen = 0, drift = 0, a_drift = 0;   // half-kicks ending / starting at t
@@ -989,39 +1053,16 @@ int enqueue_steps(fdf_ctx* c, int32_t n) {
         }
       }
     }
+    bool fused_sort = false;    // this step's push also performs the re-sort
+    double tau_pred = 0.0, a_mid = 0.0;
     if (j < nabs) {
-      bool do_sort = false;
-      if (c->sort_cells > 0) {
-        do_sort = !c->sorted_once || c->drift_cells >= c->sort_cells;
-      } else if (sort_every > 0) {
-        do_sort = t % sort_every == 0;
-      }
-      if (do_sort) {
-        // the interval until the next re-sort (as the cadence will decide
-        // it) and the conformal time and scale factor at its middle
-        double span = 0.0, cells = 0.0;
-        int steps = 0;
-        std::vector<std::pair<double, double>> iv;   // (drift, a) of the steps in the interval
-        for (int u = t; ; u += n > 0 ? 1 : -1) {
-          const bool fwd = n > 0;
-          if (fwd ? u >= c->cfg.n_steps : u <= 0) break;
-          const double dr = fwd ? c->drift[u] : -c->drift[u - 1];
-          const double ah = fwd ? c->a_half[u] : c->a_half[u - 1];
-          iv.push_back({dr, ah});
-          span += dr;
-          cells += typical_drift_cells(c, dr, ah);
-          ++steps;
-          if (c->sort_cells > 0 ? cells >= c->sort_cells : steps >= std::max(sort_every, 1)) break;
-        }
-        double half = 0.0, a_mid = c->a[t];
-        for (const auto& e : iv) {
-          if (std::fabs(half + e.first) > 0.5 * std::fabs(span)) { a_mid = e.second; break; }
-          half += e.first;
-          a_mid = e.second;
-        }
-        const double tau_pred = c->sort_predict ? 0.5 * span : 0.0;
-        rc = sort_species(c, tau_pred, a_mid);
-        if (!rc && !c->sorted_once) rc = sort_species(c, tau_pred, a_mid);   // second pass orders cells in buckets
+      if (sort_due(t)) {
+        sort_prediction(t, &tau_pred, &a_mid);
+        // the first sort takes two passes (the second orders cells in buckets)
+        const int passes = c->sorted_once ? 1 : 2;
+        fused_sort = c->sort_fused && !pa.fp64 && pa.eom == FDF_EOM_SEPARABLE;
+        for (int pass = 0; pass < passes - (fused_sort ? 1 : 0) && !rc; ++pass)
+          rc = sort_species(c, tau_pred, a_mid);
         if (rc) return rc;
         c->sorted_once = true;
         c->drift_cells = 0;
@@ -1035,6 +1076,11 @@ int enqueue_steps(fdf_ctx* c, int32_t n) {
     pa.do_drift = j < nabs;
     pa.drift = drift;
     pa.a_drift = a_drift;
+    if (fused_sort) {
+      rc = sort_push_species(c, tau_pred, a_mid, pa, table);
+      if (rc) return rc;
+      continue;
+    }
     std::pair<hipEvent_t, hipEvent_t> ev;
     timing_begin(c, FDF_KERNEL_PUSH, &ev);
     launch_push(pa, stream_of(c));
@@ -1458,6 +1504,7 @@ int fdf_get_tuning(const fdf_ctx* c, fdf_tuning* t) {
   t->persistent_blocks = c->persistent;
   t->use_graph = c->use_graph ? 1 : 0;
   t->sort_predict = c->sort_predict ? 1 : 0;
+  t->sort_fused = c->sort_fused ? 1 : 0;
   return FDF_OK;
 }
 
@@ -1476,6 +1523,7 @@ int fdf_set_tuning(fdf_ctx* c, const fdf_tuning* t) {
     return fail(c, FDF_ERR_ARG, "persistent_blocks must be 0 or a positive multiple of 8");
   if (t->use_graph != 0 && t->use_graph != 1) return fail(c, FDF_ERR_ARG, "use_graph must be 0 or 1");
   if (t->sort_predict != 0 && t->sort_predict != 1) return fail(c, FDF_ERR_ARG, "sort_predict must be 0 or 1");
+  if (t->sort_fused != 0 && t->sort_fused != 1) return fail(c, FDF_ERR_ARG, "sort_fused must be 0 or 1");
   if (p != c->ppt) c->seg_dirty = true;   // chunk boundaries depend on the block size
   clear_graphs(c);
   c->persistent = t->persistent_blocks;
@@ -1485,6 +1533,7 @@ int fdf_set_tuning(fdf_ctx* c, const fdf_tuning* t) {
   c->sort_every = t->sort_every;
   c->sort_cells = t->sort_cells;
   c->sort_predict = t->sort_predict != 0;
+  c->sort_fused = t->sort_fused != 0;
   return FDF_OK;
 }
 

@@ -105,7 +105,18 @@ struct PushArgs {
   int32_t blend;           // 1: interpolate two grid sets (super-steps)
   int32_t grid_sel;        // which set holds the earlier anchor: 0 = grid, 1 = grid2
   double blend_t;          // interpolation weight of the later anchor
+  // push fused with the move of a re-sort (launch_push_sort; FP32 separable
+  // form, one species: seg and dseg point at its entry in the two tables,
+  // total_chunks counts its kSortBlock-particle rank blocks)
+  const Segment* dseg;     // destination copy
+  const uint32_t* sort_src;     // rank pass outputs (SortArgs::src, rank, bucket)
+  const uint32_t* sort_rank;
+  const uint32_t* sort_bucket;
+  const uint32_t* sort_start;   // bucket starts (the scanned counts)
 };
+
+// Particles per block of the sort's rank pass.
+constexpr int kSortBlock = 1024;
 
 struct SortArgs {
   Segment seg;             // source copy
@@ -194,6 +205,8 @@ void launch_bin_accumulated(const PkArgs& a, hipStream_t s);
 void launch_fill_zero(void* ptr, size_t bytes, hipStream_t s);
 int push_chunk_particles(int ppt);
 void launch_sort(const SortArgs& a, hipStream_t s);
+void launch_sort_rank(const SortArgs& a, hipStream_t s);   // counts, rank pass and scan, no move
+void launch_push_sort(const PushArgs& a, hipStream_t s);
 size_t sort_scan_scratch_words(int64_t nkeys);
 
 }  // namespace fdf

@@ -90,33 +90,91 @@ __device__ __forceinline__ void gather_stencil_bf16(const void* grid, const uint
   }
 }
 
-// Every floating-point operation of the per-particle update is written out
-// (explicit fmaf, no contraction) so that the unrolled copies of the loop are
-// instruction-identical: a particle gets bit-identical results in whichever
-// slot of whichever block it lands after a re-sort.
-template <int NSLOT, int PPT, bool BLEND, bool TSC, bool OFF32>
-__device__ __forceinline__ void push_chunk_f32(const PushArgs& a, int64_t chunk) {
-#pragma clang fp contract(off)
-  constexpr int NP = Stencil<TSC>::N;
-  const int s = find_segment(a.seg, a.nseg, chunk);
-  const Segment& sg = a.seg[s];
-  const int64_t n = sg.n;
-  const int64_t first = (chunk - sg.chunk_begin) * (int64_t)(kBlock * PPT) + threadIdx.x;
-  const int shift = 32 - a.log2g;
-  const uint32_t gmask = (uint32_t)a.G - 1u;
-  const float finv = __uint_as_float((uint32_t)(127 - shift) << 23);   // 2^-shift
-  const float kick = (float)a.kick;
+// Launch constants of the FP32 update of one segment.
+struct ConstF32 {
+  int shift;
+  uint32_t gmask, G;
+  float finv, kick, ma2, mah2, dscale, ta, tb;
+  const void* gridA;
+  const void* gridB;
+};
+
+template <bool BLEND>
+__device__ __forceinline__ ConstF32 const_f32(const PushArgs& a, const Segment& sg) {
+  ConstF32 k;
+  k.shift = 32 - a.log2g;
+  k.gmask = (uint32_t)a.G - 1u;
+  k.G = (uint32_t)a.G;
+  k.finv = __uint_as_float((uint32_t)(127 - k.shift) << 23);   // 2^-shift
+  k.kick = (float)a.kick;
   const float ma = (float)(sg.m * a.a_kick);
   const float mah = (float)(sg.m * a.a_drift);
-  const float ma2 = ma * ma, mah2 = mah * mah;
-  const float dscale = (float)(a.drift * 4294967296.0 / a.box);
-  const uint32_t G = (uint32_t)a.G;
-  const void* gridA = (BLEND && a.grid_sel) ? sg.grid2 : sg.grid;
-  const void* gridB = (BLEND && a.grid_sel) ? sg.grid : sg.grid2;
-  const float tb = (float)a.blend_t, ta = 1.0f - tb;
+  k.ma2 = ma * ma;
+  k.mah2 = mah * mah;
+  k.dscale = (float)(a.drift * 4294967296.0 / a.box);
+  k.gridA = (BLEND && a.grid_sel) ? sg.grid2 : sg.grid;
+  k.gridB = (BLEND && a.grid_sel) ? sg.grid : sg.grid2;
+  k.tb = (float)a.blend_t;
+  k.ta = 1.0f - k.tb;
+  return k;
+}
+
+// The FP32 update of one particle: gather, separable kick into dq, drift of
+// the fixed-point position.  Every floating-point operation is written out
+// (explicit fmaf, no contraction) so that every copy of this code is
+// instruction-identical: a particle gets bit-identical results in whichever
+// slot of whichever block, and whichever kernel, it is updated.
+template <int NSLOT, bool BLEND, bool TSC, bool OFF32>
+__device__ __forceinline__ void update_f32(const ConstF32& k, bool drift, uint32_t* xu, const float* q0,
+                                           float* dq) {
+#pragma clang fp contract(off)
+  constexpr int NP = Stencil<TSC>::N;
+  uint32_t cell[NP];
+  float w[NP];
+  stencil_u32<TSC>(xu, k.shift, k.gmask, k.finv, k.G, cell, w);
+  float g[7] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+  if (BLEND) {   // super-steps: (1 - t) G_A + t G_B folded into the weights
+    float wa[NP], wb[NP];
+#pragma unroll
+    for (int cc = 0; cc < NP; ++cc) { wa[cc] = k.ta * w[cc]; wb[cc] = k.tb * w[cc]; }
+    gather_stencil_bf16<NSLOT, TSC, OFF32>(k.gridA, cell, wa, g);
+    gather_stencil_bf16<NSLOT, TSC, OFF32>(k.gridB, cell, wb, g);
+  } else {
+    gather_stencil_bf16<NSLOT, TSC, OFF32>(k.gridA, cell, w, g);
+  }
+  if (NSLOT == 4) { g[3] = g[0]; g[4] = g[1]; g[5] = g[2]; }
+  // separable force of eq. releq_approx
+  const float q0sq = fmaf(q0[0], q0[0], fmaf(q0[1], q0[1], q0[2] * q0[2]));
+  const float e0 = sqrtf(q0sq + k.ma2);
+  const float ie0 = 1.0f / e0;
+  const float q0g = fmaf(q0[0], g[3], fmaf(q0[1], g[4], q0[2] * g[5]));
+  const float qg = fmaf(q0g, ie0, g[6]);          // (q0 . grad phi)/eps0 + phidot
+  const float cphi = q0sq * ie0;                    // q0^2 / eps0
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const float F = fmaf(q0[d], qg, fmaf(-cphi, g[3 + d], -(e0 * g[d])));
+    dq[d] = fmaf(k.kick, F, dq[d]);
+  }
+  if (drift) {
+    float q[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) q[d] = q0[d] + dq[d];
+    const float qq = fmaf(q[0], q[0], fmaf(q[1], q[1], q[2] * q[2]));
+    const float ie = 1.0f / sqrtf(qq + k.mah2);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) xu[d] += (uint32_t)__float2int_rn(k.dscale * (q[d] * ie));
+  }
+}
+
+template <int NSLOT, int PPT, bool BLEND, bool TSC, bool OFF32>
+__device__ __forceinline__ void push_chunk_f32(const PushArgs& a, int64_t chunk) {
+  const int s = find_segment(a.seg, a.nseg, chunk);
+  const Segment& sg = a.seg[s];
+  const ConstF32 k = const_f32<BLEND>(a, sg);
+  const int64_t first = (chunk - sg.chunk_begin) * (int64_t)(kBlock * PPT) + threadIdx.x;
   // chunk-relative arrays: a uniform base and a 32-bit lane index
   const int64_t c0 = first - threadIdx.x;
-  const int64_t left = n - c0;
+  const int64_t left = sg.n - c0;
   uint32_t* X[3];
   const float* Q0[3];
   float* DQ[3];
@@ -135,47 +193,81 @@ __device__ __forceinline__ void push_chunk_f32(const PushArgs& a, int64_t chunk)
       q0[d] = ldnt(&Q0[d][i]);
       dq[d] = ldnt(&DQ[d][i]);
     }
-    // interpolation stencil from the fixed-point position
-    uint32_t cell[NP];
-    float w[NP];
-    stencil_u32<TSC>(xu, shift, gmask, finv, G, cell, w);
-    float g[7] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-    if (BLEND) {   // super-steps: (1 - t) G_A + t G_B folded into the weights
-      float wa[NP], wb[NP];
-#pragma unroll
-      for (int cc = 0; cc < NP; ++cc) { wa[cc] = ta * w[cc]; wb[cc] = tb * w[cc]; }
-      gather_stencil_bf16<NSLOT, TSC, OFF32>(gridA, cell, wa, g);
-      gather_stencil_bf16<NSLOT, TSC, OFF32>(gridB, cell, wb, g);
-    } else {
-      gather_stencil_bf16<NSLOT, TSC, OFF32>(gridA, cell, w, g);
-    }
-    if (NSLOT == 4) { g[3] = g[0]; g[4] = g[1]; g[5] = g[2]; }
-    // separable force of eq. releq_approx
-    const float q0sq = fmaf(q0[0], q0[0], fmaf(q0[1], q0[1], q0[2] * q0[2]));
-    const float e0 = sqrtf(q0sq + ma2);
-    const float ie0 = 1.0f / e0;
-    const float q0g = fmaf(q0[0], g[3], fmaf(q0[1], g[4], q0[2] * g[5]));
-    const float qg = fmaf(q0g, ie0, g[6]);          // (q0 . grad phi)/eps0 + phidot
-    const float cphi = q0sq * ie0;                    // q0^2 / eps0
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      const float F = fmaf(q0[d], qg, fmaf(-cphi, g[3 + d], -(e0 * g[d])));
-      dq[d] = fmaf(kick, F, dq[d]);
-    }
+    update_f32<NSLOT, BLEND, TSC, OFF32>(k, a.do_drift != 0, xu, q0, dq);
     if (a.do_drift) {
-      float q[3];
 #pragma unroll
-      for (int d = 0; d < 3; ++d) q[d] = q0[d] + dq[d];
-      const float qq = fmaf(q[0], q[0], fmaf(q[1], q[1], q[2] * q[2]));
-      const float ie = 1.0f / sqrtf(qq + mah2);
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        const int disp = __float2int_rn(dscale * (q[d] * ie));
-        stnt(xu[d] + (uint32_t)disp, &X[d][i]);
-      }
+      for (int d = 0; d < 3; ++d) stnt(xu[d], &X[d][i]);
     }
 #pragma unroll
     for (int d = 0; d < 3; ++d) stnt(dq[d], &DQ[d][i]);
+  }
+}
+
+// A push that also performs a re-sort of one species whose rank pass has run:
+// one block per rank block of kSortBlock particles.  The block reads its
+// particles in place (coalesced), updates them, stages the whole new state in
+// LDS and writes it out in sorted order, element e of the sorted run to
+// start[bucket[e]] + rank[e] of the other buffer copy, so consecutive threads
+// write consecutive slots of a bucket fragment.  The re-sort then costs the
+// push the writes of q0 and id and the index reads, instead of a pass of its
+// own over the whole state.
+constexpr int kFusedThreads = 512;   // 8 waves per block; 40 KB of LDS leaves 8 waves per SIMD
+
+template <int NSLOT, bool BLEND, bool TSC, bool OFF32>
+__global__ void __launch_bounds__(kFusedThreads) k_push_sort_f32(PushArgs a) {
+  constexpr int kPer = kSortBlock / kFusedThreads;
+  __shared__ uint32_t st[10][kSortBlock];
+  const Segment& sg = a.seg[0];
+  const Segment& ds = a.dseg[0];
+  const ConstF32 k = const_f32<BLEND>(a, sg);
+  const int64_t i0 = xcd_chunk(blockIdx.x, gridDim.x) * (int64_t)kSortBlock;
+  const int cnt = (int)min<int64_t>(kSortBlock, sg.n - i0);
+#pragma unroll
+  for (int r = 0; r < kPer; ++r) {
+    const int e = threadIdx.x + r * kFusedThreads;
+    if (e >= cnt) break;
+    const int64_t i = i0 + e;
+    uint32_t xu[3];
+    float dq[3], q0[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      xu[d] = ldnt(&sg.xu[d][i]);
+      q0[d] = ldnt(&sg.q0f[d][i]);
+      dq[d] = ldnt(&sg.dqf[d][i]);
+    }
+    update_f32<NSLOT, BLEND, TSC, OFF32>(k, true, xu, q0, dq);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      st[d][e] = xu[d];
+      st[3 + d][e] = __float_as_uint(q0[d]);
+      st[6 + d][e] = __float_as_uint(dq[d]);
+    }
+    st[9][e] = ldnt(&sg.id[i]);
+  }
+  // destinations of the sorted elements this thread writes
+  uint32_t src[kPer];
+  int64_t dst[kPer];
+#pragma unroll
+  for (int r = 0; r < kPer; ++r) {
+    const int e = threadIdx.x + r * kFusedThreads;
+    if (e < cnt) {
+      const int64_t o = i0 + e;                // element of the sorted order
+      src[r] = ldnt(&a.sort_src[o]);
+      dst[r] = (int64_t)a.sort_start[ldnt(&a.sort_bucket[o])] + ldnt(&a.sort_rank[o]);
+    }
+  }
+  __syncthreads();
+  // one array at a time, with cached stores: the fragments that neighbouring
+  // blocks write into a bucket merge into whole lines in L2
+  uint32_t* out[10] = {ds.xu[0], ds.xu[1], ds.xu[2], (uint32_t*)ds.q0f[0], (uint32_t*)ds.q0f[1],
+                       (uint32_t*)ds.q0f[2], (uint32_t*)ds.dqf[0], (uint32_t*)ds.dqf[1], (uint32_t*)ds.dqf[2], ds.id};
+#pragma unroll
+  for (int k = 0; k < 10; ++k) {
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) {
+      const int e = threadIdx.x + r * kFusedThreads;
+      if (e < cnt) out[k][dst[r]] = st[k][src[r]];
+    }
   }
 }
 
@@ -350,6 +442,21 @@ void push_launch(const PushArgs& a, hipStream_t s) {
   }
 }
 
+template <bool BLEND, bool TSC>
+void push_sort_launch(const PushArgs& a, hipStream_t s) {
+  const dim3 grid((unsigned)a.total_chunks), block(kFusedThreads);
+  const bool off32 = (uint64_t)a.G * a.G * a.G * (uint64_t)(a.nslot * 2) <= (1ull << 32);
+  if (off32) {
+    if (a.nslot == 8) hipLaunchKernelGGL((k_push_sort_f32<8, BLEND, TSC, true>), grid, block, 0, s, a);
+    else if (a.nslot == 6) hipLaunchKernelGGL((k_push_sort_f32<6, BLEND, TSC, true>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_push_sort_f32<4, BLEND, TSC, true>), grid, block, 0, s, a);
+  } else {
+    if (a.nslot == 8) hipLaunchKernelGGL((k_push_sort_f32<8, BLEND, TSC, false>), grid, block, 0, s, a);
+    else if (a.nslot == 6) hipLaunchKernelGGL((k_push_sort_f32<6, BLEND, TSC, false>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_push_sort_f32<4, BLEND, TSC, false>), grid, block, 0, s, a);
+  }
+}
+
 template <int PPT>
 void push_ppt(const PushArgs& a, hipStream_t s) {
   if (a.tsc) {
@@ -364,6 +471,16 @@ void push_ppt(const PushArgs& a, hipStream_t s) {
 }  // namespace
 
 int push_chunk_particles(int ppt) { return kBlock * ppt; }
+
+void launch_push_sort(const PushArgs& a, hipStream_t s) {
+  if (a.tsc) {
+    if (a.blend) push_sort_launch<true, true>(a, s);
+    else push_sort_launch<false, true>(a, s);
+  } else {
+    if (a.blend) push_sort_launch<true, false>(a, s);
+    else push_sort_launch<false, false>(a, s);
+  }
+}
 
 void launch_push(const PushArgs& a, hipStream_t s) {
   if (a.eom != 0) { launch_push_eom(a, s); return; }

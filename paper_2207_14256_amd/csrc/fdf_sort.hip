@@ -71,7 +71,7 @@ __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb) {
 }
 
 constexpr int kRankThreads = 256;
-constexpr int kRankBlock = 1024;          // particles per block
+constexpr int kRankBlock = kSortBlock;    // particles per block
 constexpr uint64_t kIdxMask = kRankBlock - 1;
 
 
@@ -87,10 +87,10 @@ __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int mask) {
 // a thread swap in registers, partners within a wave meet through lane
 // shuffles, and only the three stages that cross waves go through LDS), cuts
 // the sorted run into segments of equal bucket, and reserves one contiguous
-// range per segment with a single atomicAdd on the bucket count.  Each
-// particle's rank inside its bucket and its bucket are written in source
-// order.  The fragment a block writes into a bucket is therefore contiguous
-// and ordered by cell.
+// range per segment with a single atomicAdd on the bucket count.  For each
+// element of the block's sorted run its source slot, bucket and rank inside
+// the bucket are written at its sorted position.  The fragment a block writes
+// into a bucket is therefore contiguous and ordered by cell.
 __global__ void __launch_bounds__(kRankThreads) k_sort_rank(SortArgs a) {
   static_assert(kRankBlock == 4 * kRankThreads, "four elements per thread");
   __shared__ uint64_t kv[kRankBlock];
@@ -350,11 +350,16 @@ size_t sort_scan_scratch_words(int64_t nkeys) {
   return words + 16;
 }
 
-void launch_sort(const SortArgs& a, hipStream_t s) {
+void launch_sort_rank(const SortArgs& a, hipStream_t s) {
   const int64_t n = a.seg.n;
   launch_fill_zero(a.count, ((size_t)a.nkeys * 4 + 15) / 16 * 16, s);
   hipLaunchKernelGGL(k_sort_rank, dim3((unsigned)((n + kRankBlock - 1) / kRankBlock)), dim3(kRankThreads), 0, s, a);
   scan_exclusive(a.count, a.nkeys, a.scan_scratch, s);   // bucket counts -> bucket starts
+}
+
+void launch_sort(const SortArgs& a, hipStream_t s) {
+  const int64_t n = a.seg.n;
+  launch_sort_rank(a, s);
   hipLaunchKernelGGL(k_sort_move, dim3((unsigned)((n + kRankBlock - 1) / kRankBlock)), dim3(256), 0, s, a);
 }
 

@@ -47,3 +47,66 @@ def test_sort_then_backward_walk():
     assert np.max(np.abs(d)) < 1e-10 * L
     assert np.max(np.abs(q1 - q0)) < 1e-10 * np.max(np.abs(q0))
     ctx.close()
+
+
+def _state_by_id(cfg, tuning, steps=None, back=0):
+    ctx, fields, species = fastdf.setup_workload(cfg, tuning=tuning)
+    ctx.step(cfg["n_steps"] if steps is None else steps)
+    if back:
+        ctx.step(-back)
+    out = []
+    for s in species:
+        x, q = ctx.read_state(s)
+        out += [x, q, ctx.weights(s).cpu().numpy()]
+    ctx.close()
+    return out
+
+
+FUSED_CASES = {
+    # two species with ragged counts (not multiples of the 1024-particle rank block)
+    "slip-8slot-two-species": dict(
+        base=dict(grid_n=32, n_side=29, n_steps=60, box_mpc=600.0, z_begin=1e6, z_end=10.0),
+        second=23, tuning=dict(sort_every=3)),
+    # super-steps (two blended grid sets), TSC, 4-slot grids, adaptive cadence
+    "radmat-superstep-tsc": dict(
+        base=dict(grid_n=16, n_side=13, n_steps=60, box_mpc=600.0, z_begin=1e6, z_end=10.0,
+                  model="radmat", omega_m=0.9999, omega_r=1e-4, slip_amp=0.0,
+                  superstep_tol=0.01, interp_order=2),
+        second=0, tuning=dict(sort_every=1, sort_cells=0.3)),
+    # graph capture and replay of the fused launches
+    "graph": dict(
+        base=dict(grid_n=32, n_side=21, n_steps=60, box_mpc=600.0, z_begin=1e6, z_end=10.0),
+        second=0, tuning=dict(sort_every=2, use_graph=1)),
+}
+
+
+@pytest.mark.parametrize("case", sorted(FUSED_CASES))
+def test_fused_sort_push_bit_identical(case):
+    """A re-sort carried out by the push (sort_fused) gives the same state by id,
+    bit for bit, as separate rank/move passes and as no sorting at all."""
+    print("[gpu-case] fused sort+push %s" % case, flush=True)
+    spec = FUSED_CASES[case]
+    cfg = workloads.small("c2", precision="fp32", **spec["base"])
+    cfg["sort_every"] = 1
+    if spec["second"]:
+        cfg["fields"] = cfg["fields"] + [cfg["fields"][0] + 1]
+        cfg["species"].append(dict(field=1, m=0.2, n_side=spec["second"], seed=2999))
+    plain = _state_by_id(cfg, dict(sort_every=0))
+    sep = _state_by_id(cfg, dict(spec["tuning"], sort_fused=0))
+    fused = _state_by_id(cfg, dict(spec["tuning"], sort_fused=1))
+    for i, (a, b, c) in enumerate(zip(plain, sep, fused)):
+        assert np.array_equal(a, b), (case, i)
+        assert np.array_equal(a, c), (case, i)
+
+
+def test_fused_sort_backward_walk():
+    """Fused re-sorts in both directions of a forward-backward walk: ids stay
+    aligned and the state matches the unsorted walk bit for bit."""
+    print("[gpu-case] fused sort+push backward walk", flush=True)
+    cfg = workloads.small("c2", grid_n=32, n_side=24, n_steps=60, precision="fp32",
+                          box_mpc=600.0, z_begin=1e6, z_end=10.0)
+    cfg["sort_every"] = 1
+    plain = _state_by_id(cfg, dict(sort_every=0), steps=60, back=35)
+    fused = _state_by_id(cfg, dict(sort_every=3, sort_fused=1), steps=60, back=35)
+    for i, (a, b) in enumerate(zip(plain, fused)):
+        assert np.array_equal(a, b), i
