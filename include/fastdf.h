@@ -183,6 +183,11 @@ typedef struct fdf_tuning {
                                     (no separate move pass; results bit-identical;
                                     the default); 0: rank + move passes, then
                                     the push */
+  int32_t push_waves;            /* push launch: at most this many resident waves per
+                                    SIMD (2-8; enforced by reserving LDS per block),
+                                    fewer waves keeping more of each block's mesh
+                                    neighbourhood in cache; 0: as many as the
+                                    registers allow */
 } fdf_tuning;
 
 /* ---- lifetime -------------------------------------------------------------- */

@@ -2,9 +2,8 @@
 
 Candidates are timed on the device through the C ABI's own HIP-event timers:
 
-  1. launch shape -- particles per thread and one-block-per-chunk versus a
-     persistent grid -- on a short stretch of steps right after the initial
-     sort;
+  1. launch shape -- particles per thread and the cap on resident waves per
+     SIMD -- over the full schedule;
   2. sort policy -- bucket size and the drift threshold of the adaptive
      cadence -- over the full schedule, since the cost of a stale order and the
      number of re-sorts both depend on how far the particles travel.
@@ -64,16 +63,18 @@ def autotune(cfg, path=CACHE_PATH, log=print, full_schedule=True):
     ctx = fastdf.Context(cfg)
     sorting = cfg.get("sort_every", 0) > 0
     base = dict(particles_per_thread=4, sort_tiles=0, sort_every=cfg.get("sort_every", 0),
-                sort_cells=2.0 if sorting else 0.0, persistent_blocks=0, use_graph=0, sort_predict=1,
-                sort_fused=1)
-    # 1. launch shape
+                sort_cells=3.0 if sorting else 0.0, persistent_blocks=0, use_graph=0, sort_predict=1,
+                sort_fused=1, push_waves=0)
+    # 1. launch shape: particles per thread and the cap on resident waves,
+    #    timed over the whole schedule (the mesh locality of the gathers, and
+    #    with it the best shape, changes as the particles disperse)
     best, best_ms = None, float("inf")
-    short = min(40, cfg["n_steps"])
+    steps = cfg["n_steps"] if full_schedule else min(40, cfg["n_steps"])
     for ppt in (1, 2, 4, 8):
-        for pers in (0, 2048):
-            t = dict(base, particles_per_thread=ppt, persistent_blocks=pers)
-            r = _run(ctx, cfg, t, short)
-            log("[autotune] ppt=%d persistent=%d: push %.3f ms" % (ppt, pers, r["push_ms"]))
+        for waves in (0, 2, 3, 4):
+            t = dict(base, particles_per_thread=ppt, push_waves=waves)
+            r = _run(ctx, cfg, t, steps)
+            log("[autotune] ppt=%d push_waves=%d: push %.3f ms" % (ppt, waves, r["push_ms"]))
             if r["push_ms"] < best_ms:
                 best, best_ms = t, r["push_ms"]
     # 2. sort policy over the whole schedule
@@ -108,7 +109,7 @@ def main(argv=None):
     ap = argparse.ArgumentParser(description="autotune a workload preset and store the result")
     ap.add_argument("workload")
     ap.add_argument("--cache", default=CACHE_PATH)
-    ap.add_argument("--launch-only", action="store_true", help="skip the full-schedule sort sweep")
+    ap.add_argument("--launch-only", action="store_true", help="short launch-shape runs, no sort sweep")
     ap.add_argument("--precision", choices=["fp32", "fp64"], default=None,
                     help="override the preset's precision")
     args = ap.parse_args(argv)

@@ -336,6 +336,7 @@ struct fdf_ctx {
   bool use_graph = false;   // capture step sequences into hipGraphs
   bool sort_predict = true; // sort keys from positions extrapolated to mid-interval
   bool sort_fused = true;   // FP32 separable: re-sorts after the first ride on the push
+  int push_waves = 0;       // cap on resident push waves per SIMD (0: none)
   hipStream_t cap_stream = nullptr;   // private stream used only for graph capture
   hipStream_t launch_stream = nullptr;  // stream kernels are enqueued on right now
   std::vector<GraphRec> graphs;       // captured step sequences
@@ -535,6 +536,14 @@ int upload_segments(fdf_ctx* c) {
   int rc = hip_check(c, hipStreamSynchronize(c->stream), "segment upload");
   c->seg_dirty = false;
   return rc;
+}
+
+// LDS bytes per 4-wave push block that leave room for exactly `waves` blocks
+// (one wave per SIMD each) in the 160 KB of a CU; 0 for no cap.
+int push_lds_reserve(int waves) {
+  if (waves <= 0) return 0;
+  const int lds_per_cu = 160 * 1024;
+  return (lds_per_cu / (waves + 1) + 256 + 255) / 256 * 256;
 }
 
 // Buckets per axis of the sort: default one per 4^3 cells, at most 256.
@@ -966,6 +975,7 @@ int enqueue_steps(fdf_ctx* c, int32_t n) {
   pa.do_kick = 1;
   pa.eom = c->cfg.eom;
   pa.tsc = c->cfg.interp_order == 2;
+  pa.lds_reserve = push_lds_reserve(c->push_waves);
   // does the launch at integer time u re-sort first?
   auto sort_due = [&](int u) {
     if (c->sort_cells > 0) return !c->sorted_once || c->drift_cells >= c->sort_cells;
@@ -1505,6 +1515,7 @@ int fdf_get_tuning(const fdf_ctx* c, fdf_tuning* t) {
   t->use_graph = c->use_graph ? 1 : 0;
   t->sort_predict = c->sort_predict ? 1 : 0;
   t->sort_fused = c->sort_fused ? 1 : 0;
+  t->push_waves = c->push_waves;
   return FDF_OK;
 }
 
@@ -1524,6 +1535,8 @@ int fdf_set_tuning(fdf_ctx* c, const fdf_tuning* t) {
   if (t->use_graph != 0 && t->use_graph != 1) return fail(c, FDF_ERR_ARG, "use_graph must be 0 or 1");
   if (t->sort_predict != 0 && t->sort_predict != 1) return fail(c, FDF_ERR_ARG, "sort_predict must be 0 or 1");
   if (t->sort_fused != 0 && t->sort_fused != 1) return fail(c, FDF_ERR_ARG, "sort_fused must be 0 or 1");
+  if (t->push_waves != 0 && (t->push_waves < 2 || t->push_waves > 8))
+    return fail(c, FDF_ERR_ARG, "push_waves must be 0 or in [2, 8]");
   if (p != c->ppt) c->seg_dirty = true;   // chunk boundaries depend on the block size
   clear_graphs(c);
   c->persistent = t->persistent_blocks;
@@ -1534,6 +1547,7 @@ int fdf_set_tuning(fdf_ctx* c, const fdf_tuning* t) {
   c->sort_cells = t->sort_cells;
   c->sort_predict = t->sort_predict != 0;
   c->sort_fused = t->sort_fused != 0;
+  c->push_waves = t->push_waves;
   return FDF_OK;
 }
 

@@ -181,25 +181,37 @@ __device__ __forceinline__ void push_chunk_f32(const PushArgs& a, int64_t chunk)
 #pragma unroll
   for (int d = 0; d < 3; ++d) { X[d] = sg.xu[d] + c0; Q0[d] = sg.q0f[d] + c0; DQ[d] = sg.dqf[d] + c0; }
 
+  // three phases, so that the loads of all PPT particles are in flight
+  // together (a store between them would pin the next loads behind it)
+  uint32_t xu[PPT][3];
+  float dq[PPT][3], q0[PPT][3];
 #pragma unroll
   for (int p = 0; p < PPT; ++p) {
     const uint32_t i = threadIdx.x + (uint32_t)(p * kBlock);
     if ((int64_t)i >= left) break;
-    uint32_t xu[3];
-    float dq[3], q0[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      xu[d] = ldnt(&X[d][i]);
-      q0[d] = ldnt(&Q0[d][i]);
-      dq[d] = ldnt(&DQ[d][i]);
+      xu[p][d] = ldnt(&X[d][i]);
+      q0[p][d] = ldnt(&Q0[d][i]);
+      dq[p][d] = ldnt(&DQ[d][i]);
     }
-    update_f32<NSLOT, BLEND, TSC, OFF32>(k, a.do_drift != 0, xu, q0, dq);
+  }
+#pragma unroll
+  for (int p = 0; p < PPT; ++p) {
+    const uint32_t i = threadIdx.x + (uint32_t)(p * kBlock);
+    if ((int64_t)i >= left) break;
+    update_f32<NSLOT, BLEND, TSC, OFF32>(k, a.do_drift != 0, xu[p], q0[p], dq[p]);
+  }
+#pragma unroll
+  for (int p = 0; p < PPT; ++p) {
+    const uint32_t i = threadIdx.x + (uint32_t)(p * kBlock);
+    if ((int64_t)i >= left) break;
     if (a.do_drift) {
 #pragma unroll
-      for (int d = 0; d < 3; ++d) stnt(xu[d], &X[d][i]);
+      for (int d = 0; d < 3; ++d) stnt(xu[p][d], &X[d][i]);
     }
 #pragma unroll
-    for (int d = 0; d < 3; ++d) stnt(dq[d], &DQ[d][i]);
+    for (int d = 0; d < 3; ++d) stnt(dq[p][d], &DQ[d][i]);
   }
 }
 
@@ -421,23 +433,23 @@ void push_launch(const PushArgs& a, hipStream_t s) {
   const bool off32 = (uint64_t)a.G * a.G * a.G * (uint64_t)(a.nslot * (a.fp64 ? 8 : 2)) <= (1ull << 32);
   if (a.fp64) {
     if (off32) {
-      if (a.nslot == 8) hipLaunchKernelGGL((k_push_f64<8, PPT, BLEND, TSC, true>), grid, block, 0, s, a);
-      else if (a.nslot == 6) hipLaunchKernelGGL((k_push_f64<6, PPT, BLEND, TSC, true>), grid, block, 0, s, a);
-      else hipLaunchKernelGGL((k_push_f64<4, PPT, BLEND, TSC, true>), grid, block, 0, s, a);
+      if (a.nslot == 8) hipLaunchKernelGGL((k_push_f64<8, PPT, BLEND, TSC, true>), grid, block, a.lds_reserve, s, a);
+      else if (a.nslot == 6) hipLaunchKernelGGL((k_push_f64<6, PPT, BLEND, TSC, true>), grid, block, a.lds_reserve, s, a);
+      else hipLaunchKernelGGL((k_push_f64<4, PPT, BLEND, TSC, true>), grid, block, a.lds_reserve, s, a);
     } else {
-      if (a.nslot == 8) hipLaunchKernelGGL((k_push_f64<8, PPT, BLEND, TSC, false>), grid, block, 0, s, a);
-      else if (a.nslot == 6) hipLaunchKernelGGL((k_push_f64<6, PPT, BLEND, TSC, false>), grid, block, 0, s, a);
-      else hipLaunchKernelGGL((k_push_f64<4, PPT, BLEND, TSC, false>), grid, block, 0, s, a);
+      if (a.nslot == 8) hipLaunchKernelGGL((k_push_f64<8, PPT, BLEND, TSC, false>), grid, block, a.lds_reserve, s, a);
+      else if (a.nslot == 6) hipLaunchKernelGGL((k_push_f64<6, PPT, BLEND, TSC, false>), grid, block, a.lds_reserve, s, a);
+      else hipLaunchKernelGGL((k_push_f64<4, PPT, BLEND, TSC, false>), grid, block, a.lds_reserve, s, a);
     }
   } else {
     if (off32) {
-      if (a.nslot == 8) hipLaunchKernelGGL((k_push_f32<8, PPT, BLEND, TSC, true>), grid, block, 0, s, a);
-      else if (a.nslot == 6) hipLaunchKernelGGL((k_push_f32<6, PPT, BLEND, TSC, true>), grid, block, 0, s, a);
-      else hipLaunchKernelGGL((k_push_f32<4, PPT, BLEND, TSC, true>), grid, block, 0, s, a);
+      if (a.nslot == 8) hipLaunchKernelGGL((k_push_f32<8, PPT, BLEND, TSC, true>), grid, block, a.lds_reserve, s, a);
+      else if (a.nslot == 6) hipLaunchKernelGGL((k_push_f32<6, PPT, BLEND, TSC, true>), grid, block, a.lds_reserve, s, a);
+      else hipLaunchKernelGGL((k_push_f32<4, PPT, BLEND, TSC, true>), grid, block, a.lds_reserve, s, a);
     } else {
-      if (a.nslot == 8) hipLaunchKernelGGL((k_push_f32<8, PPT, BLEND, TSC, false>), grid, block, 0, s, a);
-      else if (a.nslot == 6) hipLaunchKernelGGL((k_push_f32<6, PPT, BLEND, TSC, false>), grid, block, 0, s, a);
-      else hipLaunchKernelGGL((k_push_f32<4, PPT, BLEND, TSC, false>), grid, block, 0, s, a);
+      if (a.nslot == 8) hipLaunchKernelGGL((k_push_f32<8, PPT, BLEND, TSC, false>), grid, block, a.lds_reserve, s, a);
+      else if (a.nslot == 6) hipLaunchKernelGGL((k_push_f32<6, PPT, BLEND, TSC, false>), grid, block, a.lds_reserve, s, a);
+      else hipLaunchKernelGGL((k_push_f32<4, PPT, BLEND, TSC, false>), grid, block, a.lds_reserve, s, a);
     }
   }
 }

@@ -294,11 +294,11 @@ void eom_launch(const PushArgs& a, hipStream_t s) {
   const int64_t grid_blocks = a.persistent ? a.persistent : a.total_chunks;
   const dim3 grid((unsigned)grid_blocks), block(kBlock);
   if (a.fp64) {
-    if (a.nslot == 8) hipLaunchKernelGGL((k_push_eom_f64<8, PPT, BLEND, TSC>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((k_push_eom_f64<4, PPT, BLEND, TSC>), grid, block, 0, s, a);
+    if (a.nslot == 8) hipLaunchKernelGGL((k_push_eom_f64<8, PPT, BLEND, TSC>), grid, block, a.lds_reserve, s, a);
+    else hipLaunchKernelGGL((k_push_eom_f64<4, PPT, BLEND, TSC>), grid, block, a.lds_reserve, s, a);
   } else {
-    if (a.nslot == 8) hipLaunchKernelGGL((k_push_eom_f32<8, PPT, BLEND, TSC>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((k_push_eom_f32<4, PPT, BLEND, TSC>), grid, block, 0, s, a);
+    if (a.nslot == 8) hipLaunchKernelGGL((k_push_eom_f32<8, PPT, BLEND, TSC>), grid, block, a.lds_reserve, s, a);
+    else hipLaunchKernelGGL((k_push_eom_f32<4, PPT, BLEND, TSC>), grid, block, a.lds_reserve, s, a);
   }
 }
 

@@ -110,3 +110,18 @@ def test_fused_sort_backward_walk():
     fused = _state_by_id(cfg, dict(sort_every=3, sort_fused=1), steps=60, back=35)
     for i, (a, b) in enumerate(zip(plain, fused)):
         assert np.array_equal(a, b), i
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_launch_shape_invariance(prec):
+    """Particles per thread and the cap on resident waves change only the
+    launch: the state by id is bit-identical."""
+    print("[gpu-case] launch shape invariance %s" % prec, flush=True)
+    cfg = workloads.small("c2", grid_n=32, n_side=27, n_steps=60, precision=prec,
+                          box_mpc=600.0, z_begin=1e6, z_end=10.0)
+    cfg["sort_every"] = 1
+    ref = _state_by_id(cfg, dict(sort_every=4))
+    for ppt, waves in ((2, 3), (4, 2), (1, 8), (8, 4)):
+        got = _state_by_id(cfg, dict(sort_every=4, particles_per_thread=ppt, push_waves=waves))
+        for i, (a, b) in enumerate(zip(ref, got)):
+            assert np.array_equal(a, b), (ppt, waves, i)
