@@ -20,7 +20,9 @@
 // CIC corner.
 // FP64 form: everything binary64; 8 slots = four 16-byte loads per corner.
 //
-// Blocks take contiguous chunks of one species, in an XCD-aware order.
+// Blocks take contiguous chunks of one species, in an XCD-aware order.  On a
+// step that begins with a re-sort, k_push_sort_f32 pushes one species and
+// writes the updated state straight to its sorted slots.
 //
 // The separable form is the one implemented here; the other equations of
 // motion (fdf_push_eom.hip) take over when PushArgs::eom is set.

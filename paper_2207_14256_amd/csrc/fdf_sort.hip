@@ -5,7 +5,9 @@
 // tile.  Rank pass: each block of 1024 particles sorts itself by that key in
 // LDS and reserves one contiguous range per bucket it touches (one atomic per
 // block and bucket).  Scan: bucket counts become bucket starts.  Move pass:
-// every state array goes to start + rank in the other buffer copy.  Within a
+// every state array goes to start + rank in the other buffer copy (in the
+// FP32 separable form the push of the step does this instead, writing its
+// updated state in sorted order: k_push_sort_f32).  Within a
 // bucket the fragments of different blocks follow each other in arbitrary
 // order, each sorted by cell.  The push is per particle, so results do not
 // depend on the order.  Particles keep their id.
