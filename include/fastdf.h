@@ -188,6 +188,11 @@ typedef struct fdf_tuning {
                                     fewer waves keeping more of each block's mesh
                                     neighbourhood in cache; 0: as many as the
                                     registers allow */
+  int32_t push_block;            /* separable form: up to this many leapfrog steps
+                                    (1-8) per push launch, the particle state
+                                    staying in registers between them; a re-sort,
+                                    a grid rebuild and the final kick end a block.
+                                    Results are bit-identical for every value */
 } fdf_tuning;
 
 /* ---- lifetime -------------------------------------------------------------- */

@@ -1,10 +1,11 @@
 // Gather + kick-drift-kick push of the neutrino tracers (sec. 3.3), gfx950.
 //
-// One launch advances every species by one leapfrog step: the kick of the
-// closing half of step k-1 and the opening half of step k are evaluated at the
-// same (x_k, a_k), so they are applied as one kick with the summed Delta tau;
-// then the drift.  The last launch of a call is a kick alone, leaving q at a
-// schedule point.
+// One launch advances every species by one or more leapfrog steps
+// (PushArgs::nsub, the particle state staying in registers in between): the
+// kick of the closing half of step k-1 and the opening half of step k are
+// evaluated at the same (x_k, a_k), so they are applied as one kick with the
+// summed Delta tau; then the drift.  The last launch of a call is a kick
+// alone, leaving q at a schedule point.
 //
 // Per particle: CIC (trilinear; or TSC, 27 points, when PushArgs::tsc is set)
 // interpolation of the gradient grids at x,
@@ -92,7 +93,7 @@ __device__ __forceinline__ void gather_stencil_bf16(const void* grid, const uint
   }
 }
 
-// Launch constants of the FP32 update of one segment.
+// Constants of the FP32 update of one segment at one step.
 struct ConstF32 {
   int shift;
   uint32_t gmask, G;
@@ -102,21 +103,22 @@ struct ConstF32 {
 };
 
 template <bool BLEND>
-__device__ __forceinline__ ConstF32 const_f32(const PushArgs& a, const Segment& sg) {
+__device__ __forceinline__ ConstF32 const_f32(const PushArgs& a, const Segment& sg, int step) {
+  const StepCoef& c = a.sub[step];
   ConstF32 k;
   k.shift = 32 - a.log2g;
   k.gmask = (uint32_t)a.G - 1u;
   k.G = (uint32_t)a.G;
   k.finv = __uint_as_float((uint32_t)(127 - k.shift) << 23);   // 2^-shift
-  k.kick = (float)a.kick;
-  const float ma = (float)(sg.m * a.a_kick);
-  const float mah = (float)(sg.m * a.a_drift);
+  k.kick = (float)c.kick;
+  const float ma = (float)(sg.m * c.a_kick);
+  const float mah = (float)(sg.m * c.a_drift);
   k.ma2 = ma * ma;
   k.mah2 = mah * mah;
-  k.dscale = (float)(a.drift * 4294967296.0 / a.box);
+  k.dscale = (float)(c.drift * 4294967296.0 / a.box);
   k.gridA = (BLEND && a.grid_sel) ? sg.grid2 : sg.grid;
   k.gridB = (BLEND && a.grid_sel) ? sg.grid : sg.grid2;
-  k.tb = (float)a.blend_t;
+  k.tb = (float)c.blend_t;
   k.ta = 1.0f - k.tb;
   return k;
 }
@@ -172,7 +174,6 @@ template <int NSLOT, int PPT, bool BLEND, bool TSC, bool OFF32>
 __device__ __forceinline__ void push_chunk_f32(const PushArgs& a, int64_t chunk) {
   const int s = find_segment(a.seg, a.nseg, chunk);
   const Segment& sg = a.seg[s];
-  const ConstF32 k = const_f32<BLEND>(a, sg);
   const int64_t first = (chunk - sg.chunk_begin) * (int64_t)(kBlock * PPT) + threadIdx.x;
   // chunk-relative arrays: a uniform base and a 32-bit lane index
   const int64_t c0 = first - threadIdx.x;
@@ -183,8 +184,8 @@ __device__ __forceinline__ void push_chunk_f32(const PushArgs& a, int64_t chunk)
 #pragma unroll
   for (int d = 0; d < 3; ++d) { X[d] = sg.xu[d] + c0; Q0[d] = sg.q0f[d] + c0; DQ[d] = sg.dqf[d] + c0; }
 
-  // three phases, so that the loads of all PPT particles are in flight
-  // together (a store between them would pin the next loads behind it)
+  // loads of all PPT particles, the launch's steps, then the stores: no store
+  // stands between two loads, and the state stays in registers across steps
   uint32_t xu[PPT][3];
   float dq[PPT][3], q0[PPT][3];
 #pragma unroll
@@ -198,11 +199,14 @@ __device__ __forceinline__ void push_chunk_f32(const PushArgs& a, int64_t chunk)
       dq[p][d] = ldnt(&DQ[d][i]);
     }
   }
+  for (int step = 0; step < a.nsub; ++step) {
+    const ConstF32 k = const_f32<BLEND>(a, sg, step);
 #pragma unroll
-  for (int p = 0; p < PPT; ++p) {
-    const uint32_t i = threadIdx.x + (uint32_t)(p * kBlock);
-    if ((int64_t)i >= left) break;
-    update_f32<NSLOT, BLEND, TSC, OFF32>(k, a.do_drift != 0, xu[p], q0[p], dq[p]);
+    for (int p = 0; p < PPT; ++p) {
+      const uint32_t i = threadIdx.x + (uint32_t)(p * kBlock);
+      if ((int64_t)i >= left) break;
+      update_f32<NSLOT, BLEND, TSC, OFF32>(k, a.do_drift != 0, xu[p], q0[p], dq[p]);
+    }
   }
 #pragma unroll
   for (int p = 0; p < PPT; ++p) {
@@ -219,13 +223,13 @@ __device__ __forceinline__ void push_chunk_f32(const PushArgs& a, int64_t chunk)
 
 // A push that also performs a re-sort of one species whose rank pass has run:
 // one block per rank block of kSortBlock particles.  The block reads its
-// particles in place (coalesced), updates them, stages the whole new state in
-// LDS and writes it out in sorted order, element e of the sorted run to
-// start[bucket[e]] + rank[e] of the other buffer copy, so consecutive threads
-// write consecutive slots of a bucket fragment.  The re-sort then costs the
-// push the writes of q0 and id and the index reads, instead of a pass of its
-// own over the whole state.
-constexpr int kFusedThreads = 512;   // 8 waves per block; 40 KB of LDS leaves 8 waves per SIMD
+// particles in place (coalesced), updates them (all of the launch's steps),
+// stages the whole new state in LDS and writes it out in sorted order,
+// element e of the sorted run to start[bucket[e]] + rank[e] of the other
+// buffer copy, so consecutive threads write consecutive slots of a bucket
+// fragment.  The re-sort then costs the push the writes of q0 and id and the
+// index reads, instead of a pass of its own over the whole state.
+constexpr int kFusedThreads = 256;   // 4 waves per block, 4 particles per thread
 
 template <int NSLOT, bool BLEND, bool TSC, bool OFF32>
 __global__ void __launch_bounds__(kFusedThreads) k_push_sort_f32(PushArgs a) {
@@ -233,42 +237,62 @@ __global__ void __launch_bounds__(kFusedThreads) k_push_sort_f32(PushArgs a) {
   __shared__ uint32_t st[10][kSortBlock];
   const Segment& sg = a.seg[0];
   const Segment& ds = a.dseg[0];
-  const ConstF32 k = const_f32<BLEND>(a, sg);
   const int64_t i0 = xcd_chunk(blockIdx.x, gridDim.x) * (int64_t)kSortBlock;
   const int cnt = (int)min<int64_t>(kSortBlock, sg.n - i0);
+  // the sort outputs and ids first: their latency (bucket, then its start)
+  // overlaps the state loads and the gathers
+  uint32_t src[kPer], bucket[kPer], rank[kPer], id[kPer];
+#pragma unroll
+  for (int r = 0; r < kPer; ++r) {
+    const int e = threadIdx.x + r * kFusedThreads;
+    if (e >= cnt) break;
+    const int64_t o = i0 + e;                  // element e of the sorted order; slot e of the block
+    src[r] = ldnt(&a.sort_src[o]);
+    bucket[r] = ldnt(&a.sort_bucket[o]);
+    rank[r] = ldnt(&a.sort_rank[o]);
+    id[r] = ldnt(&sg.id[o]);
+  }
+  uint32_t xu[kPer][3];
+  float dq[kPer][3], q0[kPer][3];
 #pragma unroll
   for (int r = 0; r < kPer; ++r) {
     const int e = threadIdx.x + r * kFusedThreads;
     if (e >= cnt) break;
     const int64_t i = i0 + e;
-    uint32_t xu[3];
-    float dq[3], q0[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      xu[d] = ldnt(&sg.xu[d][i]);
-      q0[d] = ldnt(&sg.q0f[d][i]);
-      dq[d] = ldnt(&sg.dqf[d][i]);
+      xu[r][d] = ldnt(&sg.xu[d][i]);
+      q0[r][d] = ldnt(&sg.q0f[d][i]);
+      dq[r][d] = ldnt(&sg.dqf[d][i]);
     }
-    update_f32<NSLOT, BLEND, TSC, OFF32>(k, true, xu, q0, dq);
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      st[d][e] = xu[d];
-      st[3 + d][e] = __float_as_uint(q0[d]);
-      st[6 + d][e] = __float_as_uint(dq[d]);
-    }
-    st[9][e] = ldnt(&sg.id[i]);
   }
-  // destinations of the sorted elements this thread writes
-  uint32_t src[kPer];
   int64_t dst[kPer];
 #pragma unroll
   for (int r = 0; r < kPer; ++r) {
     const int e = threadIdx.x + r * kFusedThreads;
-    if (e < cnt) {
-      const int64_t o = i0 + e;                // element of the sorted order
-      src[r] = ldnt(&a.sort_src[o]);
-      dst[r] = (int64_t)a.sort_start[ldnt(&a.sort_bucket[o])] + ldnt(&a.sort_rank[o]);
+    if (e >= cnt) break;
+    dst[r] = (int64_t)a.sort_start[bucket[r]] + rank[r];
+  }
+  for (int step = 0; step < a.nsub; ++step) {
+    const ConstF32 k = const_f32<BLEND>(a, sg, step);
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) {
+      const int e = threadIdx.x + r * kFusedThreads;
+      if (e >= cnt) break;
+      update_f32<NSLOT, BLEND, TSC, OFF32>(k, true, xu[r], q0[r], dq[r]);
     }
+  }
+#pragma unroll
+  for (int r = 0; r < kPer; ++r) {
+    const int e = threadIdx.x + r * kFusedThreads;
+    if (e >= cnt) break;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      st[d][e] = xu[r][d];
+      st[3 + d][e] = __float_as_uint(q0[r][d]);
+      st[6 + d][e] = __float_as_uint(dq[r][d]);
+    }
+    st[9][e] = id[r];
   }
   __syncthreads();
   // one array at a time, with cached stores: the fragments that neighbouring
@@ -335,76 +359,119 @@ __device__ __forceinline__ void gather_stencil_f64(const void* grid, const uint3
   }
 }
 
-template <int NSLOT, int PPT, bool BLEND, bool TSC, bool OFF32>
-__device__ __forceinline__ void push_chunk_f64(const PushArgs& a, int64_t chunk) {
+// Constants of the FP64 update of one segment at one step.
+struct ConstF64 {
+  int gm;
+  uint32_t G;
+  double ginv, ma, mah, kick, drift, box, ta, tb;
+  const void* gridA;
+  const void* gridB;
+};
+
+template <bool BLEND>
+__device__ __forceinline__ ConstF64 const_f64(const PushArgs& a, const Segment& sg, int step) {
+  const StepCoef& c = a.sub[step];
+  ConstF64 k;
+  k.gm = a.G - 1;
+  k.G = (uint32_t)a.G;
+  k.ginv = (double)a.G / a.box;
+  k.ma = sg.m * c.a_kick;
+  k.mah = sg.m * c.a_drift;
+  k.kick = c.kick;
+  k.drift = c.drift;
+  k.box = a.box;
+  k.gridA = (BLEND && a.grid_sel) ? sg.grid2 : sg.grid;
+  k.gridB = (BLEND && a.grid_sel) ? sg.grid : sg.grid2;
+  k.tb = c.blend_t;
+  k.ta = 1.0 - k.tb;
+  return k;
+}
+
+// The FP64 update of one particle (same operations as the FP32 form, in
+// binary64, with the periodic wrap taken as a floor-mod of the position).
+template <int NSLOT, bool BLEND, bool TSC, bool OFF32>
+__device__ __forceinline__ void update_f64(const ConstF64& k, bool drift, double* x, double* q, const double* q0) {
 #pragma clang fp contract(off)
   constexpr int NP = Stencil<TSC>::N;
+  uint32_t cell[NP];
+  double w[NP];
+  stencil_f64<TSC>(x, k.ginv, k.gm, k.G, cell, w);
+  double g[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if (BLEND) {
+    double wa[NP], wb[NP];
+#pragma unroll
+    for (int cc = 0; cc < NP; ++cc) { wa[cc] = k.ta * w[cc]; wb[cc] = k.tb * w[cc]; }
+    gather_stencil_f64<NSLOT, TSC, OFF32>(k.gridA, cell, wa, g);
+    gather_stencil_f64<NSLOT, TSC, OFF32>(k.gridB, cell, wb, g);
+  } else {
+    gather_stencil_f64<NSLOT, TSC, OFF32>(k.gridA, cell, w, g);
+  }
+  if (NSLOT == 4) { g[3] = g[0]; g[4] = g[1]; g[5] = g[2]; }
+  const double q0sq = fma(q0[0], q0[0], fma(q0[1], q0[1], q0[2] * q0[2]));
+  const double e0 = sqrt(q0sq + k.ma * k.ma);
+  const double qg = fma(q0[0], g[3], fma(q0[1], g[4], q0[2] * g[5])) / e0 + g[6];
+  const double cphi = q0sq / e0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const double F = fma(q0[d], qg, fma(-cphi, g[3 + d], -(e0 * g[d])));
+    q[d] = fma(k.kick, F, q[d]);
+  }
+  if (drift) {
+    const double e = sqrt(fma(q[0], q[0], fma(q[1], q[1], q[2] * q[2])) + k.mah * k.mah);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      double xn = fmod(fma(k.drift, q[d] / e, x[d]), k.box);   // floor-mod as numpy.mod
+      if (xn < 0.0) xn += k.box;
+      x[d] = xn;
+    }
+  }
+}
+
+template <int NSLOT, int PPT, bool BLEND, bool TSC, bool OFF32>
+__device__ __forceinline__ void push_chunk_f64(const PushArgs& a, int64_t chunk) {
   const int s = find_segment(a.seg, a.nseg, chunk);
   const Segment& sg = a.seg[s];
-  const int64_t n = sg.n;
   const int64_t first = (chunk - sg.chunk_begin) * (int64_t)(kBlock * PPT) + threadIdx.x;
-  const int gm = a.G - 1;
-  const double ginv = (double)a.G / a.box;
-  const double ma = sg.m * a.a_kick;
-  const double mah = sg.m * a.a_drift;
-  const uint32_t G = (uint32_t)a.G;
-  const void* gridA = (BLEND && a.grid_sel) ? sg.grid2 : sg.grid;
-  const void* gridB = (BLEND && a.grid_sel) ? sg.grid : sg.grid2;
-  const double tb = a.blend_t, ta = 1.0 - tb;
   // chunk-relative arrays: a uniform base and a 32-bit lane index
   const int64_t c0 = first - threadIdx.x;
-  const int64_t left = n - c0;
+  const int64_t left = sg.n - c0;
   double* X[3];
   double* Q[3];
   const double* Q0[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) { X[d] = sg.xd[d] + c0; Q[d] = sg.qd[d] + c0; Q0[d] = sg.q0d[d] + c0; }
 
+  double x[PPT][3], q[PPT][3], q0[PPT][3];
 #pragma unroll
   for (int p = 0; p < PPT; ++p) {
     const uint32_t i = threadIdx.x + (uint32_t)(p * kBlock);
     if ((int64_t)i >= left) break;
-    double x[3], q[3], q0[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      x[d] = ldnt(&X[d][i]);
-      q[d] = ldnt(&Q[d][i]);
-      q0[d] = ldnt(&Q0[d][i]);
+      x[p][d] = ldnt(&X[d][i]);
+      q[p][d] = ldnt(&Q[d][i]);
+      q0[p][d] = ldnt(&Q0[d][i]);
     }
-    uint32_t cell[NP];
-    double w[NP];
-    stencil_f64<TSC>(x, ginv, gm, G, cell, w);
-    double g[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    if (BLEND) {
-      double wa[NP], wb[NP];
+  }
+  for (int step = 0; step < a.nsub; ++step) {
+    const ConstF64 k = const_f64<BLEND>(a, sg, step);
 #pragma unroll
-      for (int cc = 0; cc < NP; ++cc) { wa[cc] = ta * w[cc]; wb[cc] = tb * w[cc]; }
-      gather_stencil_f64<NSLOT, TSC, OFF32>(gridA, cell, wa, g);
-      gather_stencil_f64<NSLOT, TSC, OFF32>(gridB, cell, wb, g);
-    } else {
-      gather_stencil_f64<NSLOT, TSC, OFF32>(gridA, cell, w, g);
+    for (int p = 0; p < PPT; ++p) {
+      const uint32_t i = threadIdx.x + (uint32_t)(p * kBlock);
+      if ((int64_t)i >= left) break;
+      update_f64<NSLOT, BLEND, TSC, OFF32>(k, a.do_drift != 0, x[p], q[p], q0[p]);
     }
-    if (NSLOT == 4) { g[3] = g[0]; g[4] = g[1]; g[5] = g[2]; }
-    const double q0sq = fma(q0[0], q0[0], fma(q0[1], q0[1], q0[2] * q0[2]));
-    const double e0 = sqrt(q0sq + ma * ma);
-    const double qg = fma(q0[0], g[3], fma(q0[1], g[4], q0[2] * g[5])) / e0 + g[6];
-    const double cphi = q0sq / e0;
+  }
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      const double F = fma(q0[d], qg, fma(-cphi, g[3 + d], -(e0 * g[d])));
-      q[d] = fma(a.kick, F, q[d]);
-    }
+  for (int p = 0; p < PPT; ++p) {
+    const uint32_t i = threadIdx.x + (uint32_t)(p * kBlock);
+    if ((int64_t)i >= left) break;
     if (a.do_drift) {
-      const double e = sqrt(fma(q[0], q[0], fma(q[1], q[1], q[2] * q[2])) + mah * mah);
 #pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        double xn = fmod(fma(a.drift, q[d] / e, x[d]), a.box);   // floor-mod as numpy.mod
-        if (xn < 0.0) xn += a.box;
-        stnt(xn, &X[d][i]);
-      }
+      for (int d = 0; d < 3; ++d) stnt(x[p][d], &X[d][i]);
     }
 #pragma unroll
-    for (int d = 0; d < 3; ++d) stnt(q[d], &Q[d][i]);
+    for (int d = 0; d < 3; ++d) stnt(q[p][d], &Q[d][i]);
   }
 }
 
@@ -461,13 +528,13 @@ void push_sort_launch(const PushArgs& a, hipStream_t s) {
   const dim3 grid((unsigned)a.total_chunks), block(kFusedThreads);
   const bool off32 = (uint64_t)a.G * a.G * a.G * (uint64_t)(a.nslot * 2) <= (1ull << 32);
   if (off32) {
-    if (a.nslot == 8) hipLaunchKernelGGL((k_push_sort_f32<8, BLEND, TSC, true>), grid, block, 0, s, a);
-    else if (a.nslot == 6) hipLaunchKernelGGL((k_push_sort_f32<6, BLEND, TSC, true>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((k_push_sort_f32<4, BLEND, TSC, true>), grid, block, 0, s, a);
+    if (a.nslot == 8) hipLaunchKernelGGL((k_push_sort_f32<8, BLEND, TSC, true>), grid, block, a.lds_reserve, s, a);
+    else if (a.nslot == 6) hipLaunchKernelGGL((k_push_sort_f32<6, BLEND, TSC, true>), grid, block, a.lds_reserve, s, a);
+    else hipLaunchKernelGGL((k_push_sort_f32<4, BLEND, TSC, true>), grid, block, a.lds_reserve, s, a);
   } else {
-    if (a.nslot == 8) hipLaunchKernelGGL((k_push_sort_f32<8, BLEND, TSC, false>), grid, block, 0, s, a);
-    else if (a.nslot == 6) hipLaunchKernelGGL((k_push_sort_f32<6, BLEND, TSC, false>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((k_push_sort_f32<4, BLEND, TSC, false>), grid, block, 0, s, a);
+    if (a.nslot == 8) hipLaunchKernelGGL((k_push_sort_f32<8, BLEND, TSC, false>), grid, block, a.lds_reserve, s, a);
+    else if (a.nslot == 6) hipLaunchKernelGGL((k_push_sort_f32<6, BLEND, TSC, false>), grid, block, a.lds_reserve, s, a);
+    else hipLaunchKernelGGL((k_push_sort_f32<4, BLEND, TSC, false>), grid, block, a.lds_reserve, s, a);
   }
 }
 
@@ -485,6 +552,14 @@ void push_ppt(const PushArgs& a, hipStream_t s) {
 }  // namespace
 
 int push_chunk_particles(int ppt) { return kBlock * ppt; }
+
+int push_sort_block_lds(int waves) {
+  if (waves <= 0) return 0;
+  const int lds_per_cu = 160 * 1024;
+  const int blocks = std::max(1, waves * 4 / (kFusedThreads / 64));   // blocks per CU for `waves` per SIMD
+  const int per_block = (lds_per_cu / (blocks + 1) + 256 + 255) / 256 * 256;
+  return std::max(0, per_block - (int)sizeof(uint32_t) * 10 * kSortBlock);
+}
 
 void launch_push_sort(const PushArgs& a, hipStream_t s) {
   if (a.tsc) {

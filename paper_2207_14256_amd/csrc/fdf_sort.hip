@@ -75,6 +75,7 @@ __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb) {
 constexpr int kRankThreads = 256;
 constexpr int kRankBlock = kSortBlock;    // particles per block
 constexpr uint64_t kIdxMask = kRankBlock - 1;
+constexpr uint64_t kNoKey = 0xFFFFFFFFull;      // sorts after every key (at most 30 bits)
 
 
 
@@ -108,7 +109,7 @@ __global__ void __launch_bounds__(kRankThreads) k_sort_rank(SortArgs a) {
   for (int r = 0; r < 4; ++r) {
     const int e = tid + kRankThreads * r;
     const int64_t i = i0 + e;
-    const uint64_t key = i < a.seg.n ? (uint64_t)full_key(a, i) : 0xFFFFFFFFull;
+    const uint64_t key = i < a.seg.n ? (uint64_t)full_key(a, i) : kNoKey;
     kv[e] = (key << 10) | (uint64_t)e;
   }
   __syncthreads();
@@ -190,7 +191,7 @@ __global__ void __launch_bounds__(kRankThreads) k_sort_rank(SortArgs a) {
     const int e = 4 * tid + r;
     const uint64_t key = kv[e] >> 10;
     const bool last = e == kRankBlock - 1 || (kv[e + 1] >> sh) != (kv[e] >> sh);
-    if (last && key != 0xFFFFFFFFull) {
+    if (last && key != kNoKey) {
       const uint32_t st = seg_start[e];
       seg_base[st] = atomicAdd(&a.count[(uint32_t)(key >> (3 * a.fine_bits))], (uint32_t)(e - st + 1));
     }
