@@ -58,6 +58,16 @@ def bytes_per_launch(cfg, n_particles, drift):
     return n_particles * per + grid
 
 
+def bytes_per_push_sort(cfg, n_particles):
+    """Algorithmic HBM bytes of one push launch that also carries out a
+    re-sort (FP32 form): the push's reads (x, q0, dq: 36 B), the id and the
+    rank pass outputs (source slot, bucket, rank: 16 B) read, the whole state
+    written in sorted order (40 B), and one read of the mesh."""
+    G = cfg["grid_n"]
+    nslot = 4 if not cfg.get("slip_amp", 0.0) else 8
+    return n_particles * 92 + G ** 3 * nslot * 2
+
+
 def run_leg(cfg, steps, warmup, label, tuning=None):
     import torch
     from paper_2207_14256_amd import fastdf
@@ -87,6 +97,7 @@ def run_leg(cfg, steps, warmup, label, tuning=None):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     push_ms, launches = ctx.read_timing("push")
+    ps_ms, ps_launches = ctx.read_timing("push_sort")
     grid_ms, _ = ctx.read_timing("grid")
     sort_ms, sorts = ctx.read_timing("sort")
     out_ms, _ = ctx.read_timing("output")
@@ -96,30 +107,47 @@ def run_leg(cfg, steps, warmup, label, tuning=None):
     torch.cuda.empty_cache()
     n = cfg["n_steps"]
     job_s = (t1 - t0) / steps
-    # the push timer counts the plain push launches: one kick-only launch per
-    # job, the rest kick + drift (launches that also carry out a re-sort are
-    # timed as sorting)
+    # The push timer counts the plain push launches (one kick-only launch per
+    # job, the rest kick + drift, each carrying one or more steps); the
+    # push_sort timer the launches that also carry out a re-sort, one per
+    # species and re-sort.
+    kernels = {}
     total_bytes = ((launches - steps) * bytes_per_launch(cfg, n_total, True)
                    + steps * bytes_per_launch(cfg, n_total, False))
-    avg_launch_ms = push_ms / launches
-    achieved = total_bytes / launches / (avg_launch_ms * 1e-3) / 1e9
-    return dict(job_s=job_s, updates_per_s=n_total * n / job_s, push_ms=push_ms, launches=launches,
-                avg_launch_ms=avg_launch_ms, bytes_per_launch=total_bytes / launches,
-                achieved_gbs=achieved, grid_ms_per_job=grid_ms / steps, output_ms_per_job=out_ms / steps,
+    kernels["k_push_f32" if cfg["precision"] == "fp32" else "k_push_f64"] = dict(
+        ms=push_ms, launches=launches, bytes=total_bytes)
+    if ps_launches:
+        nspec = len(cfg["species"])
+        sorts_fused = ps_launches // nspec
+        mesh = bytes_per_push_sort(cfg, 0)
+        kernels["k_push_sort_f32"] = dict(ms=ps_ms, launches=ps_launches,
+                                          bytes=sorts_fused * (bytes_per_push_sort(cfg, n_total) - mesh
+                                                               + nspec * mesh))
+    for k in kernels.values():
+        k["avg_launch_ms"] = k["ms"] / k["launches"]
+        k["bytes_per_launch"] = k["bytes"] / k["launches"]
+        k["achieved_gbs"] = k["bytes_per_launch"] / (k["avg_launch_ms"] * 1e-3) / 1e9
+        k["ms_per_job"] = k["ms"] / steps
+        k["launches_per_job"] = k["launches"] / steps
+    dominant = max(kernels, key=lambda name: kernels[name]["ms"])
+    return dict(job_s=job_s, updates_per_s=n_total * n / job_s, kernels=kernels, dominant=dominant,
+                push_ms=push_ms, launches=launches, avg_launch_ms=kernels[dominant]["avg_launch_ms"],
+                achieved_gbs=kernels[dominant]["achieved_gbs"],
+                grid_ms_per_job=grid_ms / steps, output_ms_per_job=out_ms / steps,
                 init_ms_per_job=init_ms / steps, sort_ms_per_job=sort_ms / steps,
                 sorts_per_job=sorts / steps, pk=pk, n_particles=n_total)
 
 
-def traffic_from_profile(workload):
-    """HBM bytes per push launch from committed rocprofv3 counter summaries,
-    if they were taken on the current push kernel source."""
+def traffic_from_profile(workload, kernel):
+    """HBM bytes per launch of `kernel` from committed rocprofv3 counter
+    summaries, if they were taken on the current push kernel source."""
     path = os.path.join(ROOT, "profiles", "push_%s_traffic.json" % workload)
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
     if rec.get("push_source_sha256") != push_source_sha():
         return None
-    return rec.get("hbm_bytes_per_launch")
+    return rec.get("kernels", {}).get(kernel, {}).get("hbm_bytes_per_launch")
 
 
 def push_source_sha():
@@ -213,8 +241,9 @@ def main():
     tuning = autotune.cached_tuning(cfg)
     log("workload %s: precision %s, tuning %s" % (args.workload, cfg["precision"], tuning))
     main_leg = run_leg(cfg, args.steps, args.warmup, args.workload, tuning)
-    log("%s: %.3e updates/s, push %.3f ms/launch, %.0f GB/s" % (
-        args.workload, main_leg["updates_per_s"], main_leg["avg_launch_ms"], main_leg["achieved_gbs"]))
+    log("%s: %.3e updates/s, %s %.3f ms/launch, %.0f GB/s" % (
+        args.workload, main_leg["updates_per_s"], main_leg["dominant"], main_leg["avg_launch_ms"],
+        main_leg["achieved_gbs"]))
 
     fp64 = None
     if not args.no_fp64_leg and cfg["precision"] == "fp32":
@@ -229,6 +258,8 @@ def main():
         fp64 = dict(updates_per_s=leg["updates_per_s"], ms_per_step=leg["job_s"] * 1e3,
                     push_ms_per_launch=leg["avg_launch_ms"], push_achieved_gbs=leg["achieved_gbs"],
                     push_roofline_frac=leg["achieved_gbs"] / PEAK_HBM_GBS,
+                    push_ms_per_job=leg["push_ms"] / max(1, args.steps - 1),
+                    sort_ms_per_job=leg["sort_ms_per_job"],
                     pk_rel_err_fp32_vs_fp64_max=float(rel.max()),
                     pk_rel_err_fp32_vs_fp64_rms=float(np.sqrt(np.mean(rel ** 2))),
                     pk_bins_compared="k <= k_N/2 (%d bins)" % int(sel.sum()))
@@ -243,7 +274,7 @@ def main():
             log("cpu oracle still running")
         cpu = cpu_queue.get(timeout=60)
         cpu_proc.join(timeout=60)
-    traffic = traffic_from_profile(args.workload)
+    traffic = traffic_from_profile(args.workload, main_leg["dominant"])
     out = {
         "metric": METRIC,
         "value": main_leg["updates_per_s"],
@@ -277,17 +308,21 @@ def main():
             "unit": "GB/s",
             "frac": main_leg["achieved_gbs"] / PEAK_HBM_GBS,
             "traffic": traffic,
-            "kernel": "k_push_f32" if cfg["precision"] == "fp32" else "k_push_f64",
+            "kernel": main_leg["dominant"],
             "avg_launch_ms": main_leg["avg_launch_ms"],
-            "algorithmic_bytes_per_launch": main_leg["bytes_per_launch"],
+            "algorithmic_bytes_per_launch": main_leg["kernels"][main_leg["dominant"]]["bytes_per_launch"],
         },
         "hbm_gbs": main_leg["achieved_gbs"],
+        "kernels": {name: {k: v for k, v in rec.items() if k not in ("ms", "bytes")}
+                    for name, rec in main_leg["kernels"].items()},
         "breakdown_ms_per_job": {
-            "push": main_leg["push_ms"] / args.steps, "sort": main_leg["sort_ms_per_job"],
+            "push": main_leg["push_ms"] / args.steps,
+            "push_sort": main_leg["kernels"].get("k_push_sort_f32", {}).get("ms_per_job", 0.0),
+            "sort": main_leg["sort_ms_per_job"],
             "sorts": main_leg["sorts_per_job"], "grid": main_leg["grid_ms_per_job"],
             "output": main_leg["output_ms_per_job"], "init": main_leg["init_ms_per_job"],
-            "note": "sort = rank passes and scans, plus the push launches that carry out a "
-                    "re-sort (FP32 separable form; those launches are not in push)"},
+            "note": "push = plain push launches (several steps each); push_sort = launches that "
+                    "also carry out a re-sort; sort = rank passes, scans and separate moves"},
         "fp64_leg": fp64,
         "speedup_vs_fp64": (main_leg["updates_per_s"] / fp64["updates_per_s"]) if fp64 else None,
         "cpu_baseline": cpu,

@@ -113,7 +113,9 @@ enum {
   FDF_KERNEL_GRID = 2,       /* Fourier stage + 3-D C2R FFT of the potentials  */
   FDF_KERNEL_INIT = 3,       /* field generation and particle sampling          */
   FDF_KERNEL_OUTPUT = 4,     /* weights, deposit, forward FFT and binning       */
-  FDF_KERNEL_COUNT = 5
+  FDF_KERNEL_PUSH_SORT = 5,  /* push launches that also carry out a re-sort
+                                (their rank passes count as SORT)               */
+  FDF_KERNEL_COUNT = 6
 };
 
 typedef struct fdf_config {
@@ -188,11 +190,6 @@ typedef struct fdf_tuning {
                                     fewer waves keeping more of each block's mesh
                                     neighbourhood in cache; 0: as many as the
                                     registers allow */
-  int32_t push_block;            /* separable form: up to this many leapfrog steps
-                                    (1-8) per push launch, the particle state
-                                    staying in registers between them; a re-sort,
-                                    a grid rebuild and the final kick end a block.
-                                    Results are bit-identical for every value */
 } fdf_tuning;
 
 /* ---- lifetime -------------------------------------------------------------- */

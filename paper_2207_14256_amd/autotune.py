@@ -3,7 +3,7 @@
 Candidates are timed on the device through the C ABI's own HIP-event timers:
 
   1. launch shape -- particles per thread and the cap on resident waves per
-     SIMD, with up to 8 steps per launch -- over the full schedule;
+     SIMD -- over the full schedule;
   2. sort policy -- bucket size and the drift threshold of the adaptive
      cadence -- over the full schedule, since the cost of a stale order and the
      number of re-sorts both depend on how far the particles travel.
@@ -64,7 +64,7 @@ def autotune(cfg, path=CACHE_PATH, log=print, full_schedule=True):
     sorting = cfg.get("sort_every", 0) > 0
     base = dict(particles_per_thread=4, sort_tiles=0, sort_every=cfg.get("sort_every", 0),
                 sort_cells=3.0 if sorting else 0.0, persistent_blocks=0, use_graph=0, sort_predict=1,
-                sort_fused=1, push_waves=0, push_block=8)
+                sort_fused=1, push_waves=0)
     # 1. launch shape: particles per thread and the cap on resident waves,
     #    timed over the whole schedule (the mesh locality of the gathers, and
     #    with it the best shape, changes as the particles disperse)
@@ -90,18 +90,6 @@ def autotune(cfg, path=CACHE_PATH, log=print, full_schedule=True):
                     tiles, cells, r["wall_s"], r["push_ms"], r["sorts"], r["sort_ms"]))
                 if r["wall_s"] < best_wall:
                     chosen, best_wall = t, r["wall_s"]
-        best = chosen
-    # 3. steps per launch (more is not always better: longer launches on a
-    #    stale order against the state traffic saved)
-    if full_schedule:
-        best_wall = float("inf")
-        chosen = best
-        for block in (1, 2, 4, 8):
-            t = dict(best, push_block=block)
-            r = _run(ctx, cfg, t, cfg["n_steps"])
-            log("[autotune] push_block=%d: %.3f s" % (block, r["wall_s"]))
-            if r["wall_s"] < best_wall:
-                chosen, best_wall = t, r["wall_s"]
         best = chosen
     ctx.close()
     cache = load_cache(path)

@@ -337,7 +337,6 @@ struct fdf_ctx {
   bool sort_predict = true; // sort keys from positions extrapolated to mid-interval
   bool sort_fused = true;   // FP32 separable: re-sorts after the first ride on the push
   int push_waves = 0;       // cap on resident push waves per SIMD (0: none)
-  int push_block = 1;       // steps per separable push launch
   hipStream_t cap_stream = nullptr;   // private stream used only for graph capture
   hipStream_t launch_stream = nullptr;  // stream kernels are enqueued on right now
   std::vector<GraphRec> graphs;       // captured step sequences
@@ -601,14 +600,16 @@ int sort_species(fdf_ctx* c, double predict_tau, double a_pred) {
 // A re-sort carried out by the push of the step: per species, the rank pass
 // and scan, then the push that writes the updated state in sorted order into
 // the other copy (pa describes the step's push; its segment tables are
-// indexed per species here).  Timed as a sort.
+// indexed per species here).  The rank passes are timed as sorting, the
+// pushes on their own.
 int sort_push_species(fdf_ctx* c, double predict_tau, double a_pred, const PushArgs& pa, size_t table) {
-  std::pair<hipEvent_t, hipEvent_t> ev;
-  timing_begin(c, FDF_KERNEL_SORT, &ev);
   for (size_t i = 0; i < c->species.size(); ++i) {
     SpeciesRec& s = c->species[i];
     const SortArgs a = sort_args(c, s, predict_tau, a_pred);
+    std::pair<hipEvent_t, hipEvent_t> ev;
+    timing_begin(c, FDF_KERNEL_SORT, &ev);
     launch_sort_rank(a, stream_of(c));
+    timing_end(c, FDF_KERNEL_SORT, ev);
     PushArgs p = pa;
     p.seg = (const Segment*)(c->ws + c->lay.seg + s.cur * table) + i;
     p.dseg = (const Segment*)(c->ws + c->lay.seg + (s.cur ^ 1) * table) + i;
@@ -620,10 +621,11 @@ int sort_push_species(fdf_ctx* c, double predict_tau, double a_pred, const PushA
     p.sort_rank = a.rank;
     p.sort_bucket = a.bucket;
     p.sort_start = a.count;
+    timing_begin(c, FDF_KERNEL_PUSH_SORT, &ev);
     launch_push_sort(p, stream_of(c));
+    timing_end(c, FDF_KERNEL_PUSH_SORT, ev);
     s.cur ^= 1;
   }
-  timing_end(c, FDF_KERNEL_SORT, ev);
   return launched(c, "sort + push");
 }
 
@@ -1009,46 +1011,6 @@ int enqueue_steps(fdf_ctx* c, int32_t n) {
     }
     *tau = c->sort_predict ? 0.5 * span : 0.0;
   };
-  // Steps queued for one launch.  The separable form carries up to push_block
-  // steps per launch with the particle state in registers; the queue is
-  // flushed before anything that must see the state or changes the grids (a
-  // re-sort, a grid build) and before the final kick-only launch.
-  struct Pending {
-    std::vector<StepCoef> steps;
-    bool drift = true, fused = false;
-    double tau = 0.0, amid = 0.0, kick_open = 0.0;
-    int blend = 0, sel = 0;
-  } pend;
-  const int block_max = pa.eom == FDF_EOM_SEPARABLE ? std::max(1, std::min(c->push_block, kMaxSub)) : 1;
-  auto flush = [&]() -> int {
-    if (pend.steps.empty()) return FDF_OK;
-    PushArgs p = pa;
-    p.seg = (const Segment*)(c->ws + c->lay.seg + c->species[0].cur * table);
-    p.nsub = (int)pend.steps.size();
-    for (int s = 0; s < p.nsub; ++s) p.sub[s] = pend.steps[s];
-    p.do_drift = pend.drift;
-    p.blend = pend.blend;
-    p.grid_sel = pend.sel;
-    // the other forms read the single step's coefficients from the scalars
-    p.kick = pend.steps[0].kick;
-    p.kick_open = pend.kick_open;
-    p.a_kick = pend.steps[0].a_kick;
-    p.drift = pend.steps[0].drift;
-    p.a_drift = pend.steps[0].a_drift;
-    p.blend_t = pend.steps[0].blend_t;
-    int r;
-    if (pend.fused) {
-      r = sort_push_species(c, pend.tau, pend.amid, p, table);
-    } else {
-      std::pair<hipEvent_t, hipEvent_t> ev;
-      timing_begin(c, FDF_KERNEL_PUSH, &ev);
-      launch_push(p, stream_of(c));
-      timing_end(c, FDF_KERNEL_PUSH, ev);
-      r = launched(c, "push");
-    }
-    pend = Pending{};
-    return r;
-  };
   for (int j = 0; j <= nabs; ++j) {
     int t;            // integer time of this launch's kick
     double kclose = 0, kopen = 0, drift = 0, a_drift = 0;   // half-kicks ending / starting at t
@@ -1064,21 +1026,13 @@ int enqueue_steps(fdf_ctx* c, int32_t n) {
     // the separable force does not depend on q: both halves as one kick
     const double kick = pa.eom == FDF_EOM_SEPARABLE ? kclose + kopen : kclose;
     const double a_kick = c->a[t];
-    int blend = 0, sel = 0;
-    double blend_t = 0.0;
+    pa.blend = 0;
     if (!c->anchors.empty()) {
       // super-steps: grids at the anchors around t, interpolated linearly in a
       const auto& an = c->anchors;
       size_t iv = 0;
       while (iv + 2 < an.size() && an[iv + 1] <= t) ++iv;
       const int kA = an[iv], kB = an[iv + 1];
-      bool ready = true;
-      for (size_t f = 0; f < c->fields.size(); ++f) {
-        if (!used[f]) continue;
-        const FieldRec& fr = c->fields[f];
-        ready = ready && ((fr.tag[0] == kA && fr.tag[1] == kB) || (fr.tag[1] == kA && fr.tag[0] == kB));
-      }
-      if (!ready && (rc = flush())) return rc;
       int fsel_all = -1;
       for (size_t f = 0; f < c->fields.size(); ++f) {
         if (!used[f]) continue;
@@ -1101,25 +1055,22 @@ int enqueue_steps(fdf_ctx* c, int32_t n) {
         if (fsel_all >= 0 && fsel != fsel_all) return fail(c, FDF_ERR_STATE, "grid sets of fields out of step");
         fsel_all = fsel;
       }
-      blend = 1;
-      sel = fsel_all < 0 ? 0 : fsel_all;
-      blend_t = (a_kick - c->a[kA]) / (c->a[kB] - c->a[kA]);
+      pa.blend = 1;
+      pa.grid_sel = fsel_all < 0 ? 0 : fsel_all;
+      pa.blend_t = (a_kick - c->a[kA]) / (c->a[kB] - c->a[kA]);
     } else {
       for (size_t f = 0; f < c->fields.size(); ++f) {
         if (!used[f]) continue;
         if (!c->fields[f].has_grid || (tdep && c->fields[f].grid_a != a_kick)) {
-          if ((rc = flush())) return rc;
           rc = build_grid(c, (int)f, a_kick);
           if (rc) return rc;
         }
       }
     }
-    if (!pend.steps.empty() && (pend.blend != blend || pend.sel != sel) && (rc = flush())) return rc;
     bool fused_sort = false;    // this step's push also performs the re-sort
     double tau_pred = 0.0, a_mid = 0.0;
     if (j < nabs) {
       if (sort_due(t)) {
-        if ((rc = flush())) return rc;
         sort_prediction(t, &tau_pred, &a_mid);
         // the first sort takes two passes (the second orders cells in buckets)
         const int passes = c->sorted_once ? 1 : 2;
@@ -1132,21 +1083,25 @@ int enqueue_steps(fdf_ctx* c, int32_t n) {
       }
       c->drift_cells += typical_drift_cells(c, drift, a_drift);
     }
-    const bool drift_step = j < nabs;
-    if (!drift_step && (rc = flush())) return rc;   // the kick-only launch goes alone
-    if (fused_sort) {                               // the queue is empty here
-      pend.fused = true;
-      pend.tau = tau_pred;
-      pend.amid = a_mid;
+    pa.seg = (const Segment*)(c->ws + c->lay.seg + c->species[0].cur * table);
+    pa.kick = kick;
+    pa.kick_open = pa.eom == FDF_EOM_SEPARABLE ? 0.0 : kopen;
+    pa.a_kick = a_kick;
+    pa.do_drift = j < nabs;
+    pa.drift = drift;
+    pa.a_drift = a_drift;
+    if (fused_sort) {
+      rc = sort_push_species(c, tau_pred, a_mid, pa, table);
+      if (rc) return rc;
+      continue;
     }
-    pend.steps.push_back(StepCoef{kick, a_kick, drift, a_drift, blend_t});
-    pend.drift = drift_step;
-    pend.blend = blend;
-    pend.sel = sel;
-    pend.kick_open = pa.eom == FDF_EOM_SEPARABLE ? 0.0 : kopen;
-    if (((int)pend.steps.size() >= block_max || !drift_step) && (rc = flush())) return rc;
+    std::pair<hipEvent_t, hipEvent_t> ev;
+    timing_begin(c, FDF_KERNEL_PUSH, &ev);
+    launch_push(pa, stream_of(c));
+    timing_end(c, FDF_KERNEL_PUSH, ev);
+    rc = launched(c, "push");
+    if (rc) return rc;
   }
-  if ((rc = flush())) return rc;
   c->step_index = k0 + n;
   c->stepped = true;
   return FDF_OK;
@@ -1565,7 +1520,6 @@ int fdf_get_tuning(const fdf_ctx* c, fdf_tuning* t) {
   t->sort_predict = c->sort_predict ? 1 : 0;
   t->sort_fused = c->sort_fused ? 1 : 0;
   t->push_waves = c->push_waves;
-  t->push_block = c->push_block;
   return FDF_OK;
 }
 
@@ -1587,7 +1541,6 @@ int fdf_set_tuning(fdf_ctx* c, const fdf_tuning* t) {
   if (t->sort_fused != 0 && t->sort_fused != 1) return fail(c, FDF_ERR_ARG, "sort_fused must be 0 or 1");
   if (t->push_waves != 0 && (t->push_waves < 2 || t->push_waves > 8))
     return fail(c, FDF_ERR_ARG, "push_waves must be 0 or in [2, 8]");
-  if (t->push_block < 1 || t->push_block > kMaxSub) return fail(c, FDF_ERR_ARG, "push_block must be in [1, 8]");
   if (p != c->ppt) c->seg_dirty = true;   // chunk boundaries depend on the block size
   clear_graphs(c);
   c->persistent = t->persistent_blocks;
@@ -1599,7 +1552,6 @@ int fdf_set_tuning(fdf_ctx* c, const fdf_tuning* t) {
   c->sort_predict = t->sort_predict != 0;
   c->sort_fused = t->sort_fused != 0;
   c->push_waves = t->push_waves;
-  c->push_block = t->push_block;
   return FDF_OK;
 }
 

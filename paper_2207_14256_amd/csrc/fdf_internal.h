@@ -83,19 +83,6 @@ struct Segment {
   int64_t chunk_begin;     // first chunk of this segment in the launch
 };
 
-// Coefficients of one leapfrog step of the separable push.
-struct StepCoef {
-  double kick;             // fused kick coefficient [Mpc]
-  double a_kick;           // a at the kick
-  double drift;            // Delta tau of the drift [Mpc]
-  double a_drift;          // a_{k+1/2}
-  double blend_t;          // super-steps: interpolation weight of the later anchor
-};
-
-// Most leapfrog steps one separable push launch carries (the particle state
-// stays in registers between them; the potentials must not change in between).
-constexpr int kMaxSub = 8;
-
 struct PushArgs {
   const Segment* seg;      // device array
   int32_t nseg;
@@ -119,12 +106,6 @@ struct PushArgs {
   int32_t grid_sel;        // which set holds the earlier anchor: 0 = grid, 1 = grid2
   double blend_t;          // interpolation weight of the later anchor
   int32_t lds_reserve;     // bytes of LDS reserved per block (caps resident waves), or 0
-  // separable form (k_push_f32, k_push_f64, k_push_sort_f32): the launch
-  // carries nsub steps with coefficients sub[0 .. nsub-1] (the scalar kick,
-  // a_kick, drift, a_drift and blend_t above are read by the other forms only);
-  // do_drift = 0 only with nsub = 1
-  int32_t nsub;
-  StepCoef sub[kMaxSub];
   // push fused with the move of a re-sort (launch_push_sort; FP32 separable
   // form, one species: seg and dseg point at its entry in the two tables,
   // total_chunks counts its kSortBlock-particle rank blocks)

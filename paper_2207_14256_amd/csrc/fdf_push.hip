@@ -1,11 +1,10 @@
 // Gather + kick-drift-kick push of the neutrino tracers (sec. 3.3), gfx950.
 //
-// One launch advances every species by one or more leapfrog steps
-// (PushArgs::nsub, the particle state staying in registers in between): the
-// kick of the closing half of step k-1 and the opening half of step k are
-// evaluated at the same (x_k, a_k), so they are applied as one kick with the
-// summed Delta tau; then the drift.  The last launch of a call is a kick
-// alone, leaving q at a schedule point.
+// One launch advances every species by one leapfrog step: the kick of the
+// closing half of step k-1 and the opening half of step k are evaluated at the
+// same (x_k, a_k), so they are applied as one kick with the summed Delta tau;
+// then the drift.  The last launch of a call is a kick alone, leaving q at a
+// schedule point.
 //
 // Per particle: CIC (trilinear; or TSC, 27 points, when PushArgs::tsc is set)
 // interpolation of the gradient grids at x,
@@ -103,22 +102,21 @@ struct ConstF32 {
 };
 
 template <bool BLEND>
-__device__ __forceinline__ ConstF32 const_f32(const PushArgs& a, const Segment& sg, int step) {
-  const StepCoef& c = a.sub[step];
+__device__ __forceinline__ ConstF32 const_f32(const PushArgs& a, const Segment& sg) {
   ConstF32 k;
   k.shift = 32 - a.log2g;
   k.gmask = (uint32_t)a.G - 1u;
   k.G = (uint32_t)a.G;
   k.finv = __uint_as_float((uint32_t)(127 - k.shift) << 23);   // 2^-shift
-  k.kick = (float)c.kick;
-  const float ma = (float)(sg.m * c.a_kick);
-  const float mah = (float)(sg.m * c.a_drift);
+  k.kick = (float)a.kick;
+  const float ma = (float)(sg.m * a.a_kick);
+  const float mah = (float)(sg.m * a.a_drift);
   k.ma2 = ma * ma;
   k.mah2 = mah * mah;
-  k.dscale = (float)(c.drift * 4294967296.0 / a.box);
+  k.dscale = (float)(a.drift * 4294967296.0 / a.box);
   k.gridA = (BLEND && a.grid_sel) ? sg.grid2 : sg.grid;
   k.gridB = (BLEND && a.grid_sel) ? sg.grid : sg.grid2;
-  k.tb = (float)c.blend_t;
+  k.tb = (float)a.blend_t;
   k.ta = 1.0f - k.tb;
   return k;
 }
@@ -184,8 +182,9 @@ __device__ __forceinline__ void push_chunk_f32(const PushArgs& a, int64_t chunk)
 #pragma unroll
   for (int d = 0; d < 3; ++d) { X[d] = sg.xu[d] + c0; Q0[d] = sg.q0f[d] + c0; DQ[d] = sg.dqf[d] + c0; }
 
-  // loads of all PPT particles, the launch's steps, then the stores: no store
-  // stands between two loads, and the state stays in registers across steps
+  // three phases, so that the loads of all PPT particles are in flight
+  // together (a store between them would pin the next loads behind it)
+  const ConstF32 k = const_f32<BLEND>(a, sg);
   uint32_t xu[PPT][3];
   float dq[PPT][3], q0[PPT][3];
 #pragma unroll
@@ -199,14 +198,11 @@ __device__ __forceinline__ void push_chunk_f32(const PushArgs& a, int64_t chunk)
       dq[p][d] = ldnt(&DQ[d][i]);
     }
   }
-  for (int step = 0; step < a.nsub; ++step) {
-    const ConstF32 k = const_f32<BLEND>(a, sg, step);
 #pragma unroll
-    for (int p = 0; p < PPT; ++p) {
-      const uint32_t i = threadIdx.x + (uint32_t)(p * kBlock);
-      if ((int64_t)i >= left) break;
-      update_f32<NSLOT, BLEND, TSC, OFF32>(k, a.do_drift != 0, xu[p], q0[p], dq[p]);
-    }
+  for (int p = 0; p < PPT; ++p) {
+    const uint32_t i = threadIdx.x + (uint32_t)(p * kBlock);
+    if ((int64_t)i >= left) break;
+    update_f32<NSLOT, BLEND, TSC, OFF32>(k, a.do_drift != 0, xu[p], q0[p], dq[p]);
   }
 #pragma unroll
   for (int p = 0; p < PPT; ++p) {
@@ -223,8 +219,8 @@ __device__ __forceinline__ void push_chunk_f32(const PushArgs& a, int64_t chunk)
 
 // A push that also performs a re-sort of one species whose rank pass has run:
 // one block per rank block of kSortBlock particles.  The block reads its
-// particles in place (coalesced), updates them (all of the launch's steps),
-// stages the whole new state in LDS and writes it out in sorted order,
+// particles in place (coalesced), updates them, stages the whole new state
+// in LDS and writes it out in sorted order,
 // element e of the sorted run to start[bucket[e]] + rank[e] of the other
 // buffer copy, so consecutive threads write consecutive slots of a bucket
 // fragment.  The re-sort then costs the push the writes of q0 and id and the
@@ -273,14 +269,12 @@ __global__ void __launch_bounds__(kFusedThreads) k_push_sort_f32(PushArgs a) {
     if (e >= cnt) break;
     dst[r] = (int64_t)a.sort_start[bucket[r]] + rank[r];
   }
-  for (int step = 0; step < a.nsub; ++step) {
-    const ConstF32 k = const_f32<BLEND>(a, sg, step);
+  const ConstF32 k = const_f32<BLEND>(a, sg);
 #pragma unroll
-    for (int r = 0; r < kPer; ++r) {
-      const int e = threadIdx.x + r * kFusedThreads;
-      if (e >= cnt) break;
-      update_f32<NSLOT, BLEND, TSC, OFF32>(k, true, xu[r], q0[r], dq[r]);
-    }
+  for (int r = 0; r < kPer; ++r) {
+    const int e = threadIdx.x + r * kFusedThreads;
+    if (e >= cnt) break;
+    update_f32<NSLOT, BLEND, TSC, OFF32>(k, true, xu[r], q0[r], dq[r]);
   }
 #pragma unroll
   for (int r = 0; r < kPer; ++r) {
@@ -359,7 +353,7 @@ __device__ __forceinline__ void gather_stencil_f64(const void* grid, const uint3
   }
 }
 
-// Constants of the FP64 update of one segment at one step.
+// Constants of the FP64 update of one segment.
 struct ConstF64 {
   int gm;
   uint32_t G;
@@ -369,20 +363,19 @@ struct ConstF64 {
 };
 
 template <bool BLEND>
-__device__ __forceinline__ ConstF64 const_f64(const PushArgs& a, const Segment& sg, int step) {
-  const StepCoef& c = a.sub[step];
+__device__ __forceinline__ ConstF64 const_f64(const PushArgs& a, const Segment& sg) {
   ConstF64 k;
   k.gm = a.G - 1;
   k.G = (uint32_t)a.G;
   k.ginv = (double)a.G / a.box;
-  k.ma = sg.m * c.a_kick;
-  k.mah = sg.m * c.a_drift;
-  k.kick = c.kick;
-  k.drift = c.drift;
+  k.ma = sg.m * a.a_kick;
+  k.mah = sg.m * a.a_drift;
+  k.kick = a.kick;
+  k.drift = a.drift;
   k.box = a.box;
   k.gridA = (BLEND && a.grid_sel) ? sg.grid2 : sg.grid;
   k.gridB = (BLEND && a.grid_sel) ? sg.grid : sg.grid2;
-  k.tb = c.blend_t;
+  k.tb = a.blend_t;
   k.ta = 1.0 - k.tb;
   return k;
 }
@@ -453,14 +446,12 @@ __device__ __forceinline__ void push_chunk_f64(const PushArgs& a, int64_t chunk)
       q0[p][d] = ldnt(&Q0[d][i]);
     }
   }
-  for (int step = 0; step < a.nsub; ++step) {
-    const ConstF64 k = const_f64<BLEND>(a, sg, step);
+  const ConstF64 k = const_f64<BLEND>(a, sg);
 #pragma unroll
-    for (int p = 0; p < PPT; ++p) {
-      const uint32_t i = threadIdx.x + (uint32_t)(p * kBlock);
-      if ((int64_t)i >= left) break;
-      update_f64<NSLOT, BLEND, TSC, OFF32>(k, a.do_drift != 0, x[p], q[p], q0[p]);
-    }
+  for (int p = 0; p < PPT; ++p) {
+    const uint32_t i = threadIdx.x + (uint32_t)(p * kBlock);
+    if ((int64_t)i >= left) break;
+    update_f64<NSLOT, BLEND, TSC, OFF32>(k, a.do_drift != 0, x[p], q[p], q0[p]);
   }
 #pragma unroll
   for (int p = 0; p < PPT; ++p) {

@@ -21,7 +21,7 @@ PK_CROSS, PK_AUTO = 0, 1
 PK_DENSITY, PK_MOMENTUM = 0, 1
 SPECIES_PRE_IC = 1
 KERNEL_PUSH, KERNEL_SORT, KERNEL_GRID, KERNEL_INIT, KERNEL_OUTPUT = range(5)
-KERNEL_CLASSES = {"push": 0, "sort": 1, "grid": 2, "init": 3, "output": 4}
+KERNEL_CLASSES = {"push": 0, "sort": 1, "grid": 2, "init": 3, "output": 4, "push_sort": 5}
 
 # every symbol the header declares
 EXPORTS = [
@@ -68,8 +68,7 @@ class Tuning(ctypes.Structure):
                 ("persistent_blocks", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("sort_predict", ctypes.c_int32),
                 ("sort_fused", ctypes.c_int32),
-                ("push_waves", ctypes.c_int32),
-                ("push_block", ctypes.c_int32)]
+                ("push_waves", ctypes.c_int32)]
 
 
 class FastDFError(RuntimeError):
@@ -352,16 +351,14 @@ class Context:
         return dict(particles_per_thread=t.particles_per_thread, sort_tiles=t.sort_tiles,
                     sort_every=t.sort_every, sort_cells=t.sort_cells,
                     persistent_blocks=t.persistent_blocks, use_graph=t.use_graph,
-                    sort_predict=t.sort_predict, sort_fused=t.sort_fused, push_waves=t.push_waves,
-                    push_block=t.push_block)
+                    sort_predict=t.sort_predict, sort_fused=t.sort_fused, push_waves=t.push_waves)
 
     def set_tuning(self, **kw):
         cur = self.get_tuning()
         cur.update(kw)
         t = Tuning(cur["particles_per_thread"], cur["sort_tiles"], cur["sort_every"],
                    float(cur["sort_cells"]), int(cur["persistent_blocks"]), int(cur["use_graph"]),
-                   int(cur["sort_predict"]), int(cur["sort_fused"]), int(cur["push_waves"]),
-                   int(cur["push_block"]))
+                   int(cur["sort_predict"]), int(cur["sort_fused"]), int(cur["push_waves"]))
         self._check(self.lib.fdf_set_tuning(self.ctx, ctypes.byref(t)), "fdf_set_tuning")
 
     def sync(self):

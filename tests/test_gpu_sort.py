@@ -125,51 +125,3 @@ def test_launch_shape_invariance(prec):
         got = _state_by_id(cfg, dict(sort_every=4, particles_per_thread=ppt, push_waves=waves))
         for i, (a, b) in enumerate(zip(ref, got)):
             assert np.array_equal(a, b), (ppt, waves, i)
-
-
-BLOCK_CASES = {
-    "fp32-slip-two-species": (dict(grid_n=32, n_side=29, n_steps=60, box_mpc=600.0, z_begin=1e6, z_end=10.0,
-                                   precision="fp32"), 23),
-    "fp64-slip": (dict(grid_n=32, n_side=25, n_steps=60, box_mpc=600.0, z_begin=1e6, z_end=10.0,
-                       precision="fp64"), 0),
-    "fp32-radmat-superstep-tsc": (dict(grid_n=16, n_side=13, n_steps=60, box_mpc=600.0, z_begin=1e6, z_end=10.0,
-                                       model="radmat", omega_m=0.9999, omega_r=1e-4, slip_amp=0.0,
-                                       superstep_tol=0.01, interp_order=2, precision="fp32"), 0),
-    "fp64-radmat-rebuild-every-step": (dict(grid_n=16, n_side=13, n_steps=60, box_mpc=600.0, z_begin=1e6,
-                                            z_end=10.0, model="radmat", omega_m=0.9999, omega_r=1e-4,
-                                            precision="fp64"), 0),
-    "fp32-exact-eom": (dict(grid_n=16, n_side=13, n_steps=60, box_mpc=600.0, z_begin=1e6, z_end=10.0,
-                            eom="exact", precision="fp32"), 0),
-}
-
-
-@pytest.mark.parametrize("case", sorted(BLOCK_CASES))
-def test_push_block_invariance(case):
-    """Several leapfrog steps per launch (push_block) give the state of one
-    launch per step bit for bit, with re-sorts, super-steps, per-step grid
-    rebuilds and the other equations of motion (which keep one step per
-    launch)."""
-    print("[gpu-case] push_block invariance %s" % case, flush=True)
-    base, second = BLOCK_CASES[case]
-    cfg = workloads.small("c2", **base)
-    cfg["sort_every"] = 1
-    if second:
-        cfg["fields"] = cfg["fields"] + [cfg["fields"][0] + 1]
-        cfg["species"].append(dict(field=1, m=0.2, n_side=second, seed=2999))
-    ref = _state_by_id(cfg, dict(sort_every=5, push_block=1))
-    for block, extra in ((8, {}), (3, dict(sort_every=0)), (5, dict(sort_cells=0.5)), (8, dict(use_graph=1))):
-        got = _state_by_id(cfg, dict(dict(sort_every=5, push_block=block), **extra))
-        for i, (a, b) in enumerate(zip(ref, got)):
-            assert np.array_equal(a, b), (case, block, extra, i)
-
-
-def test_push_block_backward_walk():
-    """Blocked launches in both directions of a forward-backward walk."""
-    print("[gpu-case] push_block backward walk", flush=True)
-    cfg = workloads.small("c2", grid_n=32, n_side=24, n_steps=60, precision="fp32",
-                          box_mpc=600.0, z_begin=1e6, z_end=10.0)
-    cfg["sort_every"] = 1
-    ref = _state_by_id(cfg, dict(sort_every=0, push_block=1), steps=60, back=35)
-    got = _state_by_id(cfg, dict(sort_every=3, push_block=8), steps=60, back=35)
-    for i, (a, b) in enumerate(zip(ref, got)):
-        assert np.array_equal(a, b), i
