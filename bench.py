@@ -108,9 +108,8 @@ def run_leg(cfg, steps, warmup, label, tuning=None):
     n = cfg["n_steps"]
     job_s = (t1 - t0) / steps
     # The push timer counts the plain push launches (one kick-only launch per
-    # job, the rest kick + drift, each carrying one or more steps); the
-    # push_sort timer the launches that also carry out a re-sort, one per
-    # species and re-sort.
+    # job, the rest kick + drift, one step each); the push_sort timer the
+    # launches that also carry out a re-sort, one per species and re-sort.
     kernels = {}
     total_bytes = ((launches - steps) * bytes_per_launch(cfg, n_total, True)
                    + steps * bytes_per_launch(cfg, n_total, False))
@@ -321,7 +320,7 @@ def main():
             "sort": main_leg["sort_ms_per_job"],
             "sorts": main_leg["sorts_per_job"], "grid": main_leg["grid_ms_per_job"],
             "output": main_leg["output_ms_per_job"], "init": main_leg["init_ms_per_job"],
-            "note": "push = plain push launches (several steps each); push_sort = launches that "
+            "note": "push = plain push launches (one step each); push_sort = push launches that "
                     "also carry out a re-sort; sort = rank passes, scans and separate moves"},
         "fp64_leg": fp64,
         "speedup_vs_fp64": (main_leg["updates_per_s"] / fp64["updates_per_s"]) if fp64 else None,

@@ -92,7 +92,7 @@ __device__ __forceinline__ void gather_stencil_bf16(const void* grid, const uint
   }
 }
 
-// Constants of the FP32 update of one segment at one step.
+// Launch constants of the FP32 update of one segment.
 struct ConstF32 {
   int shift;
   uint32_t gmask, G;
@@ -219,12 +219,12 @@ __device__ __forceinline__ void push_chunk_f32(const PushArgs& a, int64_t chunk)
 
 // A push that also performs a re-sort of one species whose rank pass has run:
 // one block per rank block of kSortBlock particles.  The block reads its
-// particles in place (coalesced), updates them, stages the whole new state
-// in LDS and writes it out in sorted order,
-// element e of the sorted run to start[bucket[e]] + rank[e] of the other
-// buffer copy, so consecutive threads write consecutive slots of a bucket
-// fragment.  The re-sort then costs the push the writes of q0 and id and the
-// index reads, instead of a pass of its own over the whole state.
+// particles in place (coalesced), updates them, stages the whole new state in
+// LDS and writes it out in sorted order, element e of the sorted run to
+// start[bucket[e]] + rank[e] of the other buffer copy, so consecutive threads
+// write consecutive slots of a bucket fragment.  The re-sort then costs the
+// push the writes of q0 and id and the index reads, instead of a pass of its
+// own over the whole state.
 constexpr int kFusedThreads = 256;   // 4 waves per block, 4 particles per thread
 
 template <int NSLOT, bool BLEND, bool TSC, bool OFF32>
@@ -353,116 +353,76 @@ __device__ __forceinline__ void gather_stencil_f64(const void* grid, const uint3
   }
 }
 
-// Constants of the FP64 update of one segment.
-struct ConstF64 {
-  int gm;
-  uint32_t G;
-  double ginv, ma, mah, kick, drift, box, ta, tb;
-  const void* gridA;
-  const void* gridB;
-};
-
-template <bool BLEND>
-__device__ __forceinline__ ConstF64 const_f64(const PushArgs& a, const Segment& sg) {
-  ConstF64 k;
-  k.gm = a.G - 1;
-  k.G = (uint32_t)a.G;
-  k.ginv = (double)a.G / a.box;
-  k.ma = sg.m * a.a_kick;
-  k.mah = sg.m * a.a_drift;
-  k.kick = a.kick;
-  k.drift = a.drift;
-  k.box = a.box;
-  k.gridA = (BLEND && a.grid_sel) ? sg.grid2 : sg.grid;
-  k.gridB = (BLEND && a.grid_sel) ? sg.grid : sg.grid2;
-  k.tb = a.blend_t;
-  k.ta = 1.0 - k.tb;
-  return k;
-}
-
-// The FP64 update of one particle (same operations as the FP32 form, in
-// binary64, with the periodic wrap taken as a floor-mod of the position).
-template <int NSLOT, bool BLEND, bool TSC, bool OFF32>
-__device__ __forceinline__ void update_f64(const ConstF64& k, bool drift, double* x, double* q, const double* q0) {
-#pragma clang fp contract(off)
-  constexpr int NP = Stencil<TSC>::N;
-  uint32_t cell[NP];
-  double w[NP];
-  stencil_f64<TSC>(x, k.ginv, k.gm, k.G, cell, w);
-  double g[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  if (BLEND) {
-    double wa[NP], wb[NP];
-#pragma unroll
-    for (int cc = 0; cc < NP; ++cc) { wa[cc] = k.ta * w[cc]; wb[cc] = k.tb * w[cc]; }
-    gather_stencil_f64<NSLOT, TSC, OFF32>(k.gridA, cell, wa, g);
-    gather_stencil_f64<NSLOT, TSC, OFF32>(k.gridB, cell, wb, g);
-  } else {
-    gather_stencil_f64<NSLOT, TSC, OFF32>(k.gridA, cell, w, g);
-  }
-  if (NSLOT == 4) { g[3] = g[0]; g[4] = g[1]; g[5] = g[2]; }
-  const double q0sq = fma(q0[0], q0[0], fma(q0[1], q0[1], q0[2] * q0[2]));
-  const double e0 = sqrt(q0sq + k.ma * k.ma);
-  const double qg = fma(q0[0], g[3], fma(q0[1], g[4], q0[2] * g[5])) / e0 + g[6];
-  const double cphi = q0sq / e0;
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    const double F = fma(q0[d], qg, fma(-cphi, g[3 + d], -(e0 * g[d])));
-    q[d] = fma(k.kick, F, q[d]);
-  }
-  if (drift) {
-    const double e = sqrt(fma(q[0], q[0], fma(q[1], q[1], q[2] * q[2])) + k.mah * k.mah);
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      double xn = fmod(fma(k.drift, q[d] / e, x[d]), k.box);   // floor-mod as numpy.mod
-      if (xn < 0.0) xn += k.box;
-      x[d] = xn;
-    }
-  }
-}
-
 template <int NSLOT, int PPT, bool BLEND, bool TSC, bool OFF32>
 __device__ __forceinline__ void push_chunk_f64(const PushArgs& a, int64_t chunk) {
+#pragma clang fp contract(off)
+  constexpr int NP = Stencil<TSC>::N;
   const int s = find_segment(a.seg, a.nseg, chunk);
   const Segment& sg = a.seg[s];
+  const int64_t n = sg.n;
   const int64_t first = (chunk - sg.chunk_begin) * (int64_t)(kBlock * PPT) + threadIdx.x;
+  const int gm = a.G - 1;
+  const double ginv = (double)a.G / a.box;
+  const double ma = sg.m * a.a_kick;
+  const double mah = sg.m * a.a_drift;
+  const uint32_t G = (uint32_t)a.G;
+  const void* gridA = (BLEND && a.grid_sel) ? sg.grid2 : sg.grid;
+  const void* gridB = (BLEND && a.grid_sel) ? sg.grid : sg.grid2;
+  const double tb = a.blend_t, ta = 1.0 - tb;
   // chunk-relative arrays: a uniform base and a 32-bit lane index
   const int64_t c0 = first - threadIdx.x;
-  const int64_t left = sg.n - c0;
+  const int64_t left = n - c0;
   double* X[3];
   double* Q[3];
   const double* Q0[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) { X[d] = sg.xd[d] + c0; Q[d] = sg.qd[d] + c0; Q0[d] = sg.q0d[d] + c0; }
 
-  double x[PPT][3], q[PPT][3], q0[PPT][3];
 #pragma unroll
   for (int p = 0; p < PPT; ++p) {
     const uint32_t i = threadIdx.x + (uint32_t)(p * kBlock);
     if ((int64_t)i >= left) break;
+    double x[3], q[3], q0[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      x[p][d] = ldnt(&X[d][i]);
-      q[p][d] = ldnt(&Q[d][i]);
-      q0[p][d] = ldnt(&Q0[d][i]);
+      x[d] = ldnt(&X[d][i]);
+      q[d] = ldnt(&Q[d][i]);
+      q0[d] = ldnt(&Q0[d][i]);
     }
-  }
-  const ConstF64 k = const_f64<BLEND>(a, sg);
+    uint32_t cell[NP];
+    double w[NP];
+    stencil_f64<TSC>(x, ginv, gm, G, cell, w);
+    double g[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (BLEND) {
+      double wa[NP], wb[NP];
 #pragma unroll
-  for (int p = 0; p < PPT; ++p) {
-    const uint32_t i = threadIdx.x + (uint32_t)(p * kBlock);
-    if ((int64_t)i >= left) break;
-    update_f64<NSLOT, BLEND, TSC, OFF32>(k, a.do_drift != 0, x[p], q[p], q0[p]);
-  }
+      for (int cc = 0; cc < NP; ++cc) { wa[cc] = ta * w[cc]; wb[cc] = tb * w[cc]; }
+      gather_stencil_f64<NSLOT, TSC, OFF32>(gridA, cell, wa, g);
+      gather_stencil_f64<NSLOT, TSC, OFF32>(gridB, cell, wb, g);
+    } else {
+      gather_stencil_f64<NSLOT, TSC, OFF32>(gridA, cell, w, g);
+    }
+    if (NSLOT == 4) { g[3] = g[0]; g[4] = g[1]; g[5] = g[2]; }
+    const double q0sq = fma(q0[0], q0[0], fma(q0[1], q0[1], q0[2] * q0[2]));
+    const double e0 = sqrt(q0sq + ma * ma);
+    const double qg = fma(q0[0], g[3], fma(q0[1], g[4], q0[2] * g[5])) / e0 + g[6];
+    const double cphi = q0sq / e0;
 #pragma unroll
-  for (int p = 0; p < PPT; ++p) {
-    const uint32_t i = threadIdx.x + (uint32_t)(p * kBlock);
-    if ((int64_t)i >= left) break;
+    for (int d = 0; d < 3; ++d) {
+      const double F = fma(q0[d], qg, fma(-cphi, g[3 + d], -(e0 * g[d])));
+      q[d] = fma(a.kick, F, q[d]);
+    }
     if (a.do_drift) {
+      const double e = sqrt(fma(q[0], q[0], fma(q[1], q[1], q[2] * q[2])) + mah * mah);
 #pragma unroll
-      for (int d = 0; d < 3; ++d) stnt(x[p][d], &X[d][i]);
+      for (int d = 0; d < 3; ++d) {
+        double xn = fmod(fma(a.drift, q[d] / e, x[d]), a.box);   // floor-mod as numpy.mod
+        if (xn < 0.0) xn += a.box;
+        stnt(xn, &X[d][i]);
+      }
     }
 #pragma unroll
-    for (int d = 0; d < 3; ++d) stnt(q[p][d], &Q[d][i]);
+    for (int d = 0; d < 3; ++d) stnt(q[d], &Q[d][i]);
   }
 }
 
