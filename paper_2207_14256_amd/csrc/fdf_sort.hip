@@ -116,40 +116,46 @@ __global__ void __launch_bounds__(kRankThreads) k_sort_rank(SortArgs a) {
   uint64_t v[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r) v[r] = kv[4 * tid + r];
-  // element e = 4 tid + r keeps the smaller of its pair exactly when it is the
-  // lower index of an ascending pair or the upper index of a descending one
+  // Element e = 4 tid + r keeps the smaller of its pair exactly when it is the
+  // lower index of an ascending pair or the upper index of a descending one.
+  // Keys are unique (the slot is in the low bits), so one comparison decides:
+  // take the partner's key when (partner < own) == keep_min.  For partners
+  // 4 or more apart, both bits of e that decide keep_min are bits of tid, so
+  // the direction is one per thread and stage.
 #pragma unroll
   for (int k = 2; k <= kRankBlock; k <<= 1) {
 #pragma unroll
     for (int j = k >> 1; j > 0; j >>= 1) {
-      if (j >= 4 * 64) {                 // partner in another wave
-        __syncthreads();
+      if (j >= 4) {
+        const bool upper = (tid & (j >> 2)) != 0;
+        const bool desc = k < kRankBlock && (tid & (k >> 2)) != 0;
+        const bool keep_min = upper == desc;
+        if (j >= 4 * 64) {               // partner in another wave
+          __syncthreads();
 #pragma unroll
-        for (int r = 0; r < 4; ++r) kv[4 * tid + r] = v[r];
-        __syncthreads();
+          for (int r = 0; r < 4; ++r) kv[4 * tid + r] = v[r];
+          __syncthreads();
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int e = 4 * tid + r;
-          const uint64_t w = kv[e ^ j];
-          const bool keep_min = ((e & j) == 0) == ((e & k) == 0);
-          v[r] = keep_min ? min(v[r], w) : max(v[r], w);
-        }
-      } else if (j >= 4) {               // partner in another lane of the wave
+          for (int r = 0; r < 4; ++r) {
+            const uint64_t w = kv[(4 * tid + r) ^ j];
+            v[r] = ((w < v[r]) == keep_min) ? w : v[r];
+          }
+        } else {                         // partner in another lane of the wave
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int e = 4 * tid + r;
-          const uint64_t w = shfl_xor_u64(v[r], j >> 2);
-          const bool keep_min = ((e & j) == 0) == ((e & k) == 0);
-          v[r] = keep_min ? min(v[r], w) : max(v[r], w);
+          for (int r = 0; r < 4; ++r) {
+            const uint64_t w = shfl_xor_u64(v[r], j >> 2);
+            v[r] = ((w < v[r]) == keep_min) ? w : v[r];
+          }
         }
       } else {                           // partner in this thread
+        // bit k of e: a bit of r for k < 4, of tid above (none for the last merge)
+        const bool up = k == kRankBlock || (tid & (k >> 2)) == 0;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           if (r & j) continue;
-          const int e = 4 * tid + r;
-          const bool up = (e & k) == 0;
+          const bool asc = k < 4 ? (r & k) == 0 : up;
           const uint64_t x = v[r], y = v[r + j];
-          if ((x > y) == up) { v[r] = y; v[r + j] = x; }
+          if ((x > y) == asc) { v[r] = y; v[r + j] = x; }
         }
       }
     }
