@@ -274,6 +274,7 @@ struct SpeciesRec {
   int flags = 0;
   Segment seg[2];   // state buffers (second copy only with sorting)
   int cur = 0;
+  bool pristine = false;   // state is exactly the sampled one (no pre-IC, not stepped)
 };
 
 // A captured step sequence: the host state it was captured from and the host
@@ -285,8 +286,10 @@ struct HostStepState {
   double drift_cells = 0;
   std::vector<double> grid_a;      // per field; NaN = no grid
   std::vector<int> tags;           // per field, two super-step set tags
+  std::vector<char> pristine;      // per species
   bool operator==(const HostStepState& o) const {
     if (step_index != o.step_index || cur != o.cur || sorted_once != o.sorted_once || tags != o.tags ||
+        pristine != o.pristine ||
         std::memcmp(&drift_cells, &o.drift_cells, sizeof(double)) != 0 || grid_a.size() != o.grid_a.size())
       return false;
     for (size_t i = 0; i < grid_a.size(); ++i)
@@ -586,11 +589,27 @@ SortArgs sort_args(fdf_ctx* c, const SpeciesRec& s, double predict_tau, double a
   return a;
 }
 
-int sort_species(fdf_ctx* c, double predict_tau, double a_pred) {
+// resample: a species whose state is still the sampled one moves its ids
+// alone and is sampled again, by id, into the sorted slots (the same values
+// as moving the whole state from the random sampling order, at a fraction of
+// the scattered writes).
+int sort_species(fdf_ctx* c, double predict_tau, double a_pred, bool resample) {
   std::pair<hipEvent_t, hipEvent_t> ev;
   timing_begin(c, FDF_KERNEL_SORT, &ev);
   for (auto& s : c->species) {
-    launch_sort(sort_args(c, s, predict_tau, a_pred), stream_of(c));
+    SortArgs a = sort_args(c, s, predict_tau, a_pred);
+    a.id_only = resample && s.pristine;
+    launch_sort(a, stream_of(c));
+    if (a.id_only) {
+      SampleArgs sa{};
+      sa.seg = s.seg[s.cur ^ 1];
+      sa.fp64 = c->cfg.precision == FDF_PREC_FP64;
+      sa.by_id = 1;
+      sa.seed = s.seed;
+      sa.box = c->cfg.box_mpc;
+      sa.t_nu = t_nu_ev();
+      launch_sample_species(sa, stream_of(c));
+    }
     s.cur ^= 1;
   }
   timing_end(c, FDF_KERNEL_SORT, ev);
@@ -906,6 +925,7 @@ int fdf_init_species(fdf_ctx* c, int32_t field_id, double m, int64_t n, uint64_t
     launch_pre_ic(p, c->stream);
   }
   timing_end(c, FDF_KERNEL_INIT, ev);
+  s.pristine = !(flags & FDF_SPECIES_PRE_IC);
   return launched(c, "species sampling");
 }
 
@@ -1076,7 +1096,7 @@ int enqueue_steps(fdf_ctx* c, int32_t n) {
         const int passes = c->sorted_once ? 1 : 2;
         fused_sort = c->sort_fused && !pa.fp64 && pa.eom == FDF_EOM_SEPARABLE;
         for (int pass = 0; pass < passes - (fused_sort ? 1 : 0) && !rc; ++pass)
-          rc = sort_species(c, tau_pred, a_mid);
+          rc = sort_species(c, tau_pred, a_mid, pass == 0);
         if (rc) return rc;
         c->sorted_once = true;
         c->drift_cells = 0;
@@ -1093,6 +1113,7 @@ int enqueue_steps(fdf_ctx* c, int32_t n) {
     if (fused_sort) {
       rc = sort_push_species(c, tau_pred, a_mid, pa, table);
       if (rc) return rc;
+      for (auto& s : c->species) s.pristine = false;
       continue;
     }
     std::pair<hipEvent_t, hipEvent_t> ev;
@@ -1101,6 +1122,7 @@ int enqueue_steps(fdf_ctx* c, int32_t n) {
     timing_end(c, FDF_KERNEL_PUSH, ev);
     rc = launched(c, "push");
     if (rc) return rc;
+    for (auto& s : c->species) s.pristine = false;
   }
   c->step_index = k0 + n;
   c->stepped = true;
@@ -1128,6 +1150,7 @@ HostStepState host_state(fdf_ctx* c) {
   h.cur = c->species.empty() ? 0 : c->species[0].cur;
   h.sorted_once = c->sorted_once;
   h.drift_cells = c->drift_cells;
+  for (auto& s : c->species) h.pristine.push_back(s.pristine ? 1 : 0);
   for (auto& f : c->fields) {
     h.grid_a.push_back(f.has_grid ? f.grid_a : NAN);
     h.tags.push_back(f.tag[0]);
@@ -1141,6 +1164,7 @@ void apply_state(fdf_ctx* c, const HostStepState& h) {
   for (auto& s : c->species) s.cur = h.cur;
   c->sorted_once = h.sorted_once;
   c->drift_cells = h.drift_cells;
+  for (size_t i = 0; i < c->species.size() && i < h.pristine.size(); ++i) c->species[i].pristine = h.pristine[i];
   for (size_t i = 0; i < c->fields.size() && i < h.grid_a.size(); ++i) {
     c->fields[i].has_grid = !std::isnan(h.grid_a[i]);
     c->fields[i].grid_a = h.grid_a[i];

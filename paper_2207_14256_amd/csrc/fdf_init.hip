@@ -62,7 +62,7 @@ __global__ void k_sample(SampleArgs a) {
   const double T = a.t_nu;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
-    const uint64_t id = (uint64_t)i;
+    const uint64_t id = a.by_id ? (uint64_t)a.seg.id[i] : (uint64_t)i;
     const u64x4 wp = philox4x64(id, 0, 0, 0, a.seed, kStreamPosition);
     uint32_t xu[3];
     for (int d = 0; d < 3; ++d) xu[d] = (uint32_t)(wp.v[d] >> 32);
@@ -82,7 +82,7 @@ __global__ void k_sample(SampleArgs a) {
         a.seg.dqf[d][i] = 0.0f;
       }
     }
-    a.seg.id[i] = (uint32_t)i;
+    if (!a.by_id) a.seg.id[i] = (uint32_t)i;
   }
 }
 

@@ -135,11 +135,13 @@ struct SortArgs {
   uint32_t* rank;          // [n] per sorted element of each 1024-block: rank inside its bucket
   uint32_t* bucket;        // [n] per sorted element: bucket
   uint32_t* src;           // [n] per sorted element: source slot inside the block
+  int32_t id_only;         // move pass: move the ids alone (the caller re-samples the state by id)
 };
 
 struct SampleArgs {
   Segment seg;
   int32_t fp64;
+  int32_t by_id;           // 1: slot i takes the particle seg.id[i] (ids kept); 0: slot i is id i
   uint64_t seed;
   double box;
   double t_nu;             // k_B T [eV]

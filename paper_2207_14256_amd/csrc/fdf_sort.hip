@@ -273,7 +273,9 @@ __global__ void __launch_bounds__(256) k_sort_move(SortArgs a) {
   }
   const Segment& s = a.seg;
   const Segment& d = a.dst;
-  if (a.fp64) {
+  if (a.id_only) {
+    move_array(s.id, d.id, (uint32_t*)lds_raw, i0, cnt, sidx, pos);
+  } else if (a.fp64) {
     double* l = (double*)lds_raw;
     for (int k = 0; k < 3; ++k) {
       move_array(s.xd[k], d.xd[k], l, i0, cnt, sidx, pos);

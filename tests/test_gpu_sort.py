@@ -125,3 +125,18 @@ def test_launch_shape_invariance(prec):
         got = _state_by_id(cfg, dict(sort_every=4, particles_per_thread=ppt, push_waves=waves))
         for i, (a, b) in enumerate(zip(ref, got)):
             assert np.array_equal(a, b), (ppt, waves, i)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_first_sort_of_modified_states(prec):
+    """The job's first sort re-samples untouched species by id; species whose
+    state was changed before it (pre-initial conditions) move their state.
+    Both give the unsorted run's state by id, bit for bit."""
+    print("[gpu-case] first sort, pre-IC species %s" % prec, flush=True)
+    cfg = workloads.small("c2", grid_n=32, n_side=21, n_steps=60, precision=prec,
+                          box_mpc=600.0, z_begin=1e6, z_end=10.0, pre_ic=True)
+    cfg["sort_every"] = 1
+    ref = _state_by_id(cfg, dict(sort_every=0))
+    got = _state_by_id(cfg, dict(sort_every=3))
+    for i, (a, b) in enumerate(zip(ref, got)):
+        assert np.array_equal(a, b), i
