@@ -85,43 +85,23 @@ __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int mask) {
   return ((uint64_t)hi << 32) | lo;
 }
 
-// Rank pass.  A block sorts its 1024 particles by full key (bitonic network:
-// thread t holds sorted positions 4t .. 4t + 3 in registers; partners within
-// a thread swap in registers, partners within a wave meet through lane
-// shuffles, and only the three stages that cross waves go through LDS), cuts
-// the sorted run into segments of equal bucket, and reserves one contiguous
-// range per segment with a single atomicAdd on the bucket count.  For each
-// element of the block's sorted run its source slot, bucket and rank inside
-// the bucket are written at its sorted position.  The fragment a block writes
-// into a bucket is therefore contiguous and ordered by cell.
-__global__ void __launch_bounds__(kRankThreads) k_sort_rank(SortArgs a) {
-  static_assert(kRankBlock == 4 * kRankThreads, "four elements per thread");
-  __shared__ uint64_t kv[kRankBlock];
-  __shared__ uint32_t seg_start[kRankBlock];
-  __shared__ uint32_t seg_base[kRankBlock];
-  __shared__ uint32_t wave_max[kRankThreads / 64];
-  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
-  const int64_t i0 = blk * kRankBlock;
-  const int tid = threadIdx.x;
-  // keys read coalesced (element tid + 256 r), then regrouped through LDS so
-  // that thread t holds elements 4t .. 4t + 3
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int e = tid + kRankThreads * r;
-    const int64_t i = i0 + e;
-    const uint64_t key = i < a.seg.n ? (uint64_t)full_key(a, i) : kNoKey;
-    kv[e] = (key << 10) | (uint64_t)e;
-  }
-  __syncthreads();
-  uint64_t v[4];
-#pragma unroll
-  for (int r = 0; r < 4; ++r) v[r] = kv[4 * tid + r];
-  // Element e = 4 tid + r keeps the smaller of its pair exactly when it is the
-  // lower index of an ascending pair or the upper index of a descending one.
-  // Keys are unique (the slot is in the low bits), so one comparison decides:
-  // take the partner's key when (partner < own) == keep_min.  For partners
-  // 4 or more apart, both bits of e that decide keep_min are bits of tid, so
-  // the direction is one per thread and stage.
+__device__ __forceinline__ uint32_t shfl_xor_word(uint32_t v, int mask) {
+  return (uint32_t)__shfl_xor((int)v, mask, 64);
+}
+__device__ __forceinline__ uint64_t shfl_xor_word(uint64_t v, int mask) { return shfl_xor_u64(v, mask); }
+
+// Bitonic sort of the block's 1024 words, thread t holding sorted positions
+// 4t .. 4t + 3 in registers.  Element e = 4 tid + r keeps the smaller of its
+// pair exactly when it is the lower index of an ascending pair or the upper
+// index of a descending one.  Real words are unique (the slot is in the low
+// bits; equal padding words are interchangeable), so one comparison decides:
+// take the partner's word when (partner < own) == keep_min.  For partners 4
+// or more apart, both bits of e that decide keep_min are bits of tid, so the
+// direction is one per thread and stage.  Partners within a thread swap in
+// registers, partners within a wave meet through lane shuffles, and only the
+// three stages that cross waves go through LDS (lds: kRankBlock words).
+template <typename W>
+__device__ __forceinline__ void bitonic_block(W (&v)[4], W* lds, int tid) {
 #pragma unroll
   for (int k = 2; k <= kRankBlock; k <<= 1) {
 #pragma unroll
@@ -133,17 +113,17 @@ __global__ void __launch_bounds__(kRankThreads) k_sort_rank(SortArgs a) {
         if (j >= 4 * 64) {               // partner in another wave
           __syncthreads();
 #pragma unroll
-          for (int r = 0; r < 4; ++r) kv[4 * tid + r] = v[r];
+          for (int r = 0; r < 4; ++r) lds[4 * tid + r] = v[r];
           __syncthreads();
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const uint64_t w = kv[(4 * tid + r) ^ j];
+            const W w = lds[(4 * tid + r) ^ j];
             v[r] = ((w < v[r]) == keep_min) ? w : v[r];
           }
         } else {                         // partner in another lane of the wave
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const uint64_t w = shfl_xor_u64(v[r], j >> 2);
+            const W w = shfl_xor_word(v[r], j >> 2);
             v[r] = ((w < v[r]) == keep_min) ? w : v[r];
           }
         }
@@ -154,16 +134,90 @@ __global__ void __launch_bounds__(kRankThreads) k_sort_rank(SortArgs a) {
         for (int r = 0; r < 4; ++r) {
           if (r & j) continue;
           const bool asc = k < 4 ? (r & k) == 0 : up;
-          const uint64_t x = v[r], y = v[r + j];
+          const W x = v[r], y = v[r + j];
           if ((x > y) == asc) { v[r] = y; v[r + j] = x; }
         }
       }
     }
   }
+}
+
+// Rank pass.  A block sorts its 1024 particles by (full key, slot) (bitonic,
+// above), cuts the sorted run into segments of equal bucket, and reserves one
+// contiguous range per segment with a single atomicAdd on the bucket count.
+// For each element of the block's sorted run its source slot, bucket and rank
+// inside the bucket are written at its sorted position.  The fragment a block
+// writes into a bucket is therefore contiguous and ordered by cell.
+// When the block's keys span less than 2^22 (spatially compact blocks, the
+// common case once sorted), the network runs on 32-bit words of (key - the
+// block's smallest key, slot), half the work of the 64-bit words.
+__global__ void __launch_bounds__(kRankThreads) k_sort_rank(SortArgs a) {
+  static_assert(kRankBlock == 4 * kRankThreads, "four elements per thread");
+  __shared__ uint64_t kv[kRankBlock];
+  __shared__ uint32_t seg_start[kRankBlock];
+  __shared__ uint32_t seg_base[kRankBlock];
+  __shared__ uint32_t wave_max[kRankThreads / 64];
+  __shared__ uint64_t wave_kmin[kRankThreads / 64], wave_kmax[kRankThreads / 64];
+  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t i0 = blk * kRankBlock;
+  const int cnt = (int)min<int64_t>(kRankBlock, a.seg.n - i0);
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wid = tid >> 6;
+  // keys read coalesced (element tid + 256 r)
+  uint64_t key[4];
+  uint64_t kmin = ~0ull, kmax = 0;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int e = tid + kRankThreads * r;
+    key[r] = e < cnt ? (uint64_t)full_key(a, i0 + e) : kNoKey;
+    if (e < cnt) { kmin = min(kmin, key[r]); kmax = max(kmax, key[r]); }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    kmin = min(kmin, shfl_xor_u64(kmin, off));
+    kmax = max(kmax, shfl_xor_u64(kmax, off));
+  }
+  if (lane == 0) { wave_kmin[wid] = kmin; wave_kmax[wid] = kmax; }
   __syncthreads();
 #pragma unroll
-  for (int r = 0; r < 4; ++r) kv[4 * tid + r] = v[r];
-  __syncthreads();
+  for (int w = 0; w < kRankThreads / 64; ++w) { kmin = min(kmin, wave_kmin[w]); kmax = max(kmax, wave_kmax[w]); }
+  if (kmax - kmin < (1ull << 22)) {      // block-uniform (cnt >= 1, so kmin <= kmax)
+    uint32_t* kw = (uint32_t*)kv;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int e = tid + kRankThreads * r;
+      kw[e] = e < cnt ? ((uint32_t)(key[r] - kmin) << 10) | (uint32_t)e : 0xFFFFFFFFu;
+    }
+    __syncthreads();
+    uint32_t v[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) v[r] = kw[4 * tid + r];
+    bitonic_block(v, kw, tid);
+    __syncthreads();
+    // back to (key, slot) words; the padding sorts to positions >= cnt
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int pos = 4 * tid + r;
+      kv[pos] = pos < cnt ? ((kmin + (v[r] >> 10)) << 10) | (uint64_t)(v[r] & (uint32_t)kIdxMask)
+                          : (kNoKey << 10) | (uint64_t)pos;
+    }
+    __syncthreads();
+  } else {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int e = tid + kRankThreads * r;
+      kv[e] = (key[r] << 10) | (uint64_t)e;
+    }
+    __syncthreads();
+    uint64_t v[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) v[r] = kv[4 * tid + r];
+    bitonic_block(v, kv, tid);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) kv[4 * tid + r] = v[r];
+    __syncthreads();
+  }
   // segment starts: inclusive max-scan of head positions over the sorted run;
   // thread tid owns sorted elements 4 tid .. 4 tid + 3
   const int sh = 10 + 3 * a.fine_bits;   // key bits below the bucket index
@@ -175,7 +229,6 @@ __global__ void __launch_bounds__(kRankThreads) k_sort_rank(SortArgs a) {
     m = head ? (uint32_t)e : m;
     loc[r] = m;
   }
-  const int lane = tid & 63, wid = tid >> 6;
   uint32_t inc = m;
   for (int off = 1; off < 64; off <<= 1) {
     const uint32_t y = (uint32_t)__shfl_up((int)inc, off, 64);
