@@ -134,3 +134,32 @@ def test_truncate_field_is_spectral_restriction():
     coarse = np.fft.irfftn(truncate_field(dk, Gc), s=(Gc, Gc, Gc), axes=(0, 1, 2)) * Gc ** 3
     step = G // Gc
     assert np.allclose(coarse, fine[::step, ::step, ::step], rtol=0, atol=1e-12 * np.abs(fine).max())
+
+
+_CTYPES = {"int32_t": ctypes.c_int32, "int64_t": ctypes.c_int64, "double": ctypes.c_double,
+           "float": ctypes.c_float, "size_t": ctypes.c_size_t}
+
+
+def _header_fields(struct_name):
+    """(name, ctype) of each member of `typedef struct <name> {...}` in the
+    header, in order (comments stripped; `double a, b;` gives two members)."""
+    header = open(os.path.join(ROOT, "include", "fastdf.h")).read()
+    header = re.sub(r"/\*.*?\*/", "", header, flags=re.S)
+    body = re.search(r"typedef struct %s \{(.*?)\} %s;" % (struct_name, struct_name), header, re.S).group(1)
+    fields = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        ctype, names = decl.split(None, 1)
+        for name in names.split(","):
+            fields.append((name.strip(), _CTYPES[ctype]))
+    return fields
+
+
+@pytest.mark.parametrize("struct_name,cls", [("fdf_config", fastdf.Config), ("fdf_info", fastdf.Info),
+                                             ("fdf_tuning", fastdf.Tuning)])
+def test_binding_structs_match_header(struct_name, cls):
+    """The ctypes structures of the binding have the header's members, types
+    and order (a mismatch would shift every later member)."""
+    assert [(n, t) for n, t in cls._fields_] == _header_fields(struct_name)
