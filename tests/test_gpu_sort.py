@@ -140,3 +140,19 @@ def test_first_sort_of_modified_states(prec):
     got = _state_by_id(cfg, dict(sort_every=3))
     for i, (a, b) in enumerate(zip(ref, got)):
         assert np.array_equal(a, b), i
+
+
+@pytest.mark.parametrize("eom", ["exact", "canonical"])
+def test_launch_shape_invariance_other_eoms(eom):
+    """The cap on resident waves and the particles per thread apply to the
+    kernels of the other equations of motion as well; their results by id do
+    not change either."""
+    print("[gpu-case] launch shape invariance eom=%s" % eom, flush=True)
+    cfg = workloads.small("c2", grid_n=16, n_side=15, n_steps=60, precision="fp32",
+                          box_mpc=600.0, z_begin=1e6, z_end=10.0, eom=eom)
+    cfg["sort_every"] = 1
+    ref = _state_by_id(cfg, dict(sort_every=4))
+    for ppt, waves in ((2, 3), (4, 2), (1, 8)):
+        got = _state_by_id(cfg, dict(sort_every=4, particles_per_thread=ppt, push_waves=waves))
+        for i, (a, b) in enumerate(zip(ref, got)):
+            assert np.array_equal(a, b), (eom, ppt, waves, i)
