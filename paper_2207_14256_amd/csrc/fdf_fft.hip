@@ -368,7 +368,7 @@ __global__ void __launch_bounds__(256) k_zpass_c2r(GridBuildArgs a) {
   __syncthreads();
   for (int e = threadIdx.x; e < NL * G; e += NT) {
     const int line = e / G, iz = e % G;
-    const size_t cell = ((size_t)ix * G + iy0 + line) * G + iz;
+    const size_t cell = (size_t)mesh_x(ix, G) + mesh_y(iy0 + line, G) + mesh_z(iz);   // bricked layout
     store_cell<NSLOT, OT, R>(a.out, cell, &stage[e * NSLOT]);
   }
 }

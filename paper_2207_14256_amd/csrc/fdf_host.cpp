@@ -1447,15 +1447,22 @@ int fdf_read_grid(fdf_ctx* c, int32_t field_id, int32_t slot, double* h) {
   const bool f64 = c->cfg.precision == FDF_PREC_FP64;
   int rc = hip_check(c, hipStreamSynchronize(c->stream), "sync");
   if (rc) return rc;
+  // the device mesh is bricked (mesh_x/y/z); the host array is x-major
+  const uint32_t G = (uint32_t)c->cfg.grid_n;
+  std::vector<size_t> where(cells);
+  for (uint32_t ix = 0; ix < G; ++ix)
+    for (uint32_t iy = 0; iy < G; ++iy)
+      for (uint32_t iz = 0; iz < G; ++iz)
+        where[((size_t)ix * G + iy) * G + iz] = (size_t)mesh_x(ix, G) + mesh_y(iy, G) + mesh_z(iz);
   if (f64) {
     std::vector<double> all(cells * ns);
     rc = hip_check(c, hipMemcpy(all.data(), f.grid, all.size() * 8, hipMemcpyDeviceToHost), "read grid");
-    for (size_t i = 0; i < cells && !rc; ++i) h[i] = all[i * ns + s];
+    for (size_t i = 0; i < cells && !rc; ++i) h[i] = all[where[i] * ns + s];
   } else {
     std::vector<uint16_t> all(cells * ns);
     rc = hip_check(c, hipMemcpy(all.data(), f.grid, all.size() * 2, hipMemcpyDeviceToHost), "read grid");
     for (size_t i = 0; i < cells && !rc; ++i) {
-      uint32_t u = (uint32_t)all[i * ns + s] << 16;
+      uint32_t u = (uint32_t)all[where[i] * ns + s] << 16;
       float v;
       std::memcpy(&v, &u, 4);
       h[i] = v;

@@ -8,6 +8,17 @@
 namespace fdf {
 
 // ----------------------------------------------------------------------------
+// Layout of the gradient meshes: 4 x 4 x 4-cell bricks, bricks in x, y, z
+// order and cells inside a brick in x, y, z order, so that the CIC or TSC
+// corners of a particle lie in one or two kilobyte-sized bricks instead of
+// rows a whole x-plane apart.  The index of cell (ix, iy, iz) on a G^3 mesh
+// (G a power of two >= 8) is mesh_x(ix) + mesh_y(iy) + mesh_z(iz).
+// ----------------------------------------------------------------------------
+__host__ __device__ inline uint32_t mesh_x(uint32_t i, uint32_t G) { return (i >> 2) * (G * G * 4u) + (i & 3u) * 16u; }
+__host__ __device__ inline uint32_t mesh_y(uint32_t i, uint32_t G) { return (i >> 2) * (G * 16u) + (i & 3u) * 4u; }
+__host__ __device__ inline uint32_t mesh_z(uint32_t i) { return (i >> 2) * 64u + (i & 3u); }
+
+// ----------------------------------------------------------------------------
 // Grid recipe: which potential-derived quantity each output slot carries.
 // ----------------------------------------------------------------------------
 enum SlotKind : int32_t {

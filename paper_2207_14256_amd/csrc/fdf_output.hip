@@ -126,7 +126,8 @@ __global__ void __launch_bounds__(256) k_force_terms(TermArgs a) {
     for (int c = 0; c < 8; ++c) {
       const int cx = c >> 2, cy = (c >> 1) & 1, cz = c & 1;
       const double w = (cx ? t[0] : 1 - t[0]) * (cy ? t[1] : 1 - t[1]) * (cz ? t[2] : 1 - t[2]);
-      const size_t cell = ((size_t)(cx ? i1[0] : i0[0]) * G + (cy ? i1[1] : i0[1])) * G + (cz ? i1[2] : i0[2]);
+      const size_t cell = (size_t)mesh_x(cx ? i1[0] : i0[0], G) + mesh_y(cy ? i1[1] : i0[1], G) +
+                          mesh_z(cz ? i1[2] : i0[2]);
       for (int d = 0; d < 3; ++d) {
         gpsi[d] += w * term_slot(a, cell, a.slot_gpsi + d);
         gphi[d] += w * term_slot(a, cell, a.slot_gphi + d);

@@ -65,10 +65,13 @@ __device__ __forceinline__ void stencil_u32(const uint32_t* xu, int shift, uint3
       t[d] = (float)(xu[d] & fmask) * finv;
       u[d] = 1.0f - t[d];
     }
+    const I ax[2] = {(I)mesh_x(i0[0], (uint32_t)G), (I)mesh_x(i1[0], (uint32_t)G)};
+    const I ay[2] = {(I)mesh_y(i0[1], (uint32_t)G), (I)mesh_y(i1[1], (uint32_t)G)};
+    const I az[2] = {(I)mesh_z(i0[2]), (I)mesh_z(i1[2])};
 #pragma unroll
     for (int cc = 0; cc < 8; ++cc) {
       const int cx = cc >> 2, cy = (cc >> 1) & 1, cz = cc & 1;
-      cell[cc] = ((I)(cx ? i1[0] : i0[0]) * G + (cy ? i1[1] : i0[1])) * G + (cz ? i1[2] : i0[2]);
+      cell[cc] = ax[cx] + ay[cy] + az[cz];
       w[cc] = ((cx ? t[0] : u[0]) * (cy ? t[1] : u[1])) * (cz ? t[2] : u[2]);
     }
   } else {
@@ -95,7 +98,8 @@ __device__ __forceinline__ void stencil_u32(const uint32_t* xu, int shift, uint3
       for (int b = 0; b < 3; ++b)
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          cell[9 * a + 3 * b + c] = ((I)idx[0][a] * G + idx[1][b]) * G + idx[2][c];
+          cell[9 * a + 3 * b + c] =
+              (I)mesh_x(idx[0][a], (uint32_t)G) + (I)mesh_y(idx[1][b], (uint32_t)G) + (I)mesh_z(idx[2][c]);
           w[9 * a + 3 * b + c] = (wt[0][a] * wt[1][b]) * wt[2][c];
         }
   }
@@ -117,10 +121,13 @@ __device__ __forceinline__ void stencil_f64(const double* x, double ginv, int gm
       i0[d] = ((int)fl) & gm;
       i1[d] = (i0[d] + 1) & gm;
     }
+    const I ax[2] = {(I)mesh_x((uint32_t)i0[0], (uint32_t)G), (I)mesh_x((uint32_t)i1[0], (uint32_t)G)};
+    const I ay[2] = {(I)mesh_y((uint32_t)i0[1], (uint32_t)G), (I)mesh_y((uint32_t)i1[1], (uint32_t)G)};
+    const I az[2] = {(I)mesh_z((uint32_t)i0[2]), (I)mesh_z((uint32_t)i1[2])};
 #pragma unroll
     for (int cc = 0; cc < 8; ++cc) {
       const int cx = cc >> 2, cy = (cc >> 1) & 1, cz = cc & 1;
-      cell[cc] = ((I)(cx ? i1[0] : i0[0]) * G + (cy ? i1[1] : i0[1])) * G + (cz ? i1[2] : i0[2]);
+      cell[cc] = ax[cx] + ay[cy] + az[cz];
       w[cc] = ((cx ? t[0] : 1.0 - t[0]) * (cy ? t[1] : 1.0 - t[1])) * (cz ? t[2] : 1.0 - t[2]);
     }
   } else {
@@ -145,7 +152,8 @@ __device__ __forceinline__ void stencil_f64(const double* x, double ginv, int gm
       for (int b = 0; b < 3; ++b)
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          cell[9 * a + 3 * b + c] = ((I)idx[0][a] * G + idx[1][b]) * G + idx[2][c];
+          cell[9 * a + 3 * b + c] = (I)mesh_x((uint32_t)idx[0][a], (uint32_t)G) +
+                                    (I)mesh_y((uint32_t)idx[1][b], (uint32_t)G) + (I)mesh_z((uint32_t)idx[2][c]);
           w[9 * a + 3 * b + c] = (wt[0][a] * wt[1][b]) * wt[2][c];
         }
   }
