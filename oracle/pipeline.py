@@ -223,3 +223,43 @@ def momentum_spectrum(cfg, species_index, res, mode="cross", a=None, analysis_n=
         halves.append(stats.momentum_divergence(res["x"][s], res["w"][s], res["q"][s], G, L,
                                                 int(s.sum()), mean_eps))
     return stats.binned_power_fourier(halves[0], halves[1], L, cfg["pk_bins"])
+
+
+def total_density_spectrum(cfg, species_indices, results, mode="cross", a=None, analysis_n=0):
+    """Binned P(k) of the total energy-density contrast of several species
+    that share one field (sec. 2.2 eq. empirical_rho, per species, and the
+    spectra of sec. 4).
+
+    Each species s gives its own contrast delta_s of eq. empirical_rho
+    (normalised by its own particle count and mean energy <eps>_s).  The
+    relic species share one temperature (sec. 2), hence one number density,
+    so their mean densities are proportional to <eps>_s(a) and the total is
+        delta = sum_s <eps>_s delta_s / sum_s <eps>_s.
+    Halves are the even and odd ids of every species (mode 'cross'); 'auto'
+    uses all particles.  results[i] is run_particles over all ids of
+    species_indices[i]."""
+    G, L = analysis_n or cfg["grid_n"], cfg["box_mpc"]
+    a = results[0]["sched"]["a"][-1] if a is None else a
+    halves = [np.zeros((G, G, G)), np.zeros((G, G, G))]
+    weights = []
+    for si, res in zip(species_indices, results):
+        m = cfg["species"][si]["m"]
+        mean_eps = background.mean_energy(m, a)
+        eps = stats.energies(res["q"], m, a)
+        n = res["x"].shape[0]
+        ids = np.arange(n)
+        weights.append(mean_eps)
+        if mode == "auto":
+            d = stats.density_contrast(res["x"], res["w"], eps, G, L, n, mean_eps)
+            halves[0] += mean_eps * d
+            continue
+        for par in (0, 1):
+            s = (ids % 2) == par
+            if s.any():
+                halves[par] += mean_eps * stats.density_contrast(
+                    res["x"][s], res["w"][s], eps[s], G, L, int(s.sum()), mean_eps)
+    total = float(np.sum(weights))
+    halves = [h / total for h in halves]
+    if mode == "auto":
+        return stats.binned_power(halves[0], halves[0], L, cfg["pk_bins"]), (halves[0], halves[0])
+    return stats.binned_power(halves[0], halves[1], L, cfg["pk_bins"]), tuple(halves)
