@@ -36,36 +36,54 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
+def mesh_slots(cfg):
+    """(stored slots per cell, slots that carry data): grad psi (3), grad phi
+    (3, when psi != phi) and phi-dot (1, when the potentials depend on time);
+    bfloat16 cells keep 4 or 8 slots, binary64 cells with phi-dot = 0 keep 6."""
+    slip = bool(cfg.get("slip_amp", 0.0))
+    tdep = cfg.get("model") == "radmat"
+    data = 3 + (3 if slip else 0) + (1 if tdep else 0)
+    if not slip:
+        stored = 4
+    elif cfg["precision"] == "fp64" and not tdep:
+        stored = 6
+    else:
+        stored = 8
+    return stored, data
+
+
 def bytes_per_launch(cfg, n_particles, drift):
     """Algorithmic HBM bytes of one push launch: state read + write per
-    particle, plus one read of the gradient mesh (4, 6 or 8 slots per cell).
-    FP32 form: read x, q0, dq (36 B), write x, dq (24 B; 12 B without the
-    drift); FP64 form: read x, q, q0 (72 B), write x, q (48 B; 24 B without
-    the drift)."""
+    particle, plus one read of the slots of the gradient mesh that carry data
+    (the zero phi-dot slot and the pad of a bfloat16 cell are traffic, not
+    algorithm: see mesh_padding_bytes).  FP32 form: read x, q0, dq (36 B),
+    write x, dq (24 B; 12 B without the drift); FP64 form: read x, q, q0
+    (72 B), write x, q (48 B; 24 B without the drift)."""
     G = cfg["grid_n"]
-    if not cfg.get("slip_amp", 0.0):
-        nslot = 4                                  # grad psi, phi-dot
-    elif cfg["precision"] == "fp64" and cfg.get("model") != "radmat":
-        nslot = 6                                  # grad psi, grad phi
-    else:
-        nslot = 8                                  # grad psi, grad phi, phi-dot, pad
+    _, data = mesh_slots(cfg)
     if cfg["precision"] == "fp32":
         per = 36 + (24 if drift else 12)
-        grid = G ** 3 * nslot * 2
+        grid = G ** 3 * data * 2
     else:
         per = 72 + (48 if drift else 24)
-        grid = G ** 3 * nslot * 8
+        grid = G ** 3 * data * 8
     return n_particles * per + grid
+
+
+def mesh_padding_bytes(cfg):
+    """Bytes per launch of mesh slots read but carrying no data."""
+    stored, data = mesh_slots(cfg)
+    return cfg["grid_n"] ** 3 * (stored - data) * (2 if cfg["precision"] == "fp32" else 8)
 
 
 def bytes_per_push_sort(cfg, n_particles):
     """Algorithmic HBM bytes of one push launch that also carries out a
     re-sort (FP32 form): the push's reads (x, q0, dq: 36 B), the id and the
     rank pass outputs (source slot, bucket, rank: 16 B) read, the whole state
-    written in sorted order (40 B), and one read of the mesh."""
+    written in sorted order (40 B), and one read of the mesh's data slots."""
     G = cfg["grid_n"]
-    nslot = 4 if not cfg.get("slip_amp", 0.0) else 8
-    return n_particles * 92 + G ** 3 * nslot * 2
+    _, data = mesh_slots(cfg)
+    return n_particles * 92 + G ** 3 * data * 2
 
 
 def run_leg(cfg, steps, warmup, label, tuning=None):
@@ -81,7 +99,13 @@ def run_leg(cfg, steps, warmup, label, tuning=None):
         ctx.step(cfg["n_steps"])
         for s in species:
             ctx.weights(s, out=wbuf)
-        return ctx.power_spectrum(species, cfg["pk_bins"], "cross")
+        # one total spectrum per field (the species of one field share it);
+        # the first field's is returned
+        groups = {}
+        for s, sp in zip(species, cfg["species"]):
+            groups.setdefault(sp["field"], []).append(s)
+        pks = [ctx.power_spectrum(g, cfg["pk_bins"], "cross") for _, g in sorted(groups.items())]
+        return pks[0]
 
     for i in range(warmup):
         job()
@@ -165,32 +189,74 @@ def _cpu_worker(cfg, queue):
         queue.put({"error": repr(exc)})
 
 
-def cpu_baseline(cfg, n_sample=32768, n_steps=40):
-    """The FP64 oracle (numpy, one thread) on a bounded sample of the same
-    workload: its own field and gradient grids at full mesh size, then
-    n_sample particles pushed through the first n_steps steps."""
+_GRIDS = None
+
+
+def _push_chunk(args):
+    """Oracle push of one chunk of ids (runs in a forked worker that shares
+    the parent's grids)."""
     import numpy as np
-    from oracle import field, particles, pipeline, push
+    from oracle import particles, pipeline, push
+    cfg, ids, n_steps = args
+    sp = cfg["species"][0]
+    sched = pipeline.schedule(cfg)
+    x0 = particles.positions_f64(sp["seed"], ids, cfg["box_mpc"])
+    q0 = particles.momenta_f64(sp["seed"], ids)
+    t0 = time.perf_counter()
+    push.kdk(x0, q0, q0, sp["m"], sched, cfg["box_mpc"], lambda k: _GRIDS, 0, n_steps)
+    return time.perf_counter() - t0, len(ids)
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(cfg, per_core=32768, n_steps=40, max_workers=16):
+    """The FP64 oracle (numpy) on a bounded sample of the same workload, run
+    before the GPU legs: its own field and gradient grids at full mesh size,
+    then per_core particles per core pushed through the first n_steps steps,
+    on one core and on every host core available to the process (at most
+    max_workers, forked workers sharing the grids)."""
+    global _GRIDS
+    import multiprocessing as mp
+    import numpy as np
+    from oracle import field, pipeline
     t0 = time.perf_counter()
     sched = pipeline.schedule(cfg)
     d0 = pipeline.delta0(cfg)
-    grids = field.potential_grids(d0, cfg["box_mpc"], sched["a"][0], pipeline.model_of(cfg))
+    _GRIDS = field.potential_grids(d0, cfg["box_mpc"], sched["a"][0], pipeline.model_of(cfg))
     t_setup = time.perf_counter() - t0
     log("cpu oracle: field + grids %.1f s" % t_setup)
     sp = cfg["species"][0]
     n_all = sp["n_side"] ** 3
-    ids = np.arange(0, n_all, n_all // n_sample)[:n_sample]
-    x0 = particles.positions_f64(sp["seed"], ids, cfg["box_mpc"])
-    q0 = particles.momenta_f64(sp["seed"], ids)
+    cores = max(1, min(max_workers, len(os.sched_getaffinity(0))))
+    stride = max(1, n_all // (per_core * cores))
+    ids = np.arange(0, n_all, stride)[:per_core * cores]
+    chunks = np.array_split(ids, cores)
+    t_one, n_one = _push_chunk((cfg, chunks[0], n_steps))
+    log("cpu oracle: 1 core %.1f s" % t_one)
     t1 = time.perf_counter()
-    push.kdk(x0, q0, q0, sp["m"], sched, cfg["box_mpc"], lambda k: grids, 0, n_steps)
-    t_push = time.perf_counter() - t1
-    rate = n_sample * n_steps / t_push
-    return dict(value=rate, unit="particle-updates/s", cores=1, kind="oracle",
-                sample="FP64 numpy oracle, 1 thread: %d of %d particles pushed through steps 0-%d "
-                       "of the %d-step schedule on the oracle's own %d^3 FP64 grids (%.1f s push; "
-                       "field + grid build %.1f s not in the rate)" % (
-                           n_sample, n_all, n_steps - 1, cfg["n_steps"], cfg["grid_n"], t_push, t_setup))
+    with mp.get_context("fork").Pool(cores) as pool:
+        parts = pool.map(_push_chunk, [(cfg, c, n_steps) for c in chunks])
+    t_all = time.perf_counter() - t1
+    log("cpu oracle: %d cores %.1f s" % (cores, t_all))
+    _GRIDS = None
+    n_done = sum(n for _, n in parts)
+    return dict(value=n_done * n_steps / t_all, unit="particle-updates/s", cores=cores, kind="oracle",
+                value_1core=n_one * n_steps / t_one, nproc=os.cpu_count(), cpu_model=_cpu_model(),
+                sample="FP64 numpy oracle: %d of %d particles (every %d-th id) pushed through steps "
+                       "0-%d of the %d-step schedule on the oracle's own %d^3 FP64 grids, split over "
+                       "%d forked worker processes (%.1f s wall; the 1-core rate from one worker's "
+                       "share alone, %.1f s); field + grid build %.1f s not in the rates; run before "
+                       "the GPU legs" % (
+                           n_done, n_all, stride, n_steps - 1, cfg["n_steps"], cfg["grid_n"], cores,
+                           t_all, t_one, t_setup))
 
 
 def main():
@@ -214,13 +280,19 @@ def main():
 
     from paper_2207_14256_amd import workloads
     cfg = workloads.preset(args.workload)
-    # the oracle (CPU only, numpy) runs in a spawned process while the GPU legs run
-    cpu_proc = cpu_queue = None
+    # the oracle (CPU only, numpy) runs first, in a spawned process that never
+    # touches the GPU (so it may fork its workers), with the host to itself
+    cpu = None
     if not args.no_cpu_baseline:
         mpc = mp.get_context("spawn")
         cpu_queue = mpc.Queue()
-        cpu_proc = mpc.Process(target=_cpu_worker, args=(cfg, cpu_queue), daemon=True)
+        cpu_proc = mpc.Process(target=_cpu_worker, args=(cfg, cpu_queue), daemon=False)
         cpu_proc.start()
+        while cpu_proc.is_alive() and cpu_queue.empty():
+            time.sleep(2)
+        cpu = cpu_queue.get(timeout=120)
+        cpu_proc.join(timeout=120)
+        log("cpu oracle: %s" % {k: v for k, v in cpu.items() if k != "sample"})
 
     import numpy as np
     import torch
@@ -265,14 +337,6 @@ def main():
         log("fp64 leg: %.3e updates/s, P(k) fp32/fp64 max rel diff %.2e" % (
             leg["updates_per_s"], rel.max()))
 
-    cpu = None
-    if cpu_proc is not None:
-        log("waiting for the cpu oracle sample")
-        while cpu_proc.is_alive() and cpu_queue.empty():
-            time.sleep(5)
-            log("cpu oracle still running")
-        cpu = cpu_queue.get(timeout=60)
-        cpu_proc.join(timeout=60)
     traffic = traffic_from_profile(args.workload, main_leg["dominant"])
     out = {
         "metric": METRIC,
@@ -310,6 +374,7 @@ def main():
             "kernel": main_leg["dominant"],
             "avg_launch_ms": main_leg["avg_launch_ms"],
             "algorithmic_bytes_per_launch": main_leg["kernels"][main_leg["dominant"]]["bytes_per_launch"],
+            "mesh_padding_bytes_per_launch": mesh_padding_bytes(cfg),
         },
         "hbm_gbs": main_leg["achieved_gbs"],
         "kernels": {name: {k: v for k, v in rec.items() if k not in ("ms", "bytes")}

@@ -261,9 +261,13 @@ int fdf_weights(struct fdf_ctx* ctx, int32_t species_id, double* d_w);
 
 /* Energy-density contrast of eq. empirical_rho (CIC deposit of w eps with the
  * normalisation G^3 / (N <eps>)), forward FFT and log-binned spectrum over
- * [2 pi/L, pi G/L) (sec. 4).  Species are combined with weights proportional
- * to their mean energy <eps>(a).  Host outputs of n_bins doubles: mean |k|
- * [1/Mpc], P(k) [Mpc^3] (NaN for an empty bin) and the number of modes. */
+ * [2 pi/L, pi G/L) (sec. 4).  Several species give their total contrast: the
+ * relic species share one temperature (sec. 2) and so one number density, and
+ * each species' contrast (normalised by its own count and <eps>) enters with
+ * the weight <eps>_s(a) / sum_s <eps>_s.  The species must share one field and
+ * appear once each (FDF_ERR_ARG otherwise).  Host outputs of n_bins doubles:
+ * mean |k| [1/Mpc], P(k) [Mpc^3] (NaN for an empty bin) and the number of
+ * modes. */
 int fdf_density_power_spectrum(struct fdf_ctx* ctx, const int32_t* species, int32_t n_species,
                                int32_t n_bins, int32_t mode,
                                double* h_k, double* h_p, double* h_nmodes);

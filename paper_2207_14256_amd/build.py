@@ -14,7 +14,6 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfastdf.so")
-PROBE = os.path.join(HERE, "probe_stream")   # streaming-ceiling measurement, not part of the library
 SOURCES = ["fdf_host.cpp", "fdf_init.hip", "fdf_fft.hip", "fdf_push.hip", "fdf_output.hip",
            "fdf_sort.hip", "fdf_push_eom.hip"]
 ARCH = os.environ.get("FDF_OFFLOAD_ARCH", "gfx950")
@@ -51,10 +50,6 @@ def build(verbose=False):
     if res.returncode != 0:
         raise RuntimeError("link failed:\n%s" % res.stderr)
     os.replace(tmp, LIB)
-    cmd = [HIPCC] + FLAGS + [os.path.join(CSRC, "probe_stream.hip"), "-o", PROBE]
-    res = subprocess.run(cmd, capture_output=True, text=True)
-    if res.returncode != 0:
-        raise RuntimeError("hipcc failed for probe_stream.hip:\n%s" % res.stderr)
     return LIB
 
 

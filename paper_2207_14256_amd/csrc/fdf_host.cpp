@@ -144,7 +144,7 @@ int ilog2(int v) { int r = 0; while ((1 << r) < v) ++r; return r; }
 
 // ----------------------------------------------------------------- layout --
 struct Layout {
-  size_t twiddle_d, twiddle_f, seg, bins, scratch, dens, fields, parts, sort_count, sort_scan, sort_rank,
+  size_t twiddle_d, twiddle_f, seg, bins, dep, scratch, dens, fields, parts, sort_count, sort_scan, sort_rank,
       sort_bucket, sort_src, total;
   int64_t sort_keys_max;
   int grid_sets;
@@ -214,6 +214,7 @@ Layout plan(const fdf_config& c) {
   L.twiddle_f = off; off += align_up(2 * G * 8);
   L.seg = off; off += 2 * align_up((size_t)c.max_species * sizeof(Segment));
   L.bins = off; off += align_up(3 * kMaxBins * sizeof(double));
+  L.dep = off; off += kAlign;   // the fixed-point deposit's largest |value|
   L.scratch = off; off += L.scratch_bytes;
   L.dens = off; off += L.dens_bytes;
   L.grid_sets = (c.potential_model == FDF_MODEL_RADMAT && c.superstep_tol > 0) ? 2 : 1;
@@ -500,6 +501,7 @@ GridBuildArgs grid_recipe(fdf_ctx* c, const FieldRec& f, double a, bool pre_ic_g
 
 int build_grid(fdf_ctx* c, int field, double a, int buf = 0) {
   FieldRec& f = c->fields[field];
+  c->have_density = false;   // the FFT scratch holds the FP32 form's density copy
   GridBuildArgs g = grid_recipe(c, f, a, false);
   if (buf == 1) g.out = f.grid2;
   std::pair<hipEvent_t, hipEvent_t> ev;
@@ -667,6 +669,15 @@ OutputArgs output_args(fdf_ctx* c, const SpeciesRec& s) {
   o.a = c->a[c->step_index];
   o.m = s.m;
   return o;
+}
+
+// Byte offset in the FFT scratch of the FP32 form's binary32 density halves:
+// behind the four transform planes of the largest mesh (two halves and the
+// momentum spectrum's two accumulators), 8 G^3 bytes, inside the scratch's
+// 28 G^3 bytes.
+size_t density_copy_offset(const fdf_ctx* c) {
+  const size_t G = (size_t)c->cfg.grid_n;
+  return 4 * (G * G * (G / 2)) * 8;
 }
 
 // First complex entry of the n-point table in the twiddle regions.
@@ -911,6 +922,7 @@ int fdf_init_species(fdf_ctx* c, int32_t field_id, double m, int64_t n, uint64_t
   timing_begin(c, FDF_KERNEL_INIT, &ev);
   launch_sample_species(sa, c->stream);
   if (flags & FDF_SPECIES_PRE_IC) {
+    c->have_density = false;
     GridBuildArgs g = grid_recipe(c, c->fields[field_id], c->a[0], true);
     launch_build_grids(g, c->stream);
     PreIcArgs p{};
@@ -1298,19 +1310,33 @@ static int power_spectrum(fdf_ctx* c, const int32_t* sp, int32_t ns, int32_t nbi
   if (!needs_ws(c)) return fail(c, FDF_ERR_WORKSPACE, "no workspace attached");
   if (nbins < 1 || nbins > kMaxBins) return fail(c, FDF_ERR_ARG, "n_bins must be in [1, 256]");
   if (mode != FDF_PK_CROSS && mode != FDF_PK_AUTO) return fail(c, FDF_ERR_ARG, "unknown mode");
-  for (int i = 0; i < ns; ++i)
+  for (int i = 0; i < ns; ++i) {
     if (sp[i] < 0 || sp[i] >= (int)c->species.size()) return fail(c, FDF_ERR_ARG, "bad species id");
+    // a total contrast only means something for species that see one field
+    if (c->species[sp[i]].field != c->species[sp[0]].field)
+      return fail(c, FDF_ERR_ARG, "the species of one spectrum must share a field");
+    for (int j = 0; j < i; ++j)
+      if (sp[j] == sp[i]) return fail(c, FDF_ERR_ARG, "a species is listed twice");
+  }
   const int Gm = c->cfg.grid_n;
   if (analysis_n != 0 && (!is_pow2(analysis_n) || analysis_n < 8 || analysis_n > Gm))
     return fail(c, FDF_ERR_ARG, "analysis_n must be 0 or a power of two in [8, grid_n]");
   const int G = analysis_n ? analysis_n : Gm;
   const bool f64 = c->cfg.precision == FDF_PREC_FP64;
-  const size_t rb = f64 ? 8 : 4, cells = (size_t)G * G * G;
+  const size_t cells = (size_t)G * G * G;
   const double a = c->a[c->step_index];
   double esum = 0;
   std::vector<double> emean(ns);
   for (int i = 0; i < ns; ++i) { emean[i] = mean_energy(c->species[sp[i]].m, a); esum += emean[i]; }
   char* dens = c->ws + c->lay.dens;
+  // FP32 form: fixed-point halves in dens (int64 per cell), converted to
+  // binary32 meshes behind the transform's planes in the FFT scratch
+  uint32_t* max_bits = (uint32_t*)(c->ws + c->lay.dep);
+  float* real32 = (float*)(c->ws + c->lay.scratch + density_copy_offset(c));
+  int64_t n_all = 0;
+  for (int i = 0; i < ns; ++i) n_all += c->species[sp[i]].n;
+  int fixed_bits = 62;
+  while (fixed_bits > 20 && ((int64_t)1 << (62 - fixed_bits)) < n_all) --fixed_bits;
   std::pair<hipEvent_t, hipEvent_t> ev;
   timing_begin(c, FDF_KERNEL_OUTPUT, &ev);
   double* bins = (double*)(c->ws + c->lay.bins);
@@ -1321,8 +1347,8 @@ static int power_spectrum(fdf_ctx* c, const int32_t* sp, int32_t ns, int32_t nbi
   pk.nbins = nbins;
   pk.auto_mode = mode == FDF_PK_AUTO;
   pk.volume = c->cfg.box_mpc * c->cfg.box_mpc * c->cfg.box_mpc;
-  pk.grid_a = dens;
-  pk.grid_b = dens + cells * rb;
+  pk.grid_a = f64 ? (void*)dens : (void*)real32;
+  pk.grid_b = f64 ? (void*)(dens + cells * 8) : (void*)(real32 + cells);
   pk.scratch = c->ws + c->lay.scratch;
   pk.twiddle = c->ws + (f64 ? c->lay.twiddle_d + twiddle_entry(Gm, G) * 16
                             : c->lay.twiddle_f + twiddle_entry(Gm, G) * 8);
@@ -1330,7 +1356,9 @@ static int power_spectrum(fdf_ctx* c, const int32_t* sp, int32_t ns, int32_t nbi
   pk.kf = 2.0 * kPi / c->cfg.box_mpc;
   pk.deriv_axis = -1;
   for (int axis = momentum ? 0 : -1; axis < (momentum ? 3 : 0); ++axis) {
-    launch_fill_zero(dens, align_up(2 * cells * rb), c->stream);
+    launch_fill_zero(dens, align_up(2 * cells * 8), c->stream);
+    if (!f64) launch_fill_zero(max_bits, kAlign, c->stream);
+    for (int pass = f64 ? 1 : 0; pass < 2; ++pass)
     for (int i = 0; i < ns; ++i) {
       const SpeciesRec& s = c->species[sp[i]];
       OutputArgs o = output_args(c, s);
@@ -1345,9 +1373,24 @@ static int power_spectrum(fdf_ctx* c, const int32_t* sp, int32_t ns, int32_t nbi
       }
       o.G = G;
       o.dens[0] = dens;
-      o.dens[1] = dens + cells * rb;
+      o.dens[1] = dens + cells * 8;
       o.quantity = axis;
-      launch_deposit(o, c->stream);
+      o.max_bits = max_bits;
+      o.fixed_bits = fixed_bits;
+      if (pass == 0) launch_deposit_max(o, c->stream);
+      else launch_deposit(o, c->stream);
+    }
+    if (!f64) {
+      FixedToRealArgs fr{};
+      fr.src[0] = (const long long*)dens;
+      fr.src[1] = (const long long*)(dens + cells * 8);
+      fr.dst[0] = real32;
+      fr.dst[1] = real32 + cells;
+      fr.n_half = cells;
+      fr.n = (mode == FDF_PK_AUTO ? 1 : 2) * cells;
+      fr.max_bits = max_bits;
+      fr.fixed_bits = fixed_bits;
+      launch_fixed_to_real(fr, c->stream);
     }
     pk.deriv_axis = axis;
     pk.accum_first = axis == 0;
@@ -1502,8 +1545,8 @@ int fdf_read_density(fdf_ctx* c, int32_t half, double* h) {
   if (half < 0 || half > 1) return fail(c, FDF_ERR_ARG, "half must be 0 or 1");
   const size_t cells = (size_t)c->cfg.grid_n * c->cfg.grid_n * c->cfg.grid_n;
   const bool f64 = c->cfg.precision == FDF_PREC_FP64;
-  const size_t rb = f64 ? 8 : 4;
-  char* src = c->ws + c->lay.dens + half * cells * rb;
+  const char* src = f64 ? c->ws + c->lay.dens + half * cells * 8
+                        : c->ws + c->lay.scratch + density_copy_offset(c) + half * cells * 4;
   int rc = hip_check(c, hipStreamSynchronize(c->stream), "sync");
   if (rc) return rc;
   if (f64) return hip_check(c, hipMemcpy(h, src, cells * 8, hipMemcpyDeviceToHost), "read density");

@@ -187,7 +187,18 @@ struct OutputArgs {
   int32_t auto_mode;
   int32_t quantity;        // -1: deposit w eps (energy density); 0-2: w q_axis (momentum density)
   double* w_out;           // weights by id (may be null)
-  void* dens[2];           // real [G^3] per half (f32 or f64)
+  void* dens[2];           // per half, [G^3]: f64 (FP64 form) or int64 fixed point (FP32 form)
+  uint32_t* max_bits;      // FP32 form: binary32 bits of the largest |deposited value|
+  int32_t fixed_bits;      // FP32 form: the quantum is 2^(e - fixed_bits), max |value| < 2^e
+};
+
+// Fixed-point deposit halves -> binary32 meshes (n cells in all, n_half per half).
+struct FixedToRealArgs {
+  const long long* src[2];
+  float* dst[2];
+  size_t n, n_half;
+  const uint32_t* max_bits;
+  int32_t fixed_bits;
 };
 
 // Acceleration terms of eq. releq (Fig. 2 diagnostic): sums over particles of
@@ -214,6 +225,8 @@ void launch_push(const PushArgs& a, hipStream_t s);
 void launch_push_eom(const PushArgs& a, hipStream_t s);
 void launch_weights(const OutputArgs& a, hipStream_t s);
 void launch_deposit(const OutputArgs& a, hipStream_t s);
+void launch_deposit_max(const OutputArgs& a, hipStream_t s);   // FP32 form, before launch_deposit
+void launch_fixed_to_real(const FixedToRealArgs& a, hipStream_t s);
 void launch_power_spectrum(const PkArgs& a, hipStream_t s);
 void launch_bin_accumulated(const PkArgs& a, hipStream_t s);
 void launch_fill_zero(void* ptr, size_t bytes, hipStream_t s);

@@ -54,38 +54,105 @@ __global__ void k_weights(OutputArgs a) {
   }
 }
 
-// CIC deposit of w eps (energy density) or w q_axis = w eps v_axis (momentum
-// density) times the per-half normalisation G^3 / (N_half <eps>).
-template <typename DR>
-__global__ void k_deposit(OutputArgs a) {
+// Value deposited by particle i: w eps (energy density) or w q_axis = w eps
+// v_axis (momentum density), times the per-half normalisation
+// G^3 / (N_half <eps>); *half receives the half (even / odd id).
+__device__ __forceinline__ double deposit_value(const OutputArgs& a, int64_t i, int* half) {
+  const uint32_t id = a.seg.id[i];
+  double q[3], p[3];
+  momenta(a, i, id, q, p);
+  const double w = deltaf_weight(q, p, a.t_nu);
+  const double eps = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + (a.m * a.a) * (a.m * a.a));
+  *half = a.auto_mode ? 0 : (int)(id & 1u);
+  return (a.quantity < 0 ? w * eps : w * q[a.quantity]) * a.norm[*half];
+}
+
+// CIC cell and weights of particle i on the G^3 deposit mesh (vertex-centred
+// mesh points, periodic), x-major cell index.
+__device__ __forceinline__ void deposit_cic(const OutputArgs& a, int64_t i, size_t* cell, double* wc) {
   const int G = a.G;
   const double ginv = (double)G / a.box;
+  int i0[3], i1[3];
+  double t[3];
+  for (int d = 0; d < 3; ++d) {
+    const double x = a.fp64 ? a.seg.xd[d][i] : (double)a.seg.xu[d][i] * (a.box * 0x1p-32);
+    const double u = x * ginv;
+    const double fl = floor(u);
+    t[d] = u - fl;
+    i0[d] = ((int)fl) & (G - 1);
+    i1[d] = (i0[d] + 1) & (G - 1);
+  }
+  for (int c = 0; c < 8; ++c) {
+    const int cx = c >> 2, cy = (c >> 1) & 1, cz = c & 1;
+    wc[c] = (cx ? t[0] : 1 - t[0]) * (cy ? t[1] : 1 - t[1]) * (cz ? t[2] : 1 - t[2]);
+    cell[c] = ((size_t)(cx ? i1[0] : i0[0]) * G + (cy ? i1[1] : i0[1])) * G + (cz ? i1[2] : i0[2]);
+  }
+}
+
+// Binary64 deposit (FP64 form): hardware float64 atomics into the halves.
+__global__ void k_deposit_f64(OutputArgs a) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < a.seg.n;
        i += (int64_t)gridDim.x * blockDim.x) {
-    const uint32_t id = a.seg.id[i];
-    double q[3], p[3];
-    momenta(a, i, id, q, p);
-    const double w = deltaf_weight(q, p, a.t_nu);
-    const double eps = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + (a.m * a.a) * (a.m * a.a));
-    const int half = a.auto_mode ? 0 : (int)(id & 1u);
-    const double val = (a.quantity < 0 ? w * eps : w * q[a.quantity]) * a.norm[half];
-    int i0[3], i1[3];
-    double t[3];
-    for (int d = 0; d < 3; ++d) {
-      const double x = a.fp64 ? a.seg.xd[d][i] : (double)a.seg.xu[d][i] * (a.box * 0x1p-32);
-      const double u = x * ginv;
-      const double fl = floor(u);
-      t[d] = u - fl;
-      i0[d] = ((int)fl) & (G - 1);
-      i1[d] = (i0[d] + 1) & (G - 1);
-    }
-    DR* dst = (DR*)a.dens[half];
+    int half;
+    const double val = deposit_value(a, i, &half);
+    size_t cell[8];
+    double wc[8];
+    deposit_cic(a, i, cell, wc);
+    double* dst = (double*)a.dens[half];
+    for (int c = 0; c < 8; ++c) unsafeAtomicAdd(&dst[cell[c]], wc[c] * val);
+  }
+}
+
+// Fixed-point deposit (FP32 form).  Every contribution wc * val is rounded
+// to an integer multiple of a quantum Q = 2^(e - bits), where 2^e bounds the
+// largest |val| of the spectrum's particles and bits leaves headroom for the
+// sum over all of them in 63 bits; the integers are summed with 64-bit
+// atomics, so the result does not depend on the order of the additions (bit
+// for bit the same from run to run, whatever the launch shape or particle
+// order).  Pass 1 finds the largest |val| (as binary32 bits, an order-free
+// integer maximum); pass 2 deposits; pass 3 converts to binary32.
+__device__ __forceinline__ double fixed_inv_quantum(uint32_t max_bits, int bits) {
+  int e;
+  frexpf(__uint_as_float(max_bits), &e);   // max |val| < 2^e (e = 0 when there is none)
+  return ldexp(1.0, bits - e);
+}
+
+__global__ void __launch_bounds__(256) k_deposit_max(OutputArgs a) {
+  float m = 0.0f;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < a.seg.n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    int half;
+    const double v = fabs(deposit_value(a, i, &half));
+    m = fmaxf(m, __double2float_ru(v));
+  }
+  for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+  if ((threadIdx.x & 63) == 0 && m > 0.0f) atomicMax(a.max_bits, __float_as_uint(m));
+}
+
+__global__ void k_deposit_fixed(OutputArgs a) {
+  const double inv_q = fixed_inv_quantum(*a.max_bits, a.fixed_bits);
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < a.seg.n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    int half;
+    const double val = deposit_value(a, i, &half) * inv_q;
+    size_t cell[8];
+    double wc[8];
+    deposit_cic(a, i, cell, wc);
+    unsigned long long* dst = (unsigned long long*)a.dens[half];
     for (int c = 0; c < 8; ++c) {
-      const int cx = c >> 2, cy = (c >> 1) & 1, cz = c & 1;
-      const double wc = (cx ? t[0] : 1 - t[0]) * (cy ? t[1] : 1 - t[1]) * (cz ? t[2] : 1 - t[2]);
-      const size_t cell = ((size_t)(cx ? i1[0] : i0[0]) * G + (cy ? i1[1] : i0[1])) * G + (cz ? i1[2] : i0[2]);
-      atomicAdd(&dst[cell], (DR)(wc * val));
+      const long long v = __double2ll_rn(wc[c] * val);
+      if (v) atomicAdd(&dst[cell[c]], (unsigned long long)v);
     }
+  }
+}
+
+__global__ void k_fixed_to_real(FixedToRealArgs a) {
+  const double q = 1.0 / fixed_inv_quantum(*a.max_bits, a.fixed_bits);
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < a.n;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const int h = i >= a.n_half;
+    const size_t j = i - (h ? a.n_half : 0);
+    a.dst[h][j] = (float)((double)a.src[h][j] * q);
   }
 }
 
@@ -176,8 +243,16 @@ void launch_force_terms(const TermArgs& a, hipStream_t s) {
 }
 
 void launch_deposit(const OutputArgs& a, hipStream_t s) {
-  if (a.fp64) hipLaunchKernelGGL(k_deposit<double>, dim3(grid_for((size_t)a.seg.n, 256)), dim3(256), 0, s, a);
-  else hipLaunchKernelGGL(k_deposit<float>, dim3(grid_for((size_t)a.seg.n, 256)), dim3(256), 0, s, a);
+  if (a.fp64) hipLaunchKernelGGL(k_deposit_f64, dim3(grid_for((size_t)a.seg.n, 256)), dim3(256), 0, s, a);
+  else hipLaunchKernelGGL(k_deposit_fixed, dim3(grid_for((size_t)a.seg.n, 256)), dim3(256), 0, s, a);
+}
+
+void launch_deposit_max(const OutputArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_deposit_max, dim3(std::min(grid_for((size_t)a.seg.n, 256), 8192)), dim3(256), 0, s, a);
+}
+
+void launch_fixed_to_real(const FixedToRealArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_fixed_to_real, dim3(grid_for(a.n, 256)), dim3(256), 0, s, a);
 }
 
 // Zero a 16-byte aligned buffer whose size is a multiple of 16 with a plain

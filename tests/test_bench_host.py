@@ -12,18 +12,25 @@ N3 = 512 ** 3
 
 
 def test_push_bytes_c3():
-    cfg = workloads.preset("c3")            # FP32, slip: 8 bf16 slots per cell
-    assert bench.bytes_per_launch(cfg, N3, True) == N3 * (36 + 24) + N3 * 8 * 2
-    assert bench.bytes_per_launch(cfg, N3, False) == N3 * (36 + 12) + N3 * 8 * 2
-    assert bench.bytes_per_push_sort(cfg, N3) == N3 * 92 + N3 * 8 * 2
+    # FP32, psi != phi, phi-dot = 0: 8 bf16 slots stored, 6 carry data
+    cfg = workloads.preset("c3")
+    assert bench.mesh_slots(cfg) == (8, 6)
+    assert bench.bytes_per_launch(cfg, N3, True) == N3 * (36 + 24) + N3 * 6 * 2
+    assert bench.bytes_per_launch(cfg, N3, False) == N3 * (36 + 12) + N3 * 6 * 2
+    assert bench.bytes_per_push_sort(cfg, N3) == N3 * 92 + N3 * 6 * 2
+    assert bench.mesh_padding_bytes(cfg) == N3 * 2 * 2
 
 
-def test_push_bytes_fp64_and_no_slip():
+def test_push_bytes_fp64_no_slip_and_time_dependent():
     cfg = workloads.preset("c3", precision="fp64")   # phi-dot = 0 with slip: 6 binary64 slots
+    assert bench.mesh_slots(cfg) == (6, 6)
     assert bench.bytes_per_launch(cfg, N3, True) == N3 * (72 + 48) + N3 * 6 * 8
-    cfg = workloads.preset("c3", slip_amp=0.0)       # psi = phi: 4 bf16 slots
-    assert bench.bytes_per_launch(cfg, N3, True) == N3 * 60 + N3 * 4 * 2
-    assert bench.bytes_per_push_sort(cfg, N3) == N3 * 92 + N3 * 4 * 2
+    cfg = workloads.preset("c3", slip_amp=0.0)       # psi = phi: 4 bf16 slots, 3 with data
+    assert bench.mesh_slots(cfg) == (4, 3)
+    assert bench.bytes_per_launch(cfg, N3, True) == N3 * 60 + N3 * 3 * 2
+    assert bench.bytes_per_push_sort(cfg, N3) == N3 * 92 + N3 * 3 * 2
+    cfg = workloads.preset("c3", model="radmat")     # phi-dot carries data: 7 of 8
+    assert bench.mesh_slots(cfg) == (8, 7)
 
 
 def test_refuses_several_gpus():

@@ -1,0 +1,90 @@
+"""Per-result error statement of the precision form against the FP64 oracle
+at a size the oracle integrates in full: the c3 physics (m = 0.1 eV, L = 1 Gpc,
+psi != phi, 1000 steps z = 1e9 -> 0) with 64^3 particles on a 64^3 mesh.
+
+The oracle's spectra and sampled final states are stored in
+tests/golden/c3_reduced_oracle.json, written by make_c3_reduced.py beside it
+from the oracle alone.  Compared here, bin by bin: the energy-density
+spectrum of the FP32 form (fixed-point x, q = q0 + dq, bfloat16 mesh, with
+re-sorts) and of the FP64 form; positions, |q| and weights on the sampled ids.
+
+Set FDF_REPORT_DIR to write the statement as JSON."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_2207_14256_amd import fastdf, workloads
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "c3_reduced_oracle.json")
+
+# Bounds: about 3x the recorded error statement of the FP32 form
+FP32_BOUNDS = dict(pk_cross_rel_max=3e-3, pk_auto_rel_max=3e-3, pos_rms_cells=2e-3,
+                   pos_max_cells=1e-2, q_rel_rms=1e-3, q_rel_max=1e-2, w_abs_rms_over_max_w=3e-4)
+
+
+def _golden():
+    rec = json.load(open(GOLDEN))
+    arr = lambda v: np.array([np.nan if e is None else e for e in v], dtype=np.float64)   # noqa: E731
+    for mode in ("cross", "auto"):
+        rec[mode] = {k: arr(v) for k, v in rec[mode].items()}
+    n = len(rec["sample_ids"])
+    rec["x"] = arr(rec["x"]).reshape(n, 3)
+    rec["q"] = arr(rec["q"]).reshape(n, 3)
+    rec["w"] = arr(rec["w"])
+    return rec
+
+
+def _cfg(prec, rec):
+    cfg = workloads.small("c3", grid_n=rec["grid_n"], n_side=rec["n_side"], n_steps=rec["n_steps"],
+                          precision=prec)
+    cfg["pk_bins"] = rec["pk_bins"]
+    return cfg
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_reduced_c3_error_statement(prec):
+    print("[gpu-case] reduced c3 error statement %s" % prec, flush=True)
+    rec = _golden()
+    cfg = _cfg(prec, rec)
+    ctx, fields, species = fastdf.setup_workload(cfg)
+    ctx.step(cfg["n_steps"])
+    x, q = ctx.read_state(species[0])
+    w = ctx.weights(species[0]).cpu().numpy()
+    spectra = {mode: ctx.power_spectrum(species, cfg["pk_bins"], mode) for mode in ("cross", "auto")}
+    ctx.close()
+    ids = np.array(rec["sample_ids"])
+    L, G = cfg["box_mpc"], cfg["grid_n"]
+    dx = ((x[ids] - rec["x"] + L / 2) % L - L / 2) * (G / L)
+    pos = np.sqrt(np.sum(dx ** 2, axis=1))
+    qn = np.linalg.norm(rec["q"], axis=1)
+    qrel = np.abs(np.linalg.norm(q[ids], axis=1) - qn) / qn
+    es = dict(workload=rec["workload"], precision=prec, n_sample=int(len(ids)),
+              pos_rms_cells=float(np.sqrt(np.mean(pos ** 2))), pos_max_cells=float(pos.max()),
+              q_rel_rms=float(np.sqrt(np.mean(qrel ** 2))), q_rel_max=float(qrel.max()),
+              w_abs_rms_over_max_w=float(np.sqrt(np.mean((w[ids] - rec["w"]) ** 2)) / np.abs(rec["w"]).max()))
+    for mode, (k, p, nm) in spectra.items():
+        ref = rec[mode]
+        assert np.array_equal(nm, ref["nmodes"])
+        ok = ref["nmodes"] > 0
+        assert np.allclose(k[ok], ref["k"][ok], rtol=1e-12)
+        rel = np.abs(p[ok] / ref["p"][ok] - 1.0)
+        es["pk_%s_rel_max" % mode] = float(rel.max())
+        es["pk_%s_rel_rms" % mode] = float(np.sqrt(np.mean(rel ** 2)))
+        es["pk_%s_rel_per_bin" % mode] = [float(v) for v in rel]
+        es["pk_%s_bins" % mode] = int(ok.sum())
+    d = os.environ.get("FDF_REPORT_DIR")
+    if d:
+        os.makedirs(d, exist_ok=True)
+        with open(os.path.join(d, "error_statement_c3_reduced_%s.json" % prec), "w") as f:
+            json.dump(es, f, indent=1)
+    print("[gpu-report] %s" % json.dumps({k: v for k, v in es.items() if "per_bin" not in k}), flush=True)
+    if prec == "fp64":
+        assert es["pos_max_cells"] < 1e-8 and es["q_rel_max"] < 1e-9
+        assert es["pk_cross_rel_max"] < 1e-6 and es["pk_auto_rel_max"] < 1e-6
+    else:
+        for key, bound in FP32_BOUNDS.items():
+            assert es[key] < bound, (key, es[key], bound)
