@@ -21,9 +21,12 @@ pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "c3_reduced_oracle.json")
 
-# Bounds: about 3x the recorded error statement of the FP32 form
-FP32_BOUNDS = dict(pk_cross_rel_max=3e-3, pk_auto_rel_max=3e-3, pos_rms_cells=2e-3,
-                   pos_max_cells=1e-2, q_rel_rms=1e-3, q_rel_max=1e-2, w_abs_rms_over_max_w=3e-4)
+# Bounds: about 2.5x the recorded error statement of the FP32 form (P(k) cross
+# 1.34e-3 max / 4.5e-4 rms over 29 bins, auto 4.8e-4 max; position 3.1e-4 /
+# 1.2e-3 cells; |q| 3.1e-4 / 2.3e-3; w 1.3e-4 of max |w|)
+FP32_BOUNDS = dict(pk_cross_rel_max=3.5e-3, pk_cross_rel_rms=1.2e-3, pk_auto_rel_max=1.2e-3,
+                   pos_rms_cells=8e-4, pos_max_cells=3.5e-3, q_rel_rms=8e-4, q_rel_max=6e-3,
+                   w_abs_rms_over_max_w=3e-4)
 
 
 def _golden():

@@ -86,13 +86,14 @@ def test_total_density_spectrum_parity(prec):
 
 
 def test_pre_initial_dipole_parity_late_start():
-    """eq. transform at z = 100 in a 100 Mpc box: the transform shift q0 - p is
+    """eq. transform at z = 100 in a 100 Mpc box (a short schedule to z = 95,
+    whose drifts stay below half the box): the transform shift q0 - p is
     mostly the dipole (omega eps / nu) grad(nabla^-2 theta), and it must match
     the oracle's (pinned against -(tau/2) grad psi) within the binary32
     rounding of q0."""
     say("pre-IC dipole, late start fp64")
     cfg = workloads.small("c2", grid_n=16, n_side=16, n_steps=4, precision="fp64", box_mpc=100.0,
-                          z_begin=100.0, z_end=31.0, pre_ic=True, slip_amp=0.0)
+                          z_begin=100.0, z_end=95.0, pre_ic=True, slip_amp=0.0)
     cfg["species"][0]["m"] = 0.02
     ctx, fields, species = fastdf.setup_workload(cfg)
     q0 = ctx.read_state(species[0])[1]
