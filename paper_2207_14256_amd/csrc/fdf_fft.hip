@@ -8,8 +8,9 @@
 //   Y pass  : strided C2C along y, in place;
 //   Z pass  : contiguous C2R along z through a half-length complex FFT,
 //             writing all slots of a cell together (packed [G^3][nslot]).
-// Forward direction (P(k), sec. 4): Z pass R2C, Y pass, then an X pass that
-// bins Re(A conj B) into log-spaced |k| bins directly from LDS.
+// Forward direction (P(k), sec. 4): Z pass R2C, Y pass, X pass in place (or,
+// for the momentum spectrum, multiplied by i k_a and summed over the axes),
+// then exact log-|k| binning of Re(A conj B) in fixed point.
 //
 // Half-complex intermediates keep only n_z in [0, G/2): every Nyquist mode
 // of delta_0 is zero, and the spectrum bins stop below k_N, so the n_z = G/2
@@ -419,55 +420,10 @@ __global__ void __launch_bounds__(256) k_zpass_r2c(PkArgs a) {
   }
 }
 
-// --------------------------------------------- forward X pass + log binning --
-template <typename R, int G>
-__global__ void __launch_bounds__(256) k_xpass_bin(PkArgs a) {
-  using S = Shape<R, G>;
-  constexpr int NB0 = S::NBC / 2 > 0 ? S::NBC / 2 : 1;
-  constexpr int NB = NB0, NT = S::NT, M = S::M;
-  __shared__ cplx<R> bufa[G * NB];
-  __shared__ cplx<R> bufb[G * NB];
-  __shared__ double hist[3 * 256];
-  const int nzb = M / NB;
-  const int iy = blockIdx.x / nzb, iz0 = (blockIdx.x % nzb) * NB;
-  const cplx<R>* __restrict__ tw = (const cplx<R>*)a.twiddle;
-  const cplx<R>* scr = (const cplx<R>*)a.scratch;
-  const size_t plane = (size_t)G * G * M;
-  for (int e = threadIdx.x; e < 3 * a.nbins; e += NT) hist[e] = 0.0;
-  for (int e = threadIdx.x; e < G * NB; e += NT) {
-    const int ix = e / NB, b = e % NB;
-    const size_t gi = ((size_t)ix * G + iy) * M + iz0 + b;
-    bufa[ix * NB + b] = scr[gi];
-    if (!a.auto_mode) bufb[ix * NB + b] = scr[plane + gi];
-  }
-  __syncthreads();
-  fft_lines<R, G, NB, NT, false, 1>(bufa, tw);
-  if (!a.auto_mode) fft_lines<R, G, NB, NT, false, 1>(bufb, tw);
-  const cplx<R>* bb = a.auto_mode ? bufa : bufb;
-  const double norm = a.volume / ((double)G * G * G * (double)G * G * G);
-  const double log2h = (double)(31 - __clz(G / 2));
-  const int ny = signed_index(iy, G);
-  for (int e = threadIdx.x; e < G * NB; e += NT) {
-    const int ix = e / NB, b = e % NB;
-    const int nx = signed_index(ix, G), nz = iz0 + b;
-    const long n2 = (long)nx * nx + (long)ny * ny + (long)nz * nz;
-    if (n2 == 0) continue;
-    const int bin = (int)floor((double)a.nbins * log2((double)n2) / (2.0 * log2h));
-    if (bin >= a.nbins) continue;
-    const cplx<R> A = bufa[ix * NB + b], B = bb[ix * NB + b];
-    const double p = norm * ((double)A.x * (double)B.x + (double)A.y * (double)B.y);
-    const double w = nz == 0 ? 1.0 : 2.0;
-    atomicAdd(&hist[bin], w);
-    atomicAdd(&hist[a.nbins + bin], w * a.kf * sqrt((double)n2));
-    atomicAdd(&hist[2 * a.nbins + bin], w * p);
-  }
-  __syncthreads();
-  for (int e = threadIdx.x; e < 3 * a.nbins; e += NT)
-    if (hist[e] != 0.0) atomicAdd(&a.bins[e], hist[e]);
-}
-
 // ------------------------- forward X pass + i k_axis, summed over the axes --
-// Momentum spectrum: Theta = sum_a i k_a J_a(k), one axis per call.
+// Density spectrum (deriv_axis < 0): the x transform of each half, in place.
+// Momentum spectrum: Theta = sum_a i k_a J_a(k), one axis per call, summed
+// into planes 2 (and 3).
 template <typename R, int G>
 __global__ void __launch_bounds__(256) k_xpass_accum(PkArgs a) {
   using S = Shape<R, G>;
@@ -490,6 +446,13 @@ __global__ void __launch_bounds__(256) k_xpass_accum(PkArgs a) {
   __syncthreads();
   fft_lines<R, G, NB, NT, false, 1>(buf, tw);
   const int ny = signed_index(iy, G);
+  if (a.deriv_axis < 0) {   // each block owns its columns: in place is safe
+    for (int e = threadIdx.x; e < G * NB; e += NT) {
+      const int ix = e / NB, b = e % NB;
+      scr[h * plane + ((size_t)ix * G + iy) * M + iz0 + b] = buf[ix * NB + b];
+    }
+    return;
+  }
   cplx<R>* acc = scr + (2 + h) * plane;
   for (int e = threadIdx.x; e < G * NB; e += NT) {
     const int ix = e / NB, b = e % NB;
@@ -503,37 +466,112 @@ __global__ void __launch_bounds__(256) k_xpass_accum(PkArgs a) {
   }
 }
 
-// Log binning of the accumulated planes 2 (and 3), laid out [kx][ky][kz].
-template <typename R, int G>
-__global__ void __launch_bounds__(256) k_bin_accum(PkArgs a) {
-  constexpr int M = G / 2;
-  __shared__ double hist[3 * 256];
-  const cplx<R>* scr = (const cplx<R>*)a.scratch;
-  const size_t plane = (size_t)G * G * M;
-  const cplx<R>* A = scr + 2 * plane;
-  const cplx<R>* B = a.auto_mode ? A : scr + 3 * plane;
-  for (int e = threadIdx.x; e < 3 * a.nbins; e += blockDim.x) hist[e] = 0.0;
-  __syncthreads();
-  const double norm = a.volume / ((double)G * G * G * (double)G * G * G);
+// Log binning of planes bin_plane (and bin_plane + 1), laid out [kx][ky][kz]:
+// per bin the mode count, the sum of |n| and the sum of P = V Re(A conj B)
+// (modes with n_z > 0 count twice).  The sums are exact integer sums, so the
+// result does not depend on the order of the additions (bit for bit the same
+// from run to run): |n| in units of 2^-50 and P in units of 2^(e - 61), with
+// 2^e above every |P| (from a first pass), accumulated in 128 bits (a low
+// word whose carry goes to a high word) with 64-bit atomics.
+__device__ __forceinline__ int mode_bin(size_t gi, int G, int nbins, long* n2_out, int* nz_out) {
+  const int M = G / 2;
+  const int nz = (int)(gi % M), iy = (int)((gi / M) % G), ix = (int)(gi / ((size_t)M * G));
+  const int nx = signed_index(ix, G), ny = signed_index(iy, G);
+  const long n2 = (long)nx * nx + (long)ny * ny + (long)nz * nz;
+  *n2_out = n2;
+  *nz_out = nz;
+  if (n2 == 0) return -1;
   const double log2h = (double)(31 - __clz(G / 2));
+  const int bin = (int)floor((double)nbins * log2((double)n2) / (2.0 * log2h));
+  return bin < nbins ? bin : -1;
+}
+
+template <typename R, int G>
+__device__ __forceinline__ double mode_power(const PkArgs& a, size_t gi) {
+  const size_t plane = (size_t)G * G * (G / 2);
+  const cplx<R>* scr = (const cplx<R>*)a.scratch;
+  const cplx<R> u = scr[a.bin_plane * plane + gi];
+  const cplx<R> v = a.auto_mode ? u : scr[(a.bin_plane + 1) * plane + gi];
+  const double norm = a.volume / ((double)G * G * G * (double)G * G * G);
+  return norm * ((double)u.x * (double)v.x + (double)u.y * (double)v.y);
+}
+
+template <typename R, int G>
+__global__ void __launch_bounds__(256) k_bin_max(PkArgs a) {
+  const size_t plane = (size_t)G * G * (G / 2);
+  float m = 0.0f;
   for (size_t gi = blockIdx.x * (size_t)blockDim.x + threadIdx.x; gi < plane;
        gi += (size_t)gridDim.x * blockDim.x) {
-    const int nz = (int)(gi % M), iy = (int)((gi / M) % G), ix = (int)(gi / ((size_t)M * G));
-    const int nx = signed_index(ix, G), ny = signed_index(iy, G);
-    const long n2 = (long)nx * nx + (long)ny * ny + (long)nz * nz;
-    if (n2 == 0) continue;
-    const int bin = (int)floor((double)a.nbins * log2((double)n2) / (2.0 * log2h));
-    if (bin >= a.nbins) continue;
-    const cplx<R> u = A[gi], v = B[gi];
-    const double p = norm * ((double)u.x * (double)v.x + (double)u.y * (double)v.y);
-    const double w = nz == 0 ? 1.0 : 2.0;
-    atomicAdd(&hist[bin], w);
-    atomicAdd(&hist[a.nbins + bin], w * a.kf * sqrt((double)n2));
-    atomicAdd(&hist[2 * a.nbins + bin], w * p);
+    long n2;
+    int nz;
+    if (mode_bin(gi, G, a.nbins, &n2, &nz) < 0) continue;
+    m = fmaxf(m, __double2float_ru(fabs(mode_power<R, G>(a, gi))));
+  }
+  for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+  if ((threadIdx.x & 63) == 0 && m > 0.0f) atomicMax(a.max_bits, __float_as_uint(m));
+}
+
+// 128-bit add of a signed 64-bit value into (lo, hi) words.
+__device__ __forceinline__ void add128(unsigned long long* lo, unsigned long long* hi, long long v) {
+  const unsigned long long u = (unsigned long long)v;
+  const unsigned long long old = atomicAdd(lo, u);
+  const unsigned long long carry = (old + u < old) ? 1ull : 0ull;
+  const unsigned long long h = (v < 0 ? ~0ull : 0ull) + carry;
+  if (h) atomicAdd(hi, h);
+}
+
+constexpr double kNScale = 1125899906842624.0;   // 2^50: units of the |n| sums
+
+template <typename R, int G>
+__global__ void __launch_bounds__(256) k_bin_fixed(PkArgs a) {
+  __shared__ unsigned long long acc[5 * 256];
+  const int nb = a.nbins;
+  const size_t plane = (size_t)G * G * (G / 2);
+  for (int e = threadIdx.x; e < 5 * nb; e += blockDim.x) acc[e] = 0;
+  __syncthreads();
+  int e2;
+  frexpf(__uint_as_float(*a.max_bits), &e2);       // every |P| < 2^e2
+  const double inv_q = ldexp(1.0, 61 - e2);
+  for (size_t gi = blockIdx.x * (size_t)blockDim.x + threadIdx.x; gi < plane;
+       gi += (size_t)gridDim.x * blockDim.x) {
+    long n2;
+    int nz;
+    const int bin = mode_bin(gi, G, nb, &n2, &nz);
+    if (bin < 0) continue;
+    const long long w = nz == 0 ? 1 : 2;
+    const long long pq = __double2ll_rn(mode_power<R, G>(a, gi) * inv_q) * w;
+    const long long nq = __double2ll_rn(sqrt((double)n2) * kNScale) * w;
+    atomicAdd(&acc[bin], (unsigned long long)w);
+    add128(&acc[nb + bin], &acc[2 * nb + bin], nq);
+    add128(&acc[3 * nb + bin], &acc[4 * nb + bin], pq);
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < 3 * a.nbins; e += blockDim.x)
-    if (hist[e] != 0.0) atomicAdd(&a.bins[e], hist[e]);
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+    if (!acc[b]) continue;
+    atomicAdd(&a.acc[b], acc[b]);
+    for (int k = 0; k < 2; ++k) {   // 128-bit block sums into the global ones
+      const unsigned long long lo = acc[(1 + 2 * k) * nb + b], hi = acc[(2 + 2 * k) * nb + b];
+      const unsigned long long old = atomicAdd(&a.acc[(1 + 2 * k) * nb + b], lo);
+      const unsigned long long h = hi + ((old + lo < old) ? 1ull : 0ull);
+      if (h) atomicAdd(&a.acc[(2 + 2 * k) * nb + b], h);
+    }
+  }
+}
+
+// Exact sums -> [count][sum |k|][sum P] in binary64.
+__global__ void k_bin_sums(PkArgs a) {
+  const int nb = a.nbins;
+  int e2;
+  frexpf(__uint_as_float(*a.max_bits), &e2);
+  const double q = ldexp(1.0, e2 - 61);
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+    const double nsum = ((double)a.acc[2 * nb + b] * 18446744073709551616.0 + (double)a.acc[nb + b]) / kNScale;
+    const double psum = ((double)(long long)a.acc[4 * nb + b] * 18446744073709551616.0 +
+                         (double)a.acc[3 * nb + b]) * q;
+    a.bins[b] = (double)a.acc[b];
+    a.bins[nb + b] = a.kf * nsum;
+    a.bins[2 * nb + b] = psum;
+  }
 }
 
 // --------------------------------------------------------------- dispatch --
@@ -572,17 +610,16 @@ void power_spectrum_g(const PkArgs& a, hipStream_t s) {
   hipLaunchKernelGGL((k_ypass<R, G, false>), dim3(halves * G * nzb), dim3(S::NT), 0, s,
                      (cplx<R>*)a.scratch, (const cplx<R>*)a.twiddle);
   constexpr int NBb = S::NBC / 2 > 0 ? S::NBC / 2 : 1;
-  if (a.deriv_axis < 0)
-    hipLaunchKernelGGL((k_xpass_bin<R, G>), dim3(G * (S::M / NBb)), dim3(S::NT), 0, s, a);
-  else
-    hipLaunchKernelGGL((k_xpass_accum<R, G>), dim3(halves * G * (S::M / NBb)), dim3(S::NT), 0, s, a);
+  hipLaunchKernelGGL((k_xpass_accum<R, G>), dim3(halves * G * (S::M / NBb)), dim3(S::NT), 0, s, a);
 }
 
 template <typename R, int G>
-void bin_accum_g(const PkArgs& a, hipStream_t s) {
+void bin_g(const PkArgs& a, hipStream_t s) {
   const size_t plane = (size_t)G * G * (G / 2);
   const size_t blocks = std::min<size_t>((plane + 255) / 256, 2048);
-  hipLaunchKernelGGL((k_bin_accum<R, G>), dim3((unsigned)blocks), dim3(256), 0, s, a);
+  hipLaunchKernelGGL((k_bin_max<R, G>), dim3((unsigned)blocks), dim3(256), 0, s, a);
+  hipLaunchKernelGGL((k_bin_fixed<R, G>), dim3((unsigned)blocks), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_bin_sums, dim3(1), dim3(256), 0, s, a);
 }
 
 template <typename R>
@@ -601,16 +638,16 @@ void build_grids_r(const GridBuildArgs& a, hipStream_t s) {
 }
 
 template <typename R>
-void bin_accum_r(const PkArgs& a, hipStream_t s) {
+void bin_r(const PkArgs& a, hipStream_t s) {
   switch (a.G) {
-    case 8: bin_accum_g<R, 8>(a, s); break;
-    case 16: bin_accum_g<R, 16>(a, s); break;
-    case 32: bin_accum_g<R, 32>(a, s); break;
-    case 64: bin_accum_g<R, 64>(a, s); break;
-    case 128: bin_accum_g<R, 128>(a, s); break;
-    case 256: bin_accum_g<R, 256>(a, s); break;
-    case 512: bin_accum_g<R, 512>(a, s); break;
-    case 1024: bin_accum_g<R, 1024>(a, s); break;
+    case 8: bin_g<R, 8>(a, s); break;
+    case 16: bin_g<R, 16>(a, s); break;
+    case 32: bin_g<R, 32>(a, s); break;
+    case 64: bin_g<R, 64>(a, s); break;
+    case 128: bin_g<R, 128>(a, s); break;
+    case 256: bin_g<R, 256>(a, s); break;
+    case 512: bin_g<R, 512>(a, s); break;
+    case 1024: bin_g<R, 1024>(a, s); break;
     default: break;
   }
 }
@@ -642,9 +679,9 @@ void launch_power_spectrum(const PkArgs& a, hipStream_t s) {
   else power_spectrum_r<float>(a, s);
 }
 
-void launch_bin_accumulated(const PkArgs& a, hipStream_t s) {
-  if (a.fp64) bin_accum_r<double>(a, s);
-  else bin_accum_r<float>(a, s);
+void launch_bin(const PkArgs& a, hipStream_t s) {
+  if (a.fp64) bin_r<double>(a, s);
+  else bin_r<float>(a, s);
 }
 
 }  // namespace fdf

@@ -25,6 +25,9 @@ constexpr double kBoltzmannEvK = 8.617333262e-5;
 constexpr double kTnuKelvin = 1.95;           // present neutrino temperature (sec. 2)
 constexpr double kPi = 3.14159265358979323846;
 constexpr int kMaxBins = 256;
+// Spectrum bins region: [3][kMaxBins] binary64 results, then the exact sums
+// [5][kMaxBins] (64-bit words), then the largest |P| word.
+constexpr size_t kBinsBytes = (8 * kMaxBins + 2) * 8;
 constexpr size_t kAlign = 256;
 
 double t_nu_ev() { return kTnuKelvin * kBoltzmannEvK; }
@@ -213,7 +216,7 @@ Layout plan(const fdf_config& c) {
   L.twiddle_d = off; off += align_up(2 * G * 16);
   L.twiddle_f = off; off += align_up(2 * G * 8);
   L.seg = off; off += 2 * align_up((size_t)c.max_species * sizeof(Segment));
-  L.bins = off; off += align_up(3 * kMaxBins * sizeof(double));
+  L.bins = off; off += align_up(kBinsBytes);
   L.dep = off; off += kAlign;   // the fixed-point deposit's largest |value|
   L.scratch = off; off += L.scratch_bytes;
   L.dens = off; off += L.dens_bytes;
@@ -1301,12 +1304,21 @@ int fdf_weights(fdf_ctx* c, int32_t sid, double* d_w) {
   return launched(c, "weights");
 }
 
-// Binned spectrum of the energy-density contrast, or (momentum) of
-// Theta = sum_a i k_a J_a with J the deposit of w q: the three axes are
-// deposited and transformed one after the other and summed in Fourier space.
-static int power_spectrum(fdf_ctx* c, const int32_t* sp, int32_t ns, int32_t nbins, int32_t mode,
-                          bool momentum, int32_t analysis_n, double* hk, double* hp, double* hn) {
-  if (!c || !sp || ns < 1 || !hk || !hp || !hn) return FDF_ERR_ARG;
+// Device buffers of one spectrum: the deposit halves (8 bytes per cell),
+// the fixed-point deposit's largest |value|, the FFT planes (halves and the
+// momentum spectrum's two accumulators), the FP32 form's binary32 halves and
+// the bin accumulators.
+struct PkBuffers {
+  char* dens;
+  uint32_t* max_bits;
+  void* scratch;
+  float* real32;
+  double* bins;
+};
+
+// Arguments shared by both spectrum entry points; *G receives the mesh.
+static int pk_validate(fdf_ctx* c, const int32_t* sp, int32_t ns, int32_t nbins, int32_t mode,
+                       int32_t analysis_n, int* G) {
   if (!needs_ws(c)) return fail(c, FDF_ERR_WORKSPACE, "no workspace attached");
   if (nbins < 1 || nbins > kMaxBins) return fail(c, FDF_ERR_ARG, "n_bins must be in [1, 256]");
   if (mode != FDF_PK_CROSS && mode != FDF_PK_AUTO) return fail(c, FDF_ERR_ARG, "unknown mode");
@@ -1321,43 +1333,50 @@ static int power_spectrum(fdf_ctx* c, const int32_t* sp, int32_t ns, int32_t nbi
   const int Gm = c->cfg.grid_n;
   if (analysis_n != 0 && (!is_pow2(analysis_n) || analysis_n < 8 || analysis_n > Gm))
     return fail(c, FDF_ERR_ARG, "analysis_n must be 0 or a power of two in [8, grid_n]");
-  const int G = analysis_n ? analysis_n : Gm;
+  *G = analysis_n ? analysis_n : Gm;
+  return FDF_OK;
+}
+
+// Binned spectrum of the energy-density contrast, or (momentum) of
+// Theta = sum_a i k_a J_a with J the deposit of w q: the three axes are
+// deposited and transformed one after the other and summed in Fourier space.
+// Enqueues the work on the context stream; the bins end in b.bins as
+// [count][sum |k|][sum P] per bin, from exact (order-independent) sums.
+static void pk_enqueue(fdf_ctx* c, const int32_t* sp, int32_t ns, int32_t nbins, int32_t mode,
+                       bool momentum, int G, const PkBuffers& b) {
+  const int Gm = c->cfg.grid_n;
   const bool f64 = c->cfg.precision == FDF_PREC_FP64;
   const size_t cells = (size_t)G * G * G;
   const double a = c->a[c->step_index];
   double esum = 0;
-  std::vector<double> emean(ns);
-  for (int i = 0; i < ns; ++i) { emean[i] = mean_energy(c->species[sp[i]].m, a); esum += emean[i]; }
-  char* dens = c->ws + c->lay.dens;
+  for (int i = 0; i < ns; ++i) esum += mean_energy(c->species[sp[i]].m, a);
   // FP32 form: fixed-point halves in dens (int64 per cell), converted to
-  // binary32 meshes behind the transform's planes in the FFT scratch
-  uint32_t* max_bits = (uint32_t*)(c->ws + c->lay.dep);
-  float* real32 = (float*)(c->ws + c->lay.scratch + density_copy_offset(c));
+  // binary32 meshes for the transform
   int64_t n_all = 0;
   for (int i = 0; i < ns; ++i) n_all += c->species[sp[i]].n;
   int fixed_bits = 62;
   while (fixed_bits > 20 && ((int64_t)1 << (62 - fixed_bits)) < n_all) --fixed_bits;
-  std::pair<hipEvent_t, hipEvent_t> ev;
-  timing_begin(c, FDF_KERNEL_OUTPUT, &ev);
-  double* bins = (double*)(c->ws + c->lay.bins);
-  launch_fill_zero(bins, align_up(3 * kMaxBins * sizeof(double)), c->stream);
+  launch_fill_zero(b.bins, align_up(kBinsBytes), c->stream);
   PkArgs pk{};
   pk.G = G;
   pk.fp64 = f64;
   pk.nbins = nbins;
   pk.auto_mode = mode == FDF_PK_AUTO;
   pk.volume = c->cfg.box_mpc * c->cfg.box_mpc * c->cfg.box_mpc;
-  pk.grid_a = f64 ? (void*)dens : (void*)real32;
-  pk.grid_b = f64 ? (void*)(dens + cells * 8) : (void*)(real32 + cells);
-  pk.scratch = c->ws + c->lay.scratch;
+  pk.grid_a = f64 ? (void*)b.dens : (void*)b.real32;
+  pk.grid_b = f64 ? (void*)(b.dens + cells * 8) : (void*)(b.real32 + cells);
+  pk.scratch = b.scratch;
   pk.twiddle = c->ws + (f64 ? c->lay.twiddle_d + twiddle_entry(Gm, G) * 16
                             : c->lay.twiddle_f + twiddle_entry(Gm, G) * 8);
-  pk.bins = bins;
+  pk.bins = b.bins;
+  pk.acc = (unsigned long long*)(b.bins + 3 * kMaxBins);
+  pk.max_bits = (uint32_t*)(b.bins + 8 * kMaxBins);
+  pk.bin_plane = momentum ? 2 : 0;
   pk.kf = 2.0 * kPi / c->cfg.box_mpc;
   pk.deriv_axis = -1;
   for (int axis = momentum ? 0 : -1; axis < (momentum ? 3 : 0); ++axis) {
-    launch_fill_zero(dens, align_up(2 * cells * 8), c->stream);
-    if (!f64) launch_fill_zero(max_bits, kAlign, c->stream);
+    launch_fill_zero(b.dens, align_up(2 * cells * 8), c->stream);
+    if (!f64) launch_fill_zero(b.max_bits, kAlign, c->stream);
     for (int pass = f64 ? 1 : 0; pass < 2; ++pass)
     for (int i = 0; i < ns; ++i) {
       const SpeciesRec& s = c->species[sp[i]];
@@ -1372,23 +1391,23 @@ static int power_spectrum(fdf_ctx* c, const int32_t* sp, int32_t ns, int32_t nbi
         o.norm[1] = no ? g3 / ((double)no * esum) : 0.0;
       }
       o.G = G;
-      o.dens[0] = dens;
-      o.dens[1] = dens + cells * 8;
+      o.dens[0] = b.dens;
+      o.dens[1] = b.dens + cells * 8;
       o.quantity = axis;
-      o.max_bits = max_bits;
+      o.max_bits = b.max_bits;
       o.fixed_bits = fixed_bits;
       if (pass == 0) launch_deposit_max(o, c->stream);
       else launch_deposit(o, c->stream);
     }
     if (!f64) {
       FixedToRealArgs fr{};
-      fr.src[0] = (const long long*)dens;
-      fr.src[1] = (const long long*)(dens + cells * 8);
-      fr.dst[0] = real32;
-      fr.dst[1] = real32 + cells;
+      fr.src[0] = (const long long*)b.dens;
+      fr.src[1] = (const long long*)(b.dens + cells * 8);
+      fr.dst[0] = b.real32;
+      fr.dst[1] = b.real32 + cells;
       fr.n_half = cells;
       fr.n = (mode == FDF_PK_AUTO ? 1 : 2) * cells;
-      fr.max_bits = max_bits;
+      fr.max_bits = b.max_bits;
       fr.fixed_bits = fixed_bits;
       launch_fixed_to_real(fr, c->stream);
     }
@@ -1396,21 +1415,38 @@ static int power_spectrum(fdf_ctx* c, const int32_t* sp, int32_t ns, int32_t nbi
     pk.accum_first = axis == 0;
     launch_power_spectrum(pk, c->stream);
   }
-  if (momentum) launch_bin_accumulated(pk, c->stream);
+  launch_bin(pk, c->stream);
+}
+
+static int power_spectrum(fdf_ctx* c, const int32_t* sp, int32_t ns, int32_t nbins, int32_t mode,
+                          bool momentum, int32_t analysis_n, double* hk, double* hp, double* hn) {
+  if (!c || !sp || ns < 1 || !hk || !hp || !hn) return FDF_ERR_ARG;
+  int G = 0;
+  int rc = pk_validate(c, sp, ns, nbins, mode, analysis_n, &G);
+  if (rc) return rc;
+  PkBuffers b{};
+  b.dens = c->ws + c->lay.dens;
+  b.max_bits = (uint32_t*)(c->ws + c->lay.dep);
+  b.scratch = c->ws + c->lay.scratch;
+  b.real32 = (float*)(c->ws + c->lay.scratch + density_copy_offset(c));
+  b.bins = (double*)(c->ws + c->lay.bins);
+  std::pair<hipEvent_t, hipEvent_t> ev;
+  timing_begin(c, FDF_KERNEL_OUTPUT, &ev);
+  pk_enqueue(c, sp, ns, nbins, mode, momentum, G, b);
   timing_end(c, FDF_KERNEL_OUTPUT, ev);
-  int rc = launched(c, "power spectrum");
+  rc = launched(c, "power spectrum");
   if (rc) return rc;
   std::vector<double> hb(3 * nbins);
-  rc = hip_check(c, hipMemcpyAsync(hb.data(), bins, hb.size() * 8, hipMemcpyDeviceToHost, c->stream), "bins");
+  rc = hip_check(c, hipMemcpyAsync(hb.data(), b.bins, hb.size() * 8, hipMemcpyDeviceToHost, c->stream), "bins");
   if (!rc) rc = hip_check(c, hipStreamSynchronize(c->stream), "bins");
   if (rc) return rc;
-  for (int b = 0; b < nbins; ++b) {
-    const double cnt = hb[b];
-    hn[b] = cnt;
-    hk[b] = cnt > 0 ? hb[nbins + b] / cnt : NAN;
-    hp[b] = cnt > 0 ? hb[2 * nbins + b] / cnt : NAN;
+  for (int i = 0; i < nbins; ++i) {
+    const double cnt = hb[i];
+    hn[i] = cnt;
+    hk[i] = cnt > 0 ? hb[nbins + i] / cnt : NAN;
+    hp[i] = cnt > 0 ? hb[2 * nbins + i] / cnt : NAN;
   }
-  c->have_density = !momentum && G == Gm;   // else the buffers hold another quantity or mesh
+  c->have_density = !momentum && G == c->cfg.grid_n;   // else the buffers hold another quantity or mesh
   c->density_auto = mode == FDF_PK_AUTO;
   return FDF_OK;
 }

@@ -68,11 +68,16 @@ struct PkArgs {
   const void* grid_b;
   void* scratch;           // complex [2][G][G][G/2]
   const void* twiddle;
-  double* bins;            // [3][nbins]: count, sum |k|, sum P  (zeroed by caller)
+  double* bins;            // [3][nbins]: count, sum |k|, sum P, written by the binning
+  unsigned long long* acc; // [5][nbins] exact bin sums: count, sum |n| (128-bit fixed point,
+                           // lo and hi words), sum P (128-bit fixed point, lo and signed hi)
+                           // (zeroed by the caller, with *max_bits)
+  uint32_t* max_bits;      // binary32 bits of the largest |P| of a mode (the P quantum)
   double kf;
-  int32_t deriv_axis;      // -1: bin the transforms; 0-2: multiply by i k_axis and add into
-                           // scratch planes 2 (and 3), which the binning pass then reads
+  int32_t deriv_axis;      // -1: transform the halves in place (planes 0, 1); 0-2: multiply by
+                           // i k_axis and add into scratch planes 2 (and 3)
   int32_t accum_first;     // 1: the first term of the sum (store instead of add)
+  int32_t bin_plane;       // first plane the binning reads: 0 (density) or 2 (momentum)
 };
 
 // Segment of the batched particle state: one species.
@@ -228,7 +233,7 @@ void launch_deposit(const OutputArgs& a, hipStream_t s);
 void launch_deposit_max(const OutputArgs& a, hipStream_t s);   // FP32 form, before launch_deposit
 void launch_fixed_to_real(const FixedToRealArgs& a, hipStream_t s);
 void launch_power_spectrum(const PkArgs& a, hipStream_t s);
-void launch_bin_accumulated(const PkArgs& a, hipStream_t s);
+void launch_bin(const PkArgs& a, hipStream_t s);   // bins planes bin_plane (and + 1) into a.bins
 void launch_fill_zero(void* ptr, size_t bytes, hipStream_t s);
 int push_chunk_particles(int ppt);
 int push_sort_block_lds(int waves);   // LDS to reserve per k_push_sort_f32 block for a cap of `waves` per SIMD
