@@ -292,6 +292,23 @@ int fdf_power_spectrum(struct fdf_ctx* ctx, const int32_t* species, int32_t n_sp
                        int32_t n_bins, int32_t mode, int32_t quantity, int32_t analysis_n,
                        double* h_k, double* h_p, double* h_nmodes);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * spectrum of fdf_power_spectrum on an analysis mesh of analysis_n points per
+ * side, a power of two in [8, min(64, G)] (0 means G and is accepted only when
+ * G <= 64), computed without any allocation.  Its temporaries (deposit
+ * halves, FFT planes, bin sums) live in a static 16 MiB device array of the
+ * library, one per GPU, held until the process ends; a larger mesh returns
+ * FDF_ERR_ARG.  d_out: device pointer to 3 * n_bins doubles, written as
+ * [mean |k|][P(k)][modes] (NaN means for an empty bin).  Enqueued on the
+ * context stream; nothing is copied to the host and nothing waits.  Every
+ * call on one GPU uses the same array, so calls that overlap on one GPU (two
+ * streams, two threads, two contexts) race; calls in stream order do not.
+ * Other errors as fdf_power_spectrum. */
+int fdf_power_spectrum_noalloc(struct fdf_ctx* ctx, const int32_t* species, int32_t n_species,
+                               int32_t n_bins, int32_t mode, int32_t quantity, int32_t analysis_n,
+                               double* d_out);
+
 /* Fig. 2 diagnostic (sec. 3.1): root mean square over the species' particles
  * of the magnitude of each term of eq. releq at the current state and a_k --
  * h_rms[0] = |eps grad psi|, [1] = |(q^2/eps) grad phi|, [2] = |q (q.grad phi)/eps|,

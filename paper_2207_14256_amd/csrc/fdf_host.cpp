@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -742,6 +743,48 @@ int new_species(fdf_ctx* c, int32_t field_id, double m, int64_t n, uint64_t seed
 
 }  // namespace
 
+// -------------------------------------------- static scratch (no allocation) --
+// Device memory of fdf_power_spectrum_noalloc: one array per GPU, held until
+// the process ends.  Host code never passes `scratch` itself to a kernel or a
+// copy; it uses the address hipGetSymbolAddress returns for the current device.
+constexpr size_t kStaticScratchBytes = (size_t)16 << 20;
+constexpr int kStaticMaxMesh = 64;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The static scratch of the current device (resolved once per device).
+int static_scratch(fdf_ctx* c, char** out) {
+  int dev = -1;
+  int rc = hip_check(c, hipGetDevice(&dev), "hipGetDevice");
+  if (rc) return rc;
+  if (dev < 0 || dev >= kMaxDevices) return fail(c, FDF_ERR_UNSUPPORTED, "device index beyond the static scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    rc = hip_check(c, hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+    if (rc) return rc;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = (char*)g_scratch_ptr[dev];
+  return FDF_OK;
+}
+
+// Static scratch bytes of a spectrum on a G^3 mesh: bins, the maximum word,
+// the deposit halves (8 bytes per cell each), four FFT planes and (FP32 form)
+// the binary32 halves.
+size_t static_scratch_bytes(bool f64, int G) {
+  const size_t g3 = (size_t)G * G * G, plane = (size_t)G * G * (G / 2) * (f64 ? 16 : 8);
+  return align_up(kBinsBytes) + kAlign + align_up(2 * g3 * 8) + align_up(4 * plane) +
+         (f64 ? 0 : align_up(2 * g3 * 4));
+}
+
+}  // namespace
+
 // ============================================================== C ABI ======
 extern "C" {
 
@@ -827,6 +870,9 @@ int fdf_attach_workspace(fdf_ctx* c, void* dptr, size_t bytes) {
   c->ws = (char*)dptr;
   c->ws_bytes = bytes;
   fill_twiddles(c);
+  char* st = nullptr;
+  const int rc = static_scratch(c, &st);   // set-up of the no-allocation entry point's scratch
+  if (rc) return rc;
   return fdf_reset(c);
 }
 
@@ -1466,6 +1512,33 @@ int fdf_power_spectrum(fdf_ctx* c, const int32_t* sp, int32_t ns, int32_t nbins,
   if (quantity != FDF_PK_DENSITY && quantity != FDF_PK_MOMENTUM)
     return c ? fail(c, FDF_ERR_ARG, "unknown quantity") : FDF_ERR_ARG;
   return power_spectrum(c, sp, ns, nbins, mode, quantity == FDF_PK_MOMENTUM, analysis_n, hk, hp, hn);
+}
+
+int fdf_power_spectrum_noalloc(fdf_ctx* c, const int32_t* sp, int32_t ns, int32_t nbins, int32_t mode,
+                               int32_t quantity, int32_t analysis_n, double* d_out) {
+  if (!c || !sp || ns < 1 || !d_out) return FDF_ERR_ARG;
+  if (quantity != FDF_PK_DENSITY && quantity != FDF_PK_MOMENTUM) return fail(c, FDF_ERR_ARG, "unknown quantity");
+  int G = 0;
+  int rc = pk_validate(c, sp, ns, nbins, mode, analysis_n, &G);
+  if (rc) return rc;
+  const bool f64 = c->cfg.precision == FDF_PREC_FP64;
+  if (G > kStaticMaxMesh || static_scratch_bytes(f64, G) > kStaticScratchBytes)
+    return fail(c, FDF_ERR_ARG, "the no-allocation spectrum needs an analysis mesh of at most 64^3 "
+                                "(analysis_n in [8, 64]): its static scratch holds 16 MiB");
+  char* st = nullptr;
+  rc = static_scratch(c, &st);
+  if (rc) return rc;
+  const size_t g3 = (size_t)G * G * G, plane = (size_t)G * G * (G / 2) * (f64 ? 16 : 8);
+  PkBuffers b{};
+  size_t off = 0;
+  b.bins = (double*)(st + off); off += align_up(kBinsBytes);
+  b.max_bits = (uint32_t*)(st + off); off += kAlign;
+  b.dens = st + off; off += align_up(2 * g3 * 8);
+  b.scratch = st + off; off += align_up(4 * plane);
+  b.real32 = f64 ? nullptr : (float*)(st + off);
+  pk_enqueue(c, sp, ns, nbins, mode, quantity == FDF_PK_MOMENTUM, G, b);
+  launch_bins_finalize(b.bins, nbins, d_out, c->stream);
+  return launched(c, "power spectrum (static scratch)");
 }
 
 int fdf_read_state(fdf_ctx* c, int32_t sid, double* hx, double* hq) {

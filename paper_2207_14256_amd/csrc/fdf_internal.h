@@ -232,6 +232,7 @@ void launch_weights(const OutputArgs& a, hipStream_t s);
 void launch_deposit(const OutputArgs& a, hipStream_t s);
 void launch_deposit_max(const OutputArgs& a, hipStream_t s);   // FP32 form, before launch_deposit
 void launch_fixed_to_real(const FixedToRealArgs& a, hipStream_t s);
+void launch_bins_finalize(const double* bins, int nbins, double* out, hipStream_t s);
 void launch_power_spectrum(const PkArgs& a, hipStream_t s);
 void launch_bin(const PkArgs& a, hipStream_t s);   // bins planes bin_plane (and + 1) into a.bins
 void launch_fill_zero(void* ptr, size_t bytes, hipStream_t s);

@@ -156,6 +156,18 @@ __global__ void k_fixed_to_real(FixedToRealArgs a) {
   }
 }
 
+// Bin sums [count][sum |k|][sum P] -> [mean |k|][mean P][count]; an empty
+// bin's means are NaN.
+__global__ void k_bins_finalize(const double* bins, int nbins, double* out) {
+  const double nan = __longlong_as_double(0x7ff8000000000000LL);
+  for (int b = threadIdx.x; b < nbins; b += blockDim.x) {
+    const double cnt = bins[b];
+    out[b] = cnt > 0 ? bins[nbins + b] / cnt : nan;
+    out[nbins + b] = cnt > 0 ? bins[2 * nbins + b] / cnt : nan;
+    out[2 * nbins + b] = cnt;
+  }
+}
+
 // Squared magnitudes of -eps grad psi, -(q^2/eps) grad phi, q (q . grad phi)/eps
 // and q phidot at the particle's CIC-interpolated mesh values, summed per
 // block in LDS and added to a.out.
@@ -245,6 +257,10 @@ void launch_force_terms(const TermArgs& a, hipStream_t s) {
 void launch_deposit(const OutputArgs& a, hipStream_t s) {
   if (a.fp64) hipLaunchKernelGGL(k_deposit_f64, dim3(grid_for((size_t)a.seg.n, 256)), dim3(256), 0, s, a);
   else hipLaunchKernelGGL(k_deposit_fixed, dim3(grid_for((size_t)a.seg.n, 256)), dim3(256), 0, s, a);
+}
+
+void launch_bins_finalize(const double* bins, int nbins, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_bins_finalize, dim3(1), dim3(256), 0, s, bins, nbins, out);
 }
 
 void launch_deposit_max(const OutputArgs& a, hipStream_t s) {

@@ -32,7 +32,7 @@ EXPORTS = [
     "fdf_read_state", "fdf_read_grid", "fdf_read_field", "fdf_read_density",
     "fdf_read_schedule", "fdf_get_info", "fdf_sync", "fdf_timing_enable",
     "fdf_read_timing", "fdf_timing_reset", "fdf_status_string", "fdf_last_error",
-    "fdf_get_tuning", "fdf_set_tuning",
+    "fdf_get_tuning", "fdf_set_tuning", "fdf_power_spectrum_noalloc",
 ]
 
 
@@ -107,6 +107,7 @@ def load():
         "fdf_momentum_power_spectrum": [P, ctypes.POINTER(I32), I32, I32, I32, PD, PD, PD],
         "fdf_force_terms": [P, I32, PD],
         "fdf_power_spectrum": [P, ctypes.POINTER(I32), I32, I32, I32, I32, I32, PD, PD, PD],
+        "fdf_power_spectrum_noalloc": [P, ctypes.POINTER(I32), I32, I32, I32, I32, I32, P],
         "fdf_read_state": [P, I32, PD, PD],
         "fdf_read_grid": [P, I32, I32, PD],
         "fdf_read_field": [P, I32, PD],
@@ -295,6 +296,20 @@ class Context:
             self._check(getattr(self.lib, name)(self.ctx, spp, len(sp), int(n_bins), md,
                                                 _dptr(k), _dptr(p), _dptr(nm)), name)
         return k, p, nm
+
+    def power_spectrum_noalloc(self, species, n_bins, out, mode="cross", quantity="density",
+                               analysis_n=0):
+        """fdf_power_spectrum_noalloc: the spectrum on an analysis mesh of at
+        most 64^3, written to the device tensor out (3 * n_bins float64:
+        mean k, P(k), modes) without any allocation; asynchronous."""
+        sp = np.asarray(species if hasattr(species, "__len__") else [species], dtype=np.int32)
+        assert out.dtype == self.torch.float64 and out.is_contiguous() and out.numel() >= 3 * n_bins
+        md = PK_AUTO if mode == "auto" else PK_CROSS
+        qn = {"density": PK_DENSITY, "momentum": PK_MOMENTUM}[quantity]
+        self._check(self.lib.fdf_power_spectrum_noalloc(
+            self.ctx, sp.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), len(sp), int(n_bins), md, qn,
+            int(analysis_n), ctypes.c_void_p(out.data_ptr())), "fdf_power_spectrum_noalloc")
+        return out
 
     def force_terms(self, species):
         """rms magnitudes of the four terms of eq. releq at the current state:
