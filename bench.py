@@ -39,41 +39,49 @@ def log(msg):
 def mesh_slots(cfg):
     """(stored slots per cell, slots that carry data): grad psi (3), grad phi
     (3, when psi != phi) and phi-dot (1, when the potentials depend on time);
-    bfloat16 cells keep 4 or 8 slots, binary64 cells with phi-dot = 0 keep 6."""
+    cells with phi-dot = 0 keep 6 (bfloat16 ones 8 with pad_mesh)."""
     slip = bool(cfg.get("slip_amp", 0.0))
     tdep = cfg.get("model") == "radmat"
     data = 3 + (3 if slip else 0) + (1 if tdep else 0)
     if not slip:
         stored = 4
-    elif cfg["precision"] == "fp64" and not tdep:
+    elif (cfg["precision"] == "fp64" or not cfg.get("pad_mesh")) and not tdep:
         stored = 6
     else:
         stored = 8
     return stored, data
 
 
-def bytes_per_launch(cfg, n_particles, drift):
-    """Algorithmic HBM bytes of one push launch: state read + write per
-    particle, plus one read of the slots of the gradient mesh that carry data
-    (the zero phi-dot slot and the pad of a bfloat16 cell are traffic, not
-    algorithm: see mesh_padding_bytes).  FP32 form: read x, q0, dq (36 B),
-    write x, dq (24 B; 12 B without the drift); FP64 form: read x, q, q0
-    (72 B), write x, q (48 B; 24 B without the drift)."""
-    G = cfg["grid_n"]
-    _, data = mesh_slots(cfg)
+def state_bytes(cfg, drift):
+    """Algorithmic state bytes of one particle-update: FP32 form read x, q0,
+    dq (36 B), write x, dq (24 B; 12 B on a kick-only launch); FP64 form read
+    x, q, q0 (72 B), write x, q (48 B; 24 B kick-only)."""
     if cfg["precision"] == "fp32":
-        per = 36 + (24 if drift else 12)
-        grid = G ** 3 * data * 2
-    else:
-        per = 72 + (48 if drift else 24)
-        grid = G ** 3 * data * 8
-    return n_particles * per + grid
+        return 36 + (24 if drift else 12)
+    return 72 + (48 if drift else 24)
+
+
+def mesh_cell_bytes(cfg):
+    """Algorithmic bytes of one mesh cell read: its slots that carry data (the
+    zero phi-dot slot and the pad of a bfloat16 cell are traffic, not
+    algorithm: see mesh_padding_bytes)."""
+    _, data = mesh_slots(cfg)
+    return data * (2 if cfg["precision"] == "fp32" else 8)
+
+
+def bytes_per_launch(cfg, n_particles, drift):
+    """Algorithmic HBM bytes of one push launch over n_particles of one
+    field: state read + write per particle plus one read of the mesh."""
+    return n_particles * state_bytes(cfg, drift) + cfg["grid_n"] ** 3 * mesh_cell_bytes(cfg)
 
 
 def mesh_padding_bytes(cfg):
-    """Bytes per launch of mesh slots read but carrying no data."""
+    """Bytes per mesh of slots read but carrying no data."""
     stored, data = mesh_slots(cfg)
     return cfg["grid_n"] ** 3 * (stored - data) * (2 if cfg["precision"] == "fp32" else 8)
+
+
+SORT_PUSH_STATE_BYTES = 92   # x, q0, dq, id and the rank outputs read; the 40 B state written
 
 
 def bytes_per_push_sort(cfg, n_particles):
@@ -81,9 +89,7 @@ def bytes_per_push_sort(cfg, n_particles):
     re-sort (FP32 form): the push's reads (x, q0, dq: 36 B), the id and the
     rank pass outputs (source slot, bucket, rank: 16 B) read, the whole state
     written in sorted order (40 B), and one read of the mesh's data slots."""
-    G = cfg["grid_n"]
-    _, data = mesh_slots(cfg)
-    return n_particles * 92 + G ** 3 * data * 2
+    return n_particles * SORT_PUSH_STATE_BYTES + cfg["grid_n"] ** 3 * mesh_cell_bytes(cfg)
 
 
 def run_leg(cfg, steps, warmup, label, tuning=None):
@@ -122,6 +128,7 @@ def run_leg(cfg, steps, warmup, label, tuning=None):
     t1 = time.perf_counter()
     push_ms, launches = ctx.read_timing("push")
     ps_ms, ps_launches = ctx.read_timing("push_sort")
+    work_push, work_ps = ctx.read_work("push"), ctx.read_work("push_sort")
     grid_ms, _ = ctx.read_timing("grid")
     sort_ms, sorts = ctx.read_timing("sort")
     out_ms, _ = ctx.read_timing("output")
@@ -131,21 +138,20 @@ def run_leg(cfg, steps, warmup, label, tuning=None):
     torch.cuda.empty_cache()
     n = cfg["n_steps"]
     job_s = (t1 - t0) / steps
-    # The push timer counts the plain push launches (one kick-only launch per
-    # job, the rest kick + drift, one step each); the push_sort timer the
-    # launches that also carry out a re-sort, one per species and re-sort.
+    # Algorithmic bytes from the library's own count of the work of the timed
+    # launches: particle-updates (with and without a drift) and mesh cells
+    # read (each field mesh a launch gathers from; with several species on
+    # their own re-sort cadence a plain launch may leave out the species a
+    # fused re-sort pushed).
     kernels = {}
-    total_bytes = ((launches - steps) * bytes_per_launch(cfg, n_total, True)
-                   + steps * bytes_per_launch(cfg, n_total, False))
+    wd, wk, mc = work_push
     kernels["k_push_f32" if cfg["precision"] == "fp32" else "k_push_f64"] = dict(
-        ms=push_ms, launches=launches, bytes=total_bytes)
+        ms=push_ms, launches=launches,
+        bytes=wd * state_bytes(cfg, True) + wk * state_bytes(cfg, False) + mc * mesh_cell_bytes(cfg))
     if ps_launches:
-        nspec = len(cfg["species"])
-        sorts_fused = ps_launches // nspec
-        mesh = bytes_per_push_sort(cfg, 0)
+        wd, _, mc = work_ps
         kernels["k_push_sort_f32"] = dict(ms=ps_ms, launches=ps_launches,
-                                          bytes=sorts_fused * (bytes_per_push_sort(cfg, n_total) - mesh
-                                                               + nspec * mesh))
+                                          bytes=wd * SORT_PUSH_STATE_BYTES + mc * mesh_cell_bytes(cfg))
     for k in kernels.values():
         k["avg_launch_ms"] = k["ms"] / k["launches"]
         k["bytes_per_launch"] = k["bytes"] / k["launches"]

@@ -142,6 +142,11 @@ typedef struct fdf_config {
                               built at anchor times where the transfer functions have
                               changed by more than this fraction since the previous
                               anchor, and linearly interpolated in a in between */
+  int32_t pad_mesh;        /* FP32 form with psi != phi and phi-dot identically zero (POISSON):
+                              0 stores the six gradient slots in 12-byte bfloat16 cells (the
+                              default: 25 % less mesh traffic), 1 in 16-byte cells with a zero
+                              slot and a pad (aligned, never across a cache line).  No effect
+                              otherwise; results are bit for bit the same */
 } fdf_config;
 
 typedef struct fdf_info {
@@ -352,6 +357,13 @@ int fdf_sync(struct fdf_ctx* ctx);
 int fdf_timing_enable(struct fdf_ctx* ctx, int32_t enable);
 int fdf_read_timing(struct fdf_ctx* ctx, int32_t kernel_class, double* total_ms, int64_t* launches);
 int fdf_timing_reset(struct fdf_ctx* ctx);
+
+/* Work done by the timed launches of a kernel class since the last
+ * fdf_timing_reset (counted while timing is enabled; the push classes only):
+ * work[0] particle-updates with a drift, work[1] kick-only particle-updates,
+ * work[2] mesh cells read (one per cell of each field mesh a launch gathers
+ * from, two with super-step blending).  Host pointer to 3 int64. */
+int fdf_read_work(struct fdf_ctx* ctx, int32_t kernel_class, int64_t* work);
 
 const char* fdf_status_string(int status);
 const char* fdf_last_error(const struct fdf_ctx* ctx);

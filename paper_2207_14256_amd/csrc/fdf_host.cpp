@@ -158,15 +158,16 @@ struct Layout {
 
 bool eom_potentials(const fdf_config& c) { return c.eom == FDF_EOM_EXACT || c.eom == FDF_EOM_CANONICAL; }
 // Slots per mesh cell.  Separable form: grad psi and phi-dot (4) when
-// psi = phi; else grad psi, grad phi and phi-dot (8).  Binary64 meshes drop
-// the phi-dot slot when it is zero (6 slots = three 16-byte loads per
-// corner); bfloat16 meshes keep 8, whose 16-byte cells never straddle a
-// cache line (12-byte cells measured slower).
+// psi = phi; else grad psi, grad phi and phi-dot (8).  When phi-dot is zero
+// the cell drops it and the pad: 6 slots (binary64: three 16-byte loads per
+// corner; bfloat16: one 12-byte load), unless pad_mesh asks for the aligned
+// 16-byte bfloat16 cell.
 int slots_for(const fdf_config& c) {
   if (c.eom == FDF_EOM_SEPARABLE) {
     if (c.slip_amp == 0.0) return 4;
     const bool f64 = c.precision == FDF_PREC_FP64;
-    return (f64 && c.potential_model != FDF_MODEL_RADMAT) ? 6 : 8;
+    if (c.potential_model == FDF_MODEL_RADMAT) return 8;
+    return (f64 || !c.pad_mesh) ? 6 : 8;
   }
   return eom_potentials(c) ? 8 : 4;
 }
@@ -258,6 +259,7 @@ const char* validate(const fdf_config* c) {
   if (!(c->superstep_tol >= 0) || !std::isfinite(c->superstep_tol)) return "superstep_tol must be >= 0";
   if (c->eom < FDF_EOM_SEPARABLE || c->eom > FDF_EOM_NEWTONIAN) return "unknown equation of motion";
   if (c->interp_order < 0 || c->interp_order > 2) return "interp_order must be 0, 1 (CIC) or 2 (TSC)";
+  if (c->pad_mesh != 0 && c->pad_mesh != 1) return "pad_mesh must be 0 or 1";
   return nullptr;
 }
 
@@ -280,25 +282,28 @@ struct SpeciesRec {
   Segment seg[2];   // state buffers (second copy only with sorting)
   int cur = 0;
   bool pristine = false;   // state is exactly the sampled one (no pre-IC, not stepped)
+  double drift_cells = 0;  // typical drift since its last re-sort, in mesh cells
 };
 
 // A captured step sequence: the host state it was captured from and the host
 // state it leaves behind, so a replay can stand in for the enqueue.
 struct HostStepState {
   int step_index = 0;
-  int cur = 0;
   bool sorted_once = false;
-  double drift_cells = 0;
+  std::vector<int> cur;            // per species: the copy holding its state
+  std::vector<double> drift_cells; // per species
   std::vector<double> grid_a;      // per field; NaN = no grid
   std::vector<int> tags;           // per field, two super-step set tags
   std::vector<char> pristine;      // per species
   bool operator==(const HostStepState& o) const {
     if (step_index != o.step_index || cur != o.cur || sorted_once != o.sorted_once || tags != o.tags ||
-        pristine != o.pristine ||
-        std::memcmp(&drift_cells, &o.drift_cells, sizeof(double)) != 0 || grid_a.size() != o.grid_a.size())
+        pristine != o.pristine || grid_a.size() != o.grid_a.size() ||
+        drift_cells.size() != o.drift_cells.size())
       return false;
     for (size_t i = 0; i < grid_a.size(); ++i)
       if (std::memcmp(&grid_a[i], &o.grid_a[i], sizeof(double)) != 0) return false;
+    for (size_t i = 0; i < drift_cells.size(); ++i)
+      if (std::memcmp(&drift_cells[i], &o.drift_cells[i], sizeof(double)) != 0) return false;
     return true;
   }
 };
@@ -316,6 +321,7 @@ struct TimingRec {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
   double total_ms = 0;
   int64_t launches = 0;
+  int64_t work[3] = {0, 0, 0};   // particle-updates with a drift, kick-only updates, mesh cells read
 };
 
 }  // namespace
@@ -348,7 +354,6 @@ struct fdf_ctx {
   hipStream_t cap_stream = nullptr;   // private stream used only for graph capture
   hipStream_t launch_stream = nullptr;  // stream kernels are enqueued on right now
   std::vector<GraphRec> graphs;       // captured step sequences
-  double drift_cells = 0;   // typical drift since the last sort, in cells
   bool sorted_once = false;
   std::string err;
   bool timing = false;
@@ -400,6 +405,14 @@ void timing_end(fdf_ctx* c, int cls, std::pair<hipEvent_t, hipEvent_t>& ev) {
   (void)hipEventRecord(ev.second, c->stream);
   c->tim[cls].pending.push_back(ev);
   c->tim[cls].launches++;
+}
+
+// Work done by the launches of a timed class (counted while timing is on).
+void timing_work(fdf_ctx* c, int cls, int64_t updates_drift, int64_t updates_kick, int64_t mesh_cells) {
+  if (!c->timing || c->launch_stream) return;
+  c->tim[cls].work[0] += updates_drift;
+  c->tim[cls].work[1] += updates_kick;
+  c->tim[cls].work[2] += mesh_cells;
 }
 
 void timing_collect(fdf_ctx* c) {
@@ -562,15 +575,20 @@ int sort_tiles_of(fdf_ctx* c) {
   return std::min(t, tmax);
 }
 
-// Drift of a mean-momentum particle (|q| = 3.151 T) of the fastest species
-// over one drift of length dt at a, in mesh cells: the adaptive sort cadence.
-double typical_drift_cells(fdf_ctx* c, double dt, double a) {
+// Drift of a mean-momentum particle (|q| = 3.151 T) of mass m over one drift
+// of length dt at a, in mesh cells: the adaptive sort cadence of a species.
+double typical_drift_cells(fdf_ctx* c, double dt, double a, double m) {
   const double q = 3.151374 * t_nu_ev();
-  double mmin = 1e300;
-  for (auto& s : c->species) mmin = std::min(mmin, s.m);
-  const double v = q / std::sqrt(q * q + mmin * mmin * a * a);
+  const double v = q / std::sqrt(q * q + m * m * a * a);
   return std::fabs(dt) * v * c->cfg.grid_n / c->cfg.box_mpc;
 }
+
+// Species sort on their own cadence (a mask of up to 64 species); more
+// species than that all sort together, at the cadence of the fastest.
+bool per_species_sorting(const fdf_ctx* c) { return c->species.size() <= 64; }
+
+// Prediction of a re-sort: order by x + v tau at scale factor a_mid.
+struct SortPrediction { double tau = 0, a_mid = 0; };
 
 // Spatial re-sort of every species into its other buffer copy, ordered by
 // the positions extrapolated by predict_tau at scale factor a_pred.
@@ -599,11 +617,14 @@ SortArgs sort_args(fdf_ctx* c, const SpeciesRec& s, double predict_tau, double a
 // alone and is sampled again, by id, into the sorted slots (the same values
 // as moving the whole state from the random sampling order, at a fraction of
 // the scattered writes).
-int sort_species(fdf_ctx* c, double predict_tau, double a_pred, bool resample) {
+int sort_species(fdf_ctx* c, const std::vector<SortPrediction>& pred, const std::vector<char>& due,
+                 bool resample) {
   std::pair<hipEvent_t, hipEvent_t> ev;
   timing_begin(c, FDF_KERNEL_SORT, &ev);
-  for (auto& s : c->species) {
-    SortArgs a = sort_args(c, s, predict_tau, a_pred);
+  for (size_t i = 0; i < c->species.size(); ++i) {
+    if (!due[i]) continue;
+    SpeciesRec& s = c->species[i];
+    SortArgs a = sort_args(c, s, pred[i].tau, pred[i].a_mid);
     a.id_only = resample && s.pristine;
     launch_sort(a, stream_of(c));
     if (a.id_only) {
@@ -627,10 +648,12 @@ int sort_species(fdf_ctx* c, double predict_tau, double a_pred, bool resample) {
 // the other copy (pa describes the step's push; its segment tables are
 // indexed per species here).  The rank passes are timed as sorting, the
 // pushes on their own.
-int sort_push_species(fdf_ctx* c, double predict_tau, double a_pred, const PushArgs& pa, size_t table) {
+int sort_push_species(fdf_ctx* c, const std::vector<SortPrediction>& pred, const std::vector<char>& due,
+                      const PushArgs& pa, size_t table) {
   for (size_t i = 0; i < c->species.size(); ++i) {
+    if (!due[i]) continue;
     SpeciesRec& s = c->species[i];
-    const SortArgs a = sort_args(c, s, predict_tau, a_pred);
+    const SortArgs a = sort_args(c, s, pred[i].tau, pred[i].a_mid);
     std::pair<hipEvent_t, hipEvent_t> ev;
     timing_begin(c, FDF_KERNEL_SORT, &ev);
     launch_sort_rank(a, stream_of(c));
@@ -638,6 +661,7 @@ int sort_push_species(fdf_ctx* c, double predict_tau, double a_pred, const PushA
     PushArgs p = pa;
     p.seg = (const Segment*)(c->ws + c->lay.seg + s.cur * table) + i;
     p.dseg = (const Segment*)(c->ws + c->lay.seg + (s.cur ^ 1) * table) + i;
+    p.alt_mask = p.skip_mask = 0;
     p.nseg = 1;
     p.total_chunks = (s.n + kSortBlock - 1) / kSortBlock;
     p.persistent = 0;
@@ -649,6 +673,8 @@ int sort_push_species(fdf_ctx* c, double predict_tau, double a_pred, const PushA
     timing_begin(c, FDF_KERNEL_PUSH_SORT, &ev);
     launch_push_sort(p, stream_of(c));
     timing_end(c, FDF_KERNEL_PUSH_SORT, ev);
+    timing_work(c, FDF_KERNEL_PUSH_SORT, s.n, 0, (int64_t)c->cfg.grid_n * c->cfg.grid_n * c->cfg.grid_n *
+                                                 (pa.blend ? 2 : 1));
     s.cur ^= 1;
   }
   return launched(c, "sort + push");
@@ -886,7 +912,6 @@ int fdf_reset(fdf_ctx* c) {
   c->stepped = false;
   c->seg_dirty = true;
   c->have_density = false;
-  c->drift_cells = 0;
   c->sorted_once = false;
   return FDF_OK;
 }
@@ -1061,14 +1086,35 @@ int enqueue_steps(fdf_ctx* c, int32_t n) {
   pa.eom = c->cfg.eom;
   pa.tsc = c->cfg.interp_order == 2;
   pa.lds_reserve = push_lds_reserve(c->push_waves);
-  // does the launch at integer time u re-sort first?
-  auto sort_due = [&](int u) {
-    if (c->sort_cells > 0) return !c->sorted_once || c->drift_cells >= c->sort_cells;
-    return sort_every > 0 && u % sort_every == 0;
+  // The species the launch at integer time u re-sorts first.  Adaptive
+  // cadence: each species once its own typical drift since its last sort
+  // reaches sort_cells (all of them at the first sort, and all together when
+  // there are too many species for the per-species masks); fixed cadence:
+  // every sort_every steps.
+  const size_t ns = c->species.size();
+  double m_fast = 1e300;
+  for (auto& sp : c->species) m_fast = std::min(m_fast, sp.m);
+  auto cadence_mass = [&](size_t i) { return per_species_sorting(c) ? c->species[i].m : m_fast; };
+  auto sorts_due = [&](int u, std::vector<char>* due) {
+    bool any = false;
+    for (size_t i = 0; i < ns; ++i) {
+      bool d;
+      if (c->sort_cells > 0) {
+        const double dc = per_species_sorting(c) ? c->species[i].drift_cells : c->species[0].drift_cells;
+        d = !c->sorted_once || dc >= c->sort_cells;
+      } else {
+        d = sort_every > 0 && u % sort_every == 0;
+      }
+      (*due)[i] = d;
+      any = any || d;
+    }
+    if (any && !per_species_sorting(c)) std::fill(due->begin(), due->end(), 1);
+    return any;
   };
-  // the interval until the next re-sort after one at u (as the cadence will
-  // decide it): half its conformal time and the scale factor at its middle
-  auto sort_prediction = [&](int u0, double* tau, double* amid) {
+  // the interval until the species' next re-sort after one at u0 (as the
+  // cadence will decide it): half its conformal time and the scale factor at
+  // its middle
+  auto sort_prediction = [&](int u0, double m) {
     double span = 0.0, cells = 0.0;
     int steps = 0;
     std::vector<std::pair<double, double>> iv;   // (drift, a) of the steps in the interval
@@ -1079,19 +1125,23 @@ int enqueue_steps(fdf_ctx* c, int32_t n) {
       const double ah = fwd ? c->a_half[u] : c->a_half[u - 1];
       iv.push_back({dr, ah});
       span += dr;
-      cells += typical_drift_cells(c, dr, ah);
+      cells += typical_drift_cells(c, dr, ah, m);
       ++steps;
       if (c->sort_cells > 0 ? cells >= c->sort_cells : steps >= std::max(sort_every, 1)) break;
     }
+    SortPrediction p;
+    p.a_mid = c->a[u0];
     double half = 0.0;
-    *amid = c->a[u0];
     for (const auto& e : iv) {
-      if (std::fabs(half + e.first) > 0.5 * std::fabs(span)) { *amid = e.second; break; }
+      if (std::fabs(half + e.first) > 0.5 * std::fabs(span)) { p.a_mid = e.second; break; }
       half += e.first;
-      *amid = e.second;
+      p.a_mid = e.second;
     }
-    *tau = c->sort_predict ? 0.5 * span : 0.0;
+    p.tau = c->sort_predict ? 0.5 * span : 0.0;
+    return p;
   };
+  std::vector<char> due(ns, 0);
+  std::vector<SortPrediction> pred(ns);
   for (int j = 0; j <= nabs; ++j) {
     int t;            // integer time of this launch's kick
     double kclose = 0, kopen = 0, drift = 0, a_drift = 0;   // half-kicks ending / starting at t
@@ -1148,41 +1198,65 @@ int enqueue_steps(fdf_ctx* c, int32_t n) {
         }
       }
     }
-    bool fused_sort = false;    // this step's push also performs the re-sort
-    double tau_pred = 0.0, a_mid = 0.0;
+    bool fused_sort = false;    // this step's push also performs the re-sort of the due species
+    std::fill(due.begin(), due.end(), 0);
     if (j < nabs) {
-      if (sort_due(t)) {
-        sort_prediction(t, &tau_pred, &a_mid);
+      if (sorts_due(t, &due)) {
+        for (size_t i = 0; i < ns; ++i)
+          if (due[i]) pred[i] = sort_prediction(t, cadence_mass(i));
         // the first sort takes two passes (the second orders cells in buckets)
         const int passes = c->sorted_once ? 1 : 2;
         fused_sort = c->sort_fused && !pa.fp64 && pa.eom == FDF_EOM_SEPARABLE;
         for (int pass = 0; pass < passes - (fused_sort ? 1 : 0) && !rc; ++pass)
-          rc = sort_species(c, tau_pred, a_mid, pass == 0);
+          rc = sort_species(c, pred, due, pass == 0);
         if (rc) return rc;
         c->sorted_once = true;
-        c->drift_cells = 0;
+        for (size_t i = 0; i < ns; ++i)
+          if (due[i]) c->species[i].drift_cells = 0;
       }
-      c->drift_cells += typical_drift_cells(c, drift, a_drift);
+      for (size_t i = 0; i < ns; ++i)
+        c->species[i].drift_cells += typical_drift_cells(c, drift, a_drift, cadence_mass(i));
     }
-    pa.seg = (const Segment*)(c->ws + c->lay.seg + c->species[0].cur * table);
+    // each species' state sits in its own copy: table 0 or 1 per species
+    pa.seg = (const Segment*)(c->ws + c->lay.seg);
+    pa.seg_alt = (const Segment*)(c->ws + c->lay.seg + table);
+    pa.alt_mask = 0;
+    pa.skip_mask = 0;
+    if (per_species_sorting(c)) {
+      for (size_t i = 0; i < ns; ++i) if (c->species[i].cur) pa.alt_mask |= 1ull << i;
+    } else {
+      pa.seg = (const Segment*)(c->ws + c->lay.seg + c->species[0].cur * table);
+    }
     pa.kick = kick;
     pa.kick_open = pa.eom == FDF_EOM_SEPARABLE ? 0.0 : kopen;
     pa.a_kick = a_kick;
     pa.do_drift = j < nabs;
     pa.drift = drift;
     pa.a_drift = a_drift;
+    int64_t pushed = 0;           // particles of the plain launch, and the meshes it reads
+    std::vector<char> mesh_read(c->fields.size(), 0);
     if (fused_sort) {
-      rc = sort_push_species(c, tau_pred, a_mid, pa, table);
+      rc = sort_push_species(c, pred, due, pa, table);
       if (rc) return rc;
-      for (auto& s : c->species) s.pristine = false;
-      continue;
+      for (size_t i = 0; i < ns; ++i) if (due[i]) pa.skip_mask |= 1ull << i;   // pushed already
     }
-    std::pair<hipEvent_t, hipEvent_t> ev;
-    timing_begin(c, FDF_KERNEL_PUSH, &ev);
-    launch_push(pa, stream_of(c));
-    timing_end(c, FDF_KERNEL_PUSH, ev);
-    rc = launched(c, "push");
-    if (rc) return rc;
+    for (size_t i = 0; i < ns; ++i) {
+      if (fused_sort && due[i]) continue;
+      pushed += c->species[i].n;
+      mesh_read[c->species[i].field] = 1;
+    }
+    if (pushed > 0) {
+      std::pair<hipEvent_t, hipEvent_t> ev;
+      timing_begin(c, FDF_KERNEL_PUSH, &ev);
+      launch_push(pa, stream_of(c));
+      timing_end(c, FDF_KERNEL_PUSH, ev);
+      int64_t meshes = 0;
+      for (char r : mesh_read) meshes += r;
+      timing_work(c, FDF_KERNEL_PUSH, pa.do_drift ? pushed : 0, pa.do_drift ? 0 : pushed,
+                  meshes * (int64_t)c->cfg.grid_n * c->cfg.grid_n * c->cfg.grid_n * (pa.blend ? 2 : 1));
+      rc = launched(c, "push");
+      if (rc) return rc;
+    }
     for (auto& s : c->species) s.pristine = false;
   }
   c->step_index = k0 + n;
@@ -1208,10 +1282,12 @@ std::vector<double> layout_signature(fdf_ctx* c) {
 HostStepState host_state(fdf_ctx* c) {
   HostStepState h;
   h.step_index = c->step_index;
-  h.cur = c->species.empty() ? 0 : c->species[0].cur;
   h.sorted_once = c->sorted_once;
-  h.drift_cells = c->drift_cells;
-  for (auto& s : c->species) h.pristine.push_back(s.pristine ? 1 : 0);
+  for (auto& s : c->species) {
+    h.cur.push_back(s.cur);
+    h.drift_cells.push_back(s.drift_cells);
+    h.pristine.push_back(s.pristine ? 1 : 0);
+  }
   for (auto& f : c->fields) {
     h.grid_a.push_back(f.has_grid ? f.grid_a : NAN);
     h.tags.push_back(f.tag[0]);
@@ -1222,10 +1298,12 @@ HostStepState host_state(fdf_ctx* c) {
 
 void apply_state(fdf_ctx* c, const HostStepState& h) {
   c->step_index = h.step_index;
-  for (auto& s : c->species) s.cur = h.cur;
   c->sorted_once = h.sorted_once;
-  c->drift_cells = h.drift_cells;
-  for (size_t i = 0; i < c->species.size() && i < h.pristine.size(); ++i) c->species[i].pristine = h.pristine[i];
+  for (size_t i = 0; i < c->species.size() && i < h.cur.size(); ++i) {
+    c->species[i].cur = h.cur[i];
+    c->species[i].drift_cells = h.drift_cells[i];
+    c->species[i].pristine = h.pristine[i];
+  }
   for (size_t i = 0; i < c->fields.size() && i < h.grid_a.size(); ++i) {
     c->fields[i].has_grid = !std::isnan(h.grid_a[i]);
     c->fields[i].grid_a = h.grid_a[i];
@@ -1761,7 +1839,14 @@ int fdf_read_timing(fdf_ctx* c, int32_t cls, double* ms, int64_t* launches) {
 int fdf_timing_reset(fdf_ctx* c) {
   if (!c) return FDF_ERR_ARG;
   timing_collect(c);
-  for (auto& t : c->tim) { t.total_ms = 0; t.launches = 0; }
+  for (auto& t : c->tim) { t.total_ms = 0; t.launches = 0; t.work[0] = t.work[1] = t.work[2] = 0; }
+  return FDF_OK;
+}
+
+int fdf_read_work(fdf_ctx* c, int32_t cls, int64_t* work) {
+  if (!c || !work) return FDF_ERR_ARG;
+  if (cls < 0 || cls >= FDF_KERNEL_COUNT) return fail(c, FDF_ERR_ARG, "bad kernel class");
+  for (int k = 0; k < 3; ++k) work[k] = c->tim[cls].work[k];
   return FDF_OK;
 }
 

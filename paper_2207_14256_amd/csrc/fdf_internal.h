@@ -100,7 +100,10 @@ struct Segment {
 };
 
 struct PushArgs {
-  const Segment* seg;      // device array
+  const Segment* seg;      // device array: each species' segment in copy 0 of its state
+  const Segment* seg_alt;  // the same in copy 1 (the other buffer of a sorting species)
+  uint64_t alt_mask;       // species whose current state is in copy 1 (species index < 64)
+  uint64_t skip_mask;      // species this launch leaves alone (pushed by a fused re-sort)
   int32_t nseg;
   int64_t total_chunks;
   int32_t fp64;

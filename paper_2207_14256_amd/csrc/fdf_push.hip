@@ -170,8 +170,9 @@ __device__ __forceinline__ void update_f32(const ConstF32& k, bool drift, uint32
 
 template <int NSLOT, int PPT, bool BLEND, bool TSC, bool OFF32>
 __device__ __forceinline__ void push_chunk_f32(const PushArgs& a, int64_t chunk) {
-  const int s = find_segment(a.seg, a.nseg, chunk);
-  const Segment& sg = a.seg[s];
+  bool skip;
+  const Segment& sg = chunk_segment(a, chunk, &skip);
+  if (skip) return;
   const int64_t first = (chunk - sg.chunk_begin) * (int64_t)(kBlock * PPT) + threadIdx.x;
   // chunk-relative arrays: a uniform base and a 32-bit lane index
   const int64_t c0 = first - threadIdx.x;
@@ -357,8 +358,9 @@ template <int NSLOT, int PPT, bool BLEND, bool TSC, bool OFF32>
 __device__ __forceinline__ void push_chunk_f64(const PushArgs& a, int64_t chunk) {
 #pragma clang fp contract(off)
   constexpr int NP = Stencil<TSC>::N;
-  const int s = find_segment(a.seg, a.nseg, chunk);
-  const Segment& sg = a.seg[s];
+  bool skip;
+  const Segment& sg = chunk_segment(a, chunk, &skip);
+  if (skip) return;
   const int64_t n = sg.n;
   const int64_t first = (chunk - sg.chunk_begin) * (int64_t)(kBlock * PPT) + threadIdx.x;
   const int gm = a.G - 1;

@@ -25,6 +25,16 @@ __device__ __forceinline__ int find_segment(const Segment* seg, int nseg, int64_
   return s;
 }
 
+// The segment of a chunk in the copy that holds its species' current state
+// (both copies list the same chunk ranges); *skip: the species is left alone
+// by this launch.
+__device__ __forceinline__ const Segment& chunk_segment(const PushArgs& a, int64_t chunk, bool* skip) {
+  const int s = find_segment(a.seg, a.nseg, chunk);
+  const bool low = s < 64;
+  *skip = low && ((a.skip_mask >> s) & 1ull);
+  return (low && ((a.alt_mask >> s) & 1ull)) ? a.seg_alt[s] : a.seg[s];
+}
+
 // The state arrays live in device global memory.  Their pointers come from a
 // device-side segment table, so the compiler cannot infer the address space
 // and would emit flat instructions; naming the global space gives global

@@ -135,8 +135,9 @@ template <int NSLOT, int PPT, bool BLEND, bool TSC>
 __device__ __forceinline__ void push_chunk_eom_f32(const PushArgs& a, int64_t chunk) {
 #pragma clang fp contract(off)
   constexpr int NP = Stencil<TSC>::N;
-  const int s = find_segment(a.seg, a.nseg, chunk);
-  const Segment& sg = a.seg[s];
+  bool skip;
+  const Segment& sg = chunk_segment(a, chunk, &skip);
+  if (skip) return;
   const int64_t n = sg.n;
   const int64_t first = (chunk - sg.chunk_begin) * (int64_t)(kBlock * PPT) + threadIdx.x;
   const int shift = 32 - a.log2g;
@@ -210,8 +211,9 @@ template <int NSLOT, int PPT, bool BLEND, bool TSC>
 __device__ __forceinline__ void push_chunk_eom_f64(const PushArgs& a, int64_t chunk) {
 #pragma clang fp contract(off)
   constexpr int NP = Stencil<TSC>::N;
-  const int s = find_segment(a.seg, a.nseg, chunk);
-  const Segment& sg = a.seg[s];
+  bool skip;
+  const Segment& sg = chunk_segment(a, chunk, &skip);
+  if (skip) return;
   const int64_t n = sg.n;
   const int64_t first = (chunk - sg.chunk_begin) * (int64_t)(kBlock * PPT) + threadIdx.x;
   const int gm = a.G - 1;

@@ -32,7 +32,7 @@ EXPORTS = [
     "fdf_read_state", "fdf_read_grid", "fdf_read_field", "fdf_read_density",
     "fdf_read_schedule", "fdf_get_info", "fdf_sync", "fdf_timing_enable",
     "fdf_read_timing", "fdf_timing_reset", "fdf_status_string", "fdf_last_error",
-    "fdf_get_tuning", "fdf_set_tuning", "fdf_power_spectrum_noalloc",
+    "fdf_get_tuning", "fdf_set_tuning", "fdf_power_spectrum_noalloc", "fdf_read_work",
 ]
 
 
@@ -49,6 +49,7 @@ class Config(ctypes.Structure):
         ("sort_every", ctypes.c_int32), ("max_fields", ctypes.c_int32),
         ("max_species", ctypes.c_int32), ("interp_order", ctypes.c_int32),
         ("max_particles", ctypes.c_int64), ("superstep_tol", ctypes.c_double),
+        ("pad_mesh", ctypes.c_int32),
     ]
 
 
@@ -117,6 +118,7 @@ def load():
         "fdf_sync": [P], "fdf_timing_enable": [P, I32],
         "fdf_read_timing": [P, I32, PD, ctypes.POINTER(I64)],
         "fdf_timing_reset": [P],
+        "fdf_read_work": [P, I32, ctypes.POINTER(I64)],
         "fdf_get_tuning": [P, ctypes.POINTER(Tuning)],
         "fdf_set_tuning": [P, ctypes.POINTER(Tuning)],
     }
@@ -158,6 +160,7 @@ def make_config(cfg):
     c.max_species = int(cfg.get("max_species", len(cfg["species"])))
     c.max_particles = int(cfg.get("max_particles", n_particles))
     c.superstep_tol = float(cfg.get("superstep_tol", 0.0))
+    c.pad_mesh = int(bool(cfg.get("pad_mesh", False)))
     c.eom = EOMS[cfg.get("eom", "separable")]
     c.interp_order = int(cfg.get("interp_order", 1))
     return c
@@ -389,6 +392,13 @@ class Context:
         self._check(self.lib.fdf_read_timing(self.ctx, cls, ctypes.byref(ms), ctypes.byref(n)),
                     "fdf_read_timing")
         return ms.value, n.value
+
+    def read_work(self, kernel_class):
+        """(particle-updates with a drift, kick-only updates, mesh cells read)
+        of the timed launches of a kernel class."""
+        w = (ctypes.c_int64 * 3)()
+        self._check(self.lib.fdf_read_work(self.ctx, KERNEL_CLASSES[kernel_class], w), "fdf_read_work")
+        return int(w[0]), int(w[1]), int(w[2])
 
     def timing_reset(self):
         self._check(self.lib.fdf_timing_reset(self.ctx), "fdf_timing_reset")

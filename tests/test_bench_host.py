@@ -12,12 +12,15 @@ N3 = 512 ** 3
 
 
 def test_push_bytes_c3():
-    # FP32, psi != phi, phi-dot = 0: 8 bf16 slots stored, 6 carry data
+    # FP32, psi != phi, phi-dot = 0: 6 bf16 slots (12-byte cells), all data
     cfg = workloads.preset("c3")
-    assert bench.mesh_slots(cfg) == (8, 6)
+    assert bench.mesh_slots(cfg) == (6, 6)
     assert bench.bytes_per_launch(cfg, N3, True) == N3 * (36 + 24) + N3 * 6 * 2
     assert bench.bytes_per_launch(cfg, N3, False) == N3 * (36 + 12) + N3 * 6 * 2
     assert bench.bytes_per_push_sort(cfg, N3) == N3 * 92 + N3 * 6 * 2
+    assert bench.mesh_padding_bytes(cfg) == 0
+    cfg = workloads.preset("c3", pad_mesh=True)       # 16-byte cells: 8 stored, 6 data
+    assert bench.mesh_slots(cfg) == (8, 6)
     assert bench.mesh_padding_bytes(cfg) == N3 * 2 * 2
 
 

@@ -156,3 +156,65 @@ def test_launch_shape_invariance_other_eoms(eom):
         got = _state_by_id(cfg, dict(sort_every=4, particles_per_thread=ppt, push_waves=waves))
         for i, (a, b) in enumerate(zip(ref, got)):
             assert np.array_equal(a, b), (eom, ppt, waves, i)
+
+
+@pytest.mark.parametrize("prec,fused", [("fp32", 1), ("fp32", 0), ("fp64", 0)])
+def test_per_species_cadence_bit_identical(prec, fused):
+    """Species of different masses re-sort on their own adaptive cadence (the
+    light species far more often), in split calls, graph replay and a
+    backward walk: every species' state by id equals the never-sorted run's."""
+    print("[gpu-case] per-species cadence %s fused=%d" % (prec, fused), flush=True)
+    cfg = workloads.small("c4", grid_n=32, n_side=0, n_steps=80, precision=prec, box_mpc=768.0,
+                          z_begin=1e9, z_end=31.0, sort_every=1, sort_cells=0.0)
+    cfg["fields"] = [1004, 1104]
+    cfg["species"] = [dict(field=0, m=0.005, n_side=11, seed=2040),
+                      dict(field=0, m=0.0502, n_side=17, seed=2042),
+                      dict(field=1, m=0.05, n_side=9, seed=2044)]
+    ref = _state_by_id(dict(cfg, sort_every=0), dict(sort_every=0))
+    base = dict(sort_every=1, sort_cells=0.7, sort_fused=fused)
+    for tuning, steps, back in ((base, None, 0), (dict(base, use_graph=1), None, 0),
+                                (dict(base, particles_per_thread=1), None, 0)):
+        got = _state_by_id(cfg, tuning, steps, back)
+        for a, b in zip(got, ref):
+            assert np.array_equal(a, b), tuning
+    # split calls and a walk back to the middle
+    ctx, fields, species = fastdf.setup_workload(cfg, tuning=base)
+    for k in (13, 29, 38):
+        ctx.step(k)
+    ctx.step(-40)
+    mid = []
+    for s in species:
+        x, q = ctx.read_state(s)
+        mid += [x, q]
+    ctx.close()
+    ref_mid = _state_by_id(dict(cfg, sort_every=0), dict(sort_every=0), steps=40)
+    ref_mid = [v for i, v in enumerate(ref_mid) if i % 3 != 2]
+    L = cfg["box_mpc"]
+    for i, (a, b) in enumerate(zip(mid, ref_mid)):
+        if i % 2 == 0:
+            assert np.max(np.abs((a - b + L / 2) % L - L / 2)) < 1e-6 * L   # ids stay aligned
+        else:
+            assert np.max(np.abs(a - b)) <= 1e-5 * np.max(np.abs(b))
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_padded_mesh_bit_identical(order):
+    """12-byte bfloat16 cells (the default) hold the same six gradient values
+    as the 16-byte cells with a zero slot and a pad (pad_mesh): every particle's state,
+    its weight and the spectra come out bit for bit the same, with plain and
+    fused re-sorts and with CIC or TSC gathers."""
+    print("[gpu-case] padded mesh order %d" % order, flush=True)
+    cfg = workloads.small("c3", grid_n=32, n_side=30, n_steps=200, z_begin=1e9, z_end=3.0,
+                          sort_every=4, sort_cells=0.0, interp_order=order)
+    out = []
+    for pad in (False, True):
+        ctx, fields, species = fastdf.setup_workload(dict(cfg, pad_mesh=pad))
+        ctx.step(cfg["n_steps"])
+        x, q = ctx.read_state(species[0])
+        w = ctx.weights(species[0]).cpu().numpy()
+        g = ctx.read_grid(fields[0], 4)
+        k, p, nm = ctx.power_spectrum(species, 16)
+        ctx.close()
+        out.append((x, q, w, g, p))
+    for a, b in zip(*out):
+        assert np.array_equal(a, b, equal_nan=True)
