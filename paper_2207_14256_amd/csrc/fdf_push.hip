@@ -54,30 +54,34 @@ __device__ __forceinline__ V load_cell(const void* grid, uint32_t cell) {
   }
 }
 
+// g += w * (the slots of one cell), slot by slot.
+template <int NSLOT, typename V>
+__device__ __forceinline__ void accum_cell_bf16(float w, const V& v, float* g) {
+#pragma clang fp contract(off)
+  if constexpr (NSLOT == 8) {
+    g[0] = fmaf(w, bf16_lo(v.x), g[0]); g[1] = fmaf(w, bf16_hi(v.x), g[1]);
+    g[2] = fmaf(w, bf16_lo(v.y), g[2]); g[3] = fmaf(w, bf16_hi(v.y), g[3]);
+    g[4] = fmaf(w, bf16_lo(v.z), g[4]); g[5] = fmaf(w, bf16_hi(v.z), g[5]);
+    g[6] = fmaf(w, bf16_lo(v.w), g[6]);
+  } else if constexpr (NSLOT == 6) {
+    g[0] = fmaf(w, bf16_lo(v.x), g[0]); g[1] = fmaf(w, bf16_hi(v.x), g[1]);
+    g[2] = fmaf(w, bf16_lo(v.y), g[2]); g[3] = fmaf(w, bf16_hi(v.y), g[3]);
+    g[4] = fmaf(w, bf16_lo(v.z), g[4]); g[5] = fmaf(w, bf16_hi(v.z), g[5]);
+  } else {
+    g[0] = fmaf(w, bf16_lo(v.x), g[0]); g[1] = fmaf(w, bf16_hi(v.x), g[1]);
+    g[2] = fmaf(w, bf16_lo(v.y), g[2]); g[6] = fmaf(w, bf16_hi(v.y), g[6]);
+  }
+}
+
 template <int NSLOT, int NPT, bool OFF32>
 __device__ __forceinline__ void gather_bf16(const void* grid, const uint32_t* cell, const float* w,
                                             float* g /* 7, accumulated */) {
-#pragma clang fp contract(off)
   using V = typename CellType<NSLOT>::T;
   V v[NPT];
 #pragma unroll
   for (int c = 0; c < NPT; ++c) v[c] = load_cell<V, OFF32>(grid, cell[c]);
 #pragma unroll
-  for (int c = 0; c < NPT; ++c) {
-    if constexpr (NSLOT == 8) {
-      g[0] = fmaf(w[c], bf16_lo(v[c].x), g[0]); g[1] = fmaf(w[c], bf16_hi(v[c].x), g[1]);
-      g[2] = fmaf(w[c], bf16_lo(v[c].y), g[2]); g[3] = fmaf(w[c], bf16_hi(v[c].y), g[3]);
-      g[4] = fmaf(w[c], bf16_lo(v[c].z), g[4]); g[5] = fmaf(w[c], bf16_hi(v[c].z), g[5]);
-      g[6] = fmaf(w[c], bf16_lo(v[c].w), g[6]);
-    } else if constexpr (NSLOT == 6) {
-      g[0] = fmaf(w[c], bf16_lo(v[c].x), g[0]); g[1] = fmaf(w[c], bf16_hi(v[c].x), g[1]);
-      g[2] = fmaf(w[c], bf16_lo(v[c].y), g[2]); g[3] = fmaf(w[c], bf16_hi(v[c].y), g[3]);
-      g[4] = fmaf(w[c], bf16_lo(v[c].z), g[4]); g[5] = fmaf(w[c], bf16_hi(v[c].z), g[5]);
-    } else {
-      g[0] = fmaf(w[c], bf16_lo(v[c].x), g[0]); g[1] = fmaf(w[c], bf16_hi(v[c].x), g[1]);
-      g[2] = fmaf(w[c], bf16_lo(v[c].y), g[2]); g[6] = fmaf(w[c], bf16_hi(v[c].y), g[6]);
-    }
-  }
+  for (int c = 0; c < NPT; ++c) accum_cell_bf16<NSLOT>(w[c], v[c], g);
 }
 
 // Gather over a whole stencil: CIC in one batch of 8 loads, TSC in three
@@ -121,29 +125,11 @@ __device__ __forceinline__ ConstF32 const_f32(const PushArgs& a, const Segment& 
   return k;
 }
 
-// The FP32 update of one particle: gather, separable kick into dq, drift of
-// the fixed-point position.  Every floating-point operation is written out
-// (explicit fmaf, no contraction) so that every copy of this code is
-// instruction-identical: a particle gets bit-identical results in whichever
-// slot of whichever block, and whichever kernel, it is updated.
-template <int NSLOT, bool BLEND, bool TSC, bool OFF32>
-__device__ __forceinline__ void update_f32(const ConstF32& k, bool drift, uint32_t* xu, const float* q0,
-                                           float* dq) {
+// The kick and drift of one particle from its interpolated mesh values g.
+template <int NSLOT>
+__device__ __forceinline__ void kick_drift_f32(const ConstF32& k, bool drift, float* g, uint32_t* xu,
+                                               const float* q0, float* dq) {
 #pragma clang fp contract(off)
-  constexpr int NP = Stencil<TSC>::N;
-  uint32_t cell[NP];
-  float w[NP];
-  stencil_u32<TSC>(xu, k.shift, k.gmask, k.finv, k.G, cell, w);
-  float g[7] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-  if (BLEND) {   // super-steps: (1 - t) G_A + t G_B folded into the weights
-    float wa[NP], wb[NP];
-#pragma unroll
-    for (int cc = 0; cc < NP; ++cc) { wa[cc] = k.ta * w[cc]; wb[cc] = k.tb * w[cc]; }
-    gather_stencil_bf16<NSLOT, TSC, OFF32>(k.gridA, cell, wa, g);
-    gather_stencil_bf16<NSLOT, TSC, OFF32>(k.gridB, cell, wb, g);
-  } else {
-    gather_stencil_bf16<NSLOT, TSC, OFF32>(k.gridA, cell, w, g);
-  }
   if (NSLOT == 4) { g[3] = g[0]; g[4] = g[1]; g[5] = g[2]; }
   // separable force of eq. releq_approx
   const float q0sq = fmaf(q0[0], q0[0], fmaf(q0[1], q0[1], q0[2] * q0[2]));
@@ -168,6 +154,62 @@ __device__ __forceinline__ void update_f32(const ConstF32& k, bool drift, uint32
   }
 }
 
+// The FP32 update of one particle: gather, separable kick into dq, drift of
+// the fixed-point position.  Every floating-point operation is written out
+// (explicit fmaf, no contraction) so that every copy of this code is
+// instruction-identical: a particle gets bit-identical results in whichever
+// slot of whichever block, and whichever kernel, it is updated.
+template <int NSLOT, bool BLEND, bool TSC, bool OFF32>
+__device__ __forceinline__ void update_f32(const ConstF32& k, bool drift, uint32_t* xu, const float* q0,
+                                           float* dq) {
+#pragma clang fp contract(off)
+  constexpr int NP = Stencil<TSC>::N;
+  uint32_t cell[NP];
+  float w[NP];
+  stencil_u32<TSC>(xu, k.shift, k.gmask, k.finv, k.G, cell, w);
+  float g[7] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+  if (BLEND) {   // super-steps: (1 - t) G_A + t G_B folded into the weights
+    float wa[NP], wb[NP];
+#pragma unroll
+    for (int cc = 0; cc < NP; ++cc) { wa[cc] = k.ta * w[cc]; wb[cc] = k.tb * w[cc]; }
+    gather_stencil_bf16<NSLOT, TSC, OFF32>(k.gridA, cell, wa, g);
+    gather_stencil_bf16<NSLOT, TSC, OFF32>(k.gridB, cell, wb, g);
+  } else {
+    gather_stencil_bf16<NSLOT, TSC, OFF32>(k.gridA, cell, w, g);
+  }
+  kick_drift_f32<NSLOT>(k, drift, g, xu, q0, dq);
+}
+
+// The CIC update of GRP particles at once: all their gathers are issued
+// before any is consumed, so GRP corner sets are in flight together instead
+// of one particle's at a time.  Each particle's arithmetic is the same, in the
+// same order, as update_f32's.
+template <int NSLOT, int GRP, bool OFF32>
+__device__ __forceinline__ void update_group_f32(const ConstF32& k, bool drift, uint32_t (*xu)[3],
+                                                 const float (*q0)[3], float (*dq)[3]) {
+#pragma clang fp contract(off)
+  using V = typename CellType<NSLOT>::T;
+  uint32_t cell[GRP][8];
+  float w[GRP][8];
+#pragma unroll
+  for (int p = 0; p < GRP; ++p) stencil_u32<false>(xu[p], k.shift, k.gmask, k.finv, k.G, cell[p], w[p]);
+  V v[GRP][8];
+#pragma unroll
+  for (int p = 0; p < GRP; ++p)
+#pragma unroll
+    for (int c = 0; c < 8; ++c) v[p][c] = load_cell<V, OFF32>(k.gridA, cell[p][c]);
+#pragma unroll
+  for (int p = 0; p < GRP; ++p) {
+    float g[7] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int c = 0; c < 8; ++c) accum_cell_bf16<NSLOT>(w[p][c], v[p][c], g);
+    kick_drift_f32<NSLOT>(k, drift, g, xu[p], q0[p], dq[p]);
+  }
+}
+
+// Particles per gather group of a PPT-particle thread.
+template <int PPT> struct GatherGroup { static constexpr int N = PPT < 4 ? PPT : 4; };
+
 template <int NSLOT, int PPT, bool BLEND, bool TSC, bool OFF32>
 __device__ __forceinline__ void push_chunk_f32(const PushArgs& a, int64_t chunk) {
   bool skip;
@@ -184,14 +226,16 @@ __device__ __forceinline__ void push_chunk_f32(const PushArgs& a, int64_t chunk)
   for (int d = 0; d < 3; ++d) { X[d] = sg.xu[d] + c0; Q0[d] = sg.q0f[d] + c0; DQ[d] = sg.dqf[d] + c0; }
 
   // three phases, so that the loads of all PPT particles are in flight
-  // together (a store between them would pin the next loads behind it)
+  // together (a store between them would pin the next loads behind it).
+  // Slots past the end of the species load its last particle and are not
+  // stored, so the loads and updates are straight-line code.
   const ConstF32 k = const_f32<BLEND>(a, sg);
   uint32_t xu[PPT][3];
   float dq[PPT][3], q0[PPT][3];
+  const uint32_t last = (uint32_t)min<int64_t>(left - 1, (int64_t)(PPT * kBlock - 1));
 #pragma unroll
   for (int p = 0; p < PPT; ++p) {
-    const uint32_t i = threadIdx.x + (uint32_t)(p * kBlock);
-    if ((int64_t)i >= left) break;
+    const uint32_t i = min(threadIdx.x + (uint32_t)(p * kBlock), last);
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       xu[p][d] = ldnt(&X[d][i]);
@@ -199,11 +243,14 @@ __device__ __forceinline__ void push_chunk_f32(const PushArgs& a, int64_t chunk)
       dq[p][d] = ldnt(&DQ[d][i]);
     }
   }
+  if constexpr (!BLEND && !TSC) {
+    constexpr int GRP = GatherGroup<PPT>::N;
 #pragma unroll
-  for (int p = 0; p < PPT; ++p) {
-    const uint32_t i = threadIdx.x + (uint32_t)(p * kBlock);
-    if ((int64_t)i >= left) break;
-    update_f32<NSLOT, BLEND, TSC, OFF32>(k, a.do_drift != 0, xu[p], q0[p], dq[p]);
+    for (int p = 0; p < PPT; p += GRP)
+      update_group_f32<NSLOT, GRP, OFF32>(k, a.do_drift != 0, xu + p, q0 + p, dq + p);
+  } else {
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) update_f32<NSLOT, BLEND, TSC, OFF32>(k, a.do_drift != 0, xu[p], q0[p], dq[p]);
   }
 #pragma unroll
   for (int p = 0; p < PPT; ++p) {
@@ -237,12 +284,13 @@ __global__ void __launch_bounds__(kFusedThreads) k_push_sort_f32(PushArgs a) {
   const int64_t i0 = xcd_chunk(blockIdx.x, gridDim.x) * (int64_t)kSortBlock;
   const int cnt = (int)min<int64_t>(kSortBlock, sg.n - i0);
   // the sort outputs and ids first: their latency (bucket, then its start)
-  // overlaps the state loads and the gathers
+  // overlaps the state loads and the gathers.  Elements past the end of the
+  // species load its last one and are neither staged nor stored, so the
+  // loads and updates are straight-line code.
   uint32_t src[kPer], bucket[kPer], rank[kPer], id[kPer];
 #pragma unroll
   for (int r = 0; r < kPer; ++r) {
-    const int e = threadIdx.x + r * kFusedThreads;
-    if (e >= cnt) break;
+    const int e = min((int)threadIdx.x + r * kFusedThreads, cnt - 1);
     const int64_t o = i0 + e;                  // element e of the sorted order; slot e of the block
     src[r] = ldnt(&a.sort_src[o]);
     bucket[r] = ldnt(&a.sort_bucket[o]);
@@ -253,9 +301,7 @@ __global__ void __launch_bounds__(kFusedThreads) k_push_sort_f32(PushArgs a) {
   float dq[kPer][3], q0[kPer][3];
 #pragma unroll
   for (int r = 0; r < kPer; ++r) {
-    const int e = threadIdx.x + r * kFusedThreads;
-    if (e >= cnt) break;
-    const int64_t i = i0 + e;
+    const int64_t i = i0 + min((int)threadIdx.x + r * kFusedThreads, cnt - 1);
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       xu[r][d] = ldnt(&sg.xu[d][i]);
@@ -265,17 +311,13 @@ __global__ void __launch_bounds__(kFusedThreads) k_push_sort_f32(PushArgs a) {
   }
   int64_t dst[kPer];
 #pragma unroll
-  for (int r = 0; r < kPer; ++r) {
-    const int e = threadIdx.x + r * kFusedThreads;
-    if (e >= cnt) break;
-    dst[r] = (int64_t)a.sort_start[bucket[r]] + rank[r];
-  }
+  for (int r = 0; r < kPer; ++r) dst[r] = (int64_t)a.sort_start[bucket[r]] + rank[r];
   const ConstF32 k = const_f32<BLEND>(a, sg);
+  if constexpr (!BLEND && !TSC) {
+    update_group_f32<NSLOT, kPer, OFF32>(k, true, xu, q0, dq);
+  } else {
 #pragma unroll
-  for (int r = 0; r < kPer; ++r) {
-    const int e = threadIdx.x + r * kFusedThreads;
-    if (e >= cnt) break;
-    update_f32<NSLOT, BLEND, TSC, OFF32>(k, true, xu[r], q0[r], dq[r]);
+    for (int r = 0; r < kPer; ++r) update_f32<NSLOT, BLEND, TSC, OFF32>(k, true, xu[r], q0[r], dq[r]);
   }
 #pragma unroll
   for (int r = 0; r < kPer; ++r) {
