@@ -195,6 +195,9 @@ typedef struct fdf_tuning {
                                     fewer waves keeping more of each block's mesh
                                     neighbourhood in cache; 0: as many as the
                                     registers allow */
+  int32_t sort_push_ppt;         /* push that carries out a re-sort: particles per
+                                    thread (1, 2 or 4; 0 selects 4) of its
+                                    1024-particle blocks */
 } fdf_tuning;
 
 /* ---- lifetime -------------------------------------------------------------- */

@@ -3,8 +3,8 @@
 Candidates are timed on the device through the C ABI's own HIP-event timers:
 
   1. launch shape -- particles per thread and the cap on resident waves per
-     SIMD -- over the full schedule, scored by the time of both push kernels
-     (plain and fused with a re-sort);
+     SIMD, then the particles per thread of the push fused with a re-sort --
+     over the full schedule, scored by the time of both push kernels;
   2. sort policy -- bucket size and the drift threshold of the adaptive
      cadence -- over the full schedule, since the cost of a stale order and the
      number of re-sorts both depend on how far the particles travel;
@@ -69,7 +69,7 @@ def autotune(cfg, path=CACHE_PATH, log=print, full_schedule=True):
     sorting = cfg.get("sort_every", 0) > 0
     base = dict(particles_per_thread=4, sort_tiles=0, sort_every=cfg.get("sort_every", 0),
                 sort_cells=3.0 if sorting else 0.0, persistent_blocks=0, use_graph=0, sort_predict=1,
-                sort_fused=1, push_waves=0)
+                sort_fused=1, push_waves=0, sort_push_ppt=1)
     # 1. launch shape: particles per thread and the cap on resident waves,
     #    timed over the whole schedule (the mesh locality of the gathers, and
     #    with it the best shape, changes as the particles disperse).  The cap
@@ -83,6 +83,14 @@ def autotune(cfg, path=CACHE_PATH, log=print, full_schedule=True):
             r = _run(ctx, cfg, t, steps)
             log("[autotune] ppt=%d push_waves=%d: push %.3f ms per launch, %.1f ms both push kernels" % (
                 ppt, waves, r["push_ms"], r["push_total_ms"]))
+            if r["push_total_ms"] < best_ms:
+                best, best_ms = t, r["push_total_ms"]
+    #    then the particles per thread of the fused re-sort push
+    if sorting:
+        for sppt in (2, 4):
+            t = dict(best, sort_push_ppt=sppt)
+            r = _run(ctx, cfg, t, steps)
+            log("[autotune] sort_push_ppt=%d: %.1f ms both push kernels" % (sppt, r["push_total_ms"]))
             if r["push_total_ms"] < best_ms:
                 best, best_ms = t, r["push_total_ms"]
     # 2. sort policy over the whole schedule

@@ -351,6 +351,7 @@ struct fdf_ctx {
   bool sort_predict = true; // sort keys from positions extrapolated to mid-interval
   bool sort_fused = true;   // FP32 separable: re-sorts after the first ride on the push
   int push_waves = 0;       // cap on resident push waves per SIMD (0: none)
+  int sort_push_ppt = 4;    // particles per thread of the fused re-sort push
   hipStream_t cap_stream = nullptr;   // private stream used only for graph capture
   hipStream_t launch_stream = nullptr;  // stream kernels are enqueued on right now
   std::vector<GraphRec> graphs;       // captured step sequences
@@ -665,7 +666,8 @@ int sort_push_species(fdf_ctx* c, const std::vector<SortPrediction>& pred, const
     p.nseg = 1;
     p.total_chunks = (s.n + kSortBlock - 1) / kSortBlock;
     p.persistent = 0;
-    p.lds_reserve = push_sort_block_lds(c->push_waves);
+    p.ppt = c->sort_push_ppt;
+    p.lds_reserve = push_sort_block_lds(c->push_waves, c->sort_push_ppt);
     p.sort_src = a.src;
     p.sort_rank = a.rank;
     p.sort_bucket = a.bucket;
@@ -1530,6 +1532,7 @@ static void pk_enqueue(fdf_ctx* c, const int32_t* sp, int32_t ns, int32_t nbins,
       fr.dst[0] = b.real32;
       fr.dst[1] = b.real32 + cells;
       fr.n_half = cells;
+      fr.G = G;
       fr.n = (mode == FDF_PK_AUTO ? 1 : 2) * cells;
       fr.max_bits = b.max_bits;
       fr.fixed_bits = fixed_bits;
@@ -1781,6 +1784,7 @@ int fdf_get_tuning(const fdf_ctx* c, fdf_tuning* t) {
   t->sort_predict = c->sort_predict ? 1 : 0;
   t->sort_fused = c->sort_fused ? 1 : 0;
   t->push_waves = c->push_waves;
+  t->sort_push_ppt = c->sort_push_ppt;
   return FDF_OK;
 }
 
@@ -1802,6 +1806,8 @@ int fdf_set_tuning(fdf_ctx* c, const fdf_tuning* t) {
   if (t->sort_fused != 0 && t->sort_fused != 1) return fail(c, FDF_ERR_ARG, "sort_fused must be 0 or 1");
   if (t->push_waves != 0 && (t->push_waves < 2 || t->push_waves > 8))
     return fail(c, FDF_ERR_ARG, "push_waves must be 0 or in [2, 8]");
+  if (t->sort_push_ppt != 0 && t->sort_push_ppt != 1 && t->sort_push_ppt != 2 && t->sort_push_ppt != 4)
+    return fail(c, FDF_ERR_ARG, "sort_push_ppt must be 0, 1, 2 or 4");
   if (p != c->ppt) c->seg_dirty = true;   // chunk boundaries depend on the block size
   clear_graphs(c);
   c->persistent = t->persistent_blocks;
@@ -1813,6 +1819,7 @@ int fdf_set_tuning(fdf_ctx* c, const fdf_tuning* t) {
   c->sort_predict = t->sort_predict != 0;
   c->sort_fused = t->sort_fused != 0;
   c->push_waves = t->push_waves;
+  c->sort_push_ppt = t->sort_push_ppt ? t->sort_push_ppt : 4;
   return FDF_OK;
 }
 

@@ -118,7 +118,7 @@ struct PushArgs {
   double drift;            // Delta tau of the drift [Mpc]
   double a_drift;          // a_{k+1/2}
   double box;              // L
-  int32_t ppt;             // particles per thread
+  int32_t ppt;             // particles per thread (fused re-sort push: 1, 2 or 4)
   int32_t persistent;      // 0: one block per chunk; > 0: this many blocks (a multiple of 8) loop
   int32_t tsc;             // 1: TSC (r = 2) force interpolation, 0: CIC
   int32_t blend;           // 1: interpolate two grid sets (super-steps)
@@ -200,11 +200,13 @@ struct OutputArgs {
   int32_t fixed_bits;      // FP32 form: the quantum is 2^(e - fixed_bits), max |value| < 2^e
 };
 
-// Fixed-point deposit halves -> binary32 meshes (n cells in all, n_half per half).
+// Fixed-point deposit halves (bricked cell order) -> x-major binary32 meshes
+// (n cells in all, n_half = G^3 per half).
 struct FixedToRealArgs {
   const long long* src[2];
   float* dst[2];
   size_t n, n_half;
+  int32_t G;
   const uint32_t* max_bits;
   int32_t fixed_bits;
 };
@@ -240,7 +242,8 @@ void launch_power_spectrum(const PkArgs& a, hipStream_t s);
 void launch_bin(const PkArgs& a, hipStream_t s);   // bins planes bin_plane (and + 1) into a.bins
 void launch_fill_zero(void* ptr, size_t bytes, hipStream_t s);
 int push_chunk_particles(int ppt);
-int push_sort_block_lds(int waves);   // LDS to reserve per k_push_sort_f32 block for a cap of `waves` per SIMD
+int push_sort_block_lds(int waves, int per);   // LDS to reserve per k_push_sort_f32 block (per particles per
+                                              // thread) for a cap of `waves` per SIMD
 void launch_sort(const SortArgs& a, hipStream_t s);
 void launch_sort_rank(const SortArgs& a, hipStream_t s);   // counts, rank pass and scan, no move
 void launch_push_sort(const PushArgs& a, hipStream_t s);

@@ -68,7 +68,10 @@ __device__ __forceinline__ double deposit_value(const OutputArgs& a, int64_t i, 
 }
 
 // CIC cell and weights of particle i on the G^3 deposit mesh (vertex-centred
-// mesh points, periodic), x-major cell index.
+// mesh points, periodic): x-major cell index, or (bricked) the 4^3-brick
+// index of the gradient meshes, so that a wave of sorted particles adds into
+// a few contiguous kilobytes.
+template <bool BRICKED>
 __device__ __forceinline__ void deposit_cic(const OutputArgs& a, int64_t i, size_t* cell, double* wc) {
   const int G = a.G;
   const double ginv = (double)G / a.box;
@@ -85,7 +88,11 @@ __device__ __forceinline__ void deposit_cic(const OutputArgs& a, int64_t i, size
   for (int c = 0; c < 8; ++c) {
     const int cx = c >> 2, cy = (c >> 1) & 1, cz = c & 1;
     wc[c] = (cx ? t[0] : 1 - t[0]) * (cy ? t[1] : 1 - t[1]) * (cz ? t[2] : 1 - t[2]);
-    cell[c] = ((size_t)(cx ? i1[0] : i0[0]) * G + (cy ? i1[1] : i0[1])) * G + (cz ? i1[2] : i0[2]);
+    const int jx = cx ? i1[0] : i0[0], jy = cy ? i1[1] : i0[1], jz = cz ? i1[2] : i0[2];
+    if constexpr (BRICKED)
+      cell[c] = (size_t)mesh_x((uint32_t)jx, (uint32_t)G) + mesh_y((uint32_t)jy, (uint32_t)G) + mesh_z((uint32_t)jz);
+    else
+      cell[c] = ((size_t)jx * G + jy) * G + jz;
   }
 }
 
@@ -97,7 +104,7 @@ __global__ void k_deposit_f64(OutputArgs a) {
     const double val = deposit_value(a, i, &half);
     size_t cell[8];
     double wc[8];
-    deposit_cic(a, i, cell, wc);
+    deposit_cic<false>(a, i, cell, wc);
     double* dst = (double*)a.dens[half];
     for (int c = 0; c < 8; ++c) unsafeAtomicAdd(&dst[cell[c]], wc[c] * val);
   }
@@ -137,7 +144,7 @@ __global__ void k_deposit_fixed(OutputArgs a) {
     const double val = deposit_value(a, i, &half) * inv_q;
     size_t cell[8];
     double wc[8];
-    deposit_cic(a, i, cell, wc);
+    deposit_cic<true>(a, i, cell, wc);
     unsigned long long* dst = (unsigned long long*)a.dens[half];
     for (int c = 0; c < 8; ++c) {
       const long long v = __double2ll_rn(wc[c] * val);
@@ -146,13 +153,17 @@ __global__ void k_deposit_fixed(OutputArgs a) {
   }
 }
 
+// Bricked fixed-point halves -> x-major binary32 meshes.
 __global__ void k_fixed_to_real(FixedToRealArgs a) {
   const double q = 1.0 / fixed_inv_quantum(*a.max_bits, a.fixed_bits);
+  const uint32_t G = (uint32_t)a.G, lg = 31 - __clz(G);
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < a.n;
        i += (size_t)gridDim.x * blockDim.x) {
     const int h = i >= a.n_half;
-    const size_t j = i - (h ? a.n_half : 0);
-    a.dst[h][j] = (float)((double)a.src[h][j] * q);
+    const size_t j = i - (h ? a.n_half : 0);     // x-major cell (ix, iy, iz)
+    const uint32_t iz = (uint32_t)(j & (G - 1)), iy = (uint32_t)((j >> lg) & (G - 1)), ix = (uint32_t)(j >> (2 * lg));
+    const size_t b = (size_t)mesh_x(ix, G) + mesh_y(iy, G) + mesh_z(iz);
+    a.dst[h][j] = (float)((double)a.src[h][b] * q);
   }
 }
 

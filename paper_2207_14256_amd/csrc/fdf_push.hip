@@ -273,11 +273,11 @@ __device__ __forceinline__ void push_chunk_f32(const PushArgs& a, int64_t chunk)
 // write consecutive slots of a bucket fragment.  The re-sort then costs the
 // push the writes of q0 and id and the index reads, instead of a pass of its
 // own over the whole state.
-constexpr int kFusedThreads = 256;   // 4 waves per block, 4 particles per thread
-
-template <int NSLOT, bool BLEND, bool TSC, bool OFF32>
-__global__ void __launch_bounds__(kFusedThreads) k_push_sort_f32(PushArgs a) {
-  constexpr int kPer = kSortBlock / kFusedThreads;
+// PER particles per thread: kSortBlock / PER threads per block.
+template <int NSLOT, bool BLEND, bool TSC, bool OFF32, int PER>
+__global__ void __launch_bounds__(kSortBlock / PER) k_push_sort_f32(PushArgs a) {
+  constexpr int kPer = PER;
+  constexpr int kFusedThreads = kSortBlock / PER;
   __shared__ uint32_t st[10][kSortBlock];
   const Segment& sg = a.seg[0];
   const Segment& ds = a.dseg[0];
@@ -518,19 +518,26 @@ void push_launch(const PushArgs& a, hipStream_t s) {
   }
 }
 
-template <bool BLEND, bool TSC>
-void push_sort_launch(const PushArgs& a, hipStream_t s) {
-  const dim3 grid((unsigned)a.total_chunks), block(kFusedThreads);
+template <bool BLEND, bool TSC, int PER>
+void push_sort_launch_per(const PushArgs& a, hipStream_t s) {
+  const dim3 grid((unsigned)a.total_chunks), block(kSortBlock / PER);
   const bool off32 = (uint64_t)a.G * a.G * a.G * (uint64_t)(a.nslot * 2) <= (1ull << 32);
   if (off32) {
-    if (a.nslot == 8) hipLaunchKernelGGL((k_push_sort_f32<8, BLEND, TSC, true>), grid, block, a.lds_reserve, s, a);
-    else if (a.nslot == 6) hipLaunchKernelGGL((k_push_sort_f32<6, BLEND, TSC, true>), grid, block, a.lds_reserve, s, a);
-    else hipLaunchKernelGGL((k_push_sort_f32<4, BLEND, TSC, true>), grid, block, a.lds_reserve, s, a);
+    if (a.nslot == 8) hipLaunchKernelGGL((k_push_sort_f32<8, BLEND, TSC, true, PER>), grid, block, a.lds_reserve, s, a);
+    else if (a.nslot == 6) hipLaunchKernelGGL((k_push_sort_f32<6, BLEND, TSC, true, PER>), grid, block, a.lds_reserve, s, a);
+    else hipLaunchKernelGGL((k_push_sort_f32<4, BLEND, TSC, true, PER>), grid, block, a.lds_reserve, s, a);
   } else {
-    if (a.nslot == 8) hipLaunchKernelGGL((k_push_sort_f32<8, BLEND, TSC, false>), grid, block, a.lds_reserve, s, a);
-    else if (a.nslot == 6) hipLaunchKernelGGL((k_push_sort_f32<6, BLEND, TSC, false>), grid, block, a.lds_reserve, s, a);
-    else hipLaunchKernelGGL((k_push_sort_f32<4, BLEND, TSC, false>), grid, block, a.lds_reserve, s, a);
+    if (a.nslot == 8) hipLaunchKernelGGL((k_push_sort_f32<8, BLEND, TSC, false, PER>), grid, block, a.lds_reserve, s, a);
+    else if (a.nslot == 6) hipLaunchKernelGGL((k_push_sort_f32<6, BLEND, TSC, false, PER>), grid, block, a.lds_reserve, s, a);
+    else hipLaunchKernelGGL((k_push_sort_f32<4, BLEND, TSC, false, PER>), grid, block, a.lds_reserve, s, a);
   }
+}
+
+template <bool BLEND, bool TSC>
+void push_sort_launch(const PushArgs& a, hipStream_t s) {
+  if (a.ppt == 1) push_sort_launch_per<BLEND, TSC, 1>(a, s);
+  else if (a.ppt == 2) push_sort_launch_per<BLEND, TSC, 2>(a, s);
+  else push_sort_launch_per<BLEND, TSC, 4>(a, s);
 }
 
 template <int PPT>
@@ -548,10 +555,11 @@ void push_ppt(const PushArgs& a, hipStream_t s) {
 
 int push_chunk_particles(int ppt) { return kBlock * ppt; }
 
-int push_sort_block_lds(int waves) {
+int push_sort_block_lds(int waves, int per) {
   if (waves <= 0) return 0;
   const int lds_per_cu = 160 * 1024;
-  const int blocks = std::max(1, waves * 4 / (kFusedThreads / 64));   // blocks per CU for `waves` per SIMD
+  const int wave_per_block = kSortBlock / per / 64;
+  const int blocks = std::max(1, waves * 4 / wave_per_block);   // blocks per CU for `waves` per SIMD
   const int per_block = (lds_per_cu / (blocks + 1) + 256 + 255) / 256 * 256;
   return std::max(0, per_block - (int)sizeof(uint32_t) * 10 * kSortBlock);
 }
