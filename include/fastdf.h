@@ -190,7 +190,8 @@ typedef struct fdf_tuning {
                                     (no separate move pass; results bit-identical;
                                     the default); 0: rank + move passes, then
                                     the push */
-  int32_t push_waves;            /* push launch: at most this many resident waves per
+  int32_t push_waves;            /* plain push launch (not one that carries out a
+                                    re-sort): at most this many resident waves per
                                     SIMD (2-8; enforced by reserving LDS per block),
                                     fewer waves keeping more of each block's mesh
                                     neighbourhood in cache; 0: as many as the

@@ -72,9 +72,8 @@ def autotune(cfg, path=CACHE_PATH, log=print, full_schedule=True):
                 sort_fused=1, push_waves=0, sort_push_ppt=1)
     # 1. launch shape: particles per thread and the cap on resident waves,
     #    timed over the whole schedule (the mesh locality of the gathers, and
-    #    with it the best shape, changes as the particles disperse).  The cap
-    #    also sets the LDS reservation of the fused re-sort push, so the score
-    #    is the time of both push kernels together.
+    #    with it the best shape, changes as the particles disperse), scored
+    #    by the time of both push kernels together.
     best, best_ms = None, float("inf")
     steps = cfg["n_steps"] if full_schedule else min(40, cfg["n_steps"])
     for ppt in (1, 2, 4, 8):

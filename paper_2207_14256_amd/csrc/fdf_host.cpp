@@ -667,7 +667,7 @@ int sort_push_species(fdf_ctx* c, const std::vector<SortPrediction>& pred, const
     p.total_chunks = (s.n + kSortBlock - 1) / kSortBlock;
     p.persistent = 0;
     p.ppt = c->sort_push_ppt;
-    p.lds_reserve = push_sort_block_lds(c->push_waves, c->sort_push_ppt);
+    p.lds_reserve = 0;   // the cap on resident waves is the plain push's; this kernel runs at full occupancy
     p.sort_src = a.src;
     p.sort_rank = a.rank;
     p.sort_bucket = a.bucket;

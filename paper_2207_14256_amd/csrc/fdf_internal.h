@@ -14,8 +14,12 @@ namespace fdf {
 // rows a whole x-plane apart.  The index of cell (ix, iy, iz) on a G^3 mesh
 // (G a power of two >= 8) is mesh_x(ix) + mesh_y(iy) + mesh_z(iz).
 // ----------------------------------------------------------------------------
-__host__ __device__ inline uint32_t mesh_x(uint32_t i, uint32_t G) { return (i >> 2) * (G * G * 4u) + (i & 3u) * 16u; }
-__host__ __device__ inline uint32_t mesh_y(uint32_t i, uint32_t G) { return (i >> 2) * (G * 16u) + (i & 3u) * 4u; }
+// (G is a power of two: the brick strides are shifts, not multiplications)
+__host__ __device__ inline uint32_t log2_pow2(uint32_t G) { return 31u - (uint32_t)__builtin_clz(G); }
+__host__ __device__ inline uint32_t mesh_x(uint32_t i, uint32_t G) {
+  return ((i >> 2) << (2u * log2_pow2(G) + 2u)) + (i & 3u) * 16u;
+}
+__host__ __device__ inline uint32_t mesh_y(uint32_t i, uint32_t G) { return ((i >> 2) << (log2_pow2(G) + 4u)) + (i & 3u) * 4u; }
 __host__ __device__ inline uint32_t mesh_z(uint32_t i) { return (i >> 2) * 64u + (i & 3u); }
 
 // ----------------------------------------------------------------------------
@@ -242,8 +246,6 @@ void launch_power_spectrum(const PkArgs& a, hipStream_t s);
 void launch_bin(const PkArgs& a, hipStream_t s);   // bins planes bin_plane (and + 1) into a.bins
 void launch_fill_zero(void* ptr, size_t bytes, hipStream_t s);
 int push_chunk_particles(int ppt);
-int push_sort_block_lds(int waves, int per);   // LDS to reserve per k_push_sort_f32 block (per particles per
-                                              // thread) for a cap of `waves` per SIMD
 void launch_sort(const SortArgs& a, hipStream_t s);
 void launch_sort_rank(const SortArgs& a, hipStream_t s);   // counts, rank pass and scan, no move
 void launch_push_sort(const PushArgs& a, hipStream_t s);

@@ -132,9 +132,12 @@ __device__ __forceinline__ void kick_drift_f32(const ConstF32& k, bool drift, fl
 #pragma clang fp contract(off)
   if (NSLOT == 4) { g[3] = g[0]; g[4] = g[1]; g[5] = g[2]; }
   // separable force of eq. releq_approx
+  // 1/eps from the hardware reciprocal square root (about 1 ulp; the bf16
+  // mesh dominates the error budget of this form by four orders of magnitude)
   const float q0sq = fmaf(q0[0], q0[0], fmaf(q0[1], q0[1], q0[2] * q0[2]));
-  const float e0 = sqrtf(q0sq + k.ma2);
-  const float ie0 = 1.0f / e0;
+  const float e02 = q0sq + k.ma2;
+  const float ie0 = __builtin_amdgcn_rsqf(e02);
+  const float e0 = e02 * ie0;
   const float q0g = fmaf(q0[0], g[3], fmaf(q0[1], g[4], q0[2] * g[5]));
   const float qg = fmaf(q0g, ie0, g[6]);          // (q0 . grad phi)/eps0 + phidot
   const float cphi = q0sq * ie0;                    // q0^2 / eps0
@@ -148,7 +151,7 @@ __device__ __forceinline__ void kick_drift_f32(const ConstF32& k, bool drift, fl
 #pragma unroll
     for (int d = 0; d < 3; ++d) q[d] = q0[d] + dq[d];
     const float qq = fmaf(q[0], q[0], fmaf(q[1], q[1], q[2] * q[2]));
-    const float ie = 1.0f / sqrtf(qq + k.mah2);
+    const float ie = __builtin_amdgcn_rsqf(qq + k.mah2);
 #pragma unroll
     for (int d = 0; d < 3; ++d) xu[d] += (uint32_t)__float2int_rn(k.dscale * (q[d] * ie));
   }
@@ -191,13 +194,25 @@ __device__ __forceinline__ void update_group_f32(const ConstF32& k, bool drift, 
   using V = typename CellType<NSLOT>::T;
   uint32_t cell[GRP][8];
   float w[GRP][8];
-#pragma unroll
-  for (int p = 0; p < GRP; ++p) stencil_u32<false>(xu[p], k.shift, k.gmask, k.finv, k.G, cell[p], w[p]);
   V v[GRP][8];
+  if constexpr (OFF32) {   // byte offsets straight from the stencil
+    const uint32_t lg = 32u - (uint32_t)k.shift;
 #pragma unroll
-  for (int p = 0; p < GRP; ++p)
+    for (int p = 0; p < GRP; ++p)
+      stencil_u32_bytes<(uint32_t)sizeof(V)>(xu[p], k.shift, k.gmask, k.finv, lg, cell[p], w[p]);
+    const char FDF_GLOBAL* b = (const char FDF_GLOBAL*)k.gridA;
 #pragma unroll
-    for (int c = 0; c < 8; ++c) v[p][c] = load_cell<V, OFF32>(k.gridA, cell[p][c]);
+    for (int p = 0; p < GRP; ++p)
+#pragma unroll
+      for (int c = 0; c < 8; ++c) v[p][c] = *(const FDF_GLOBAL V*)(b + cell[p][c]);
+  } else {
+#pragma unroll
+    for (int p = 0; p < GRP; ++p) stencil_u32<false>(xu[p], k.shift, k.gmask, k.finv, k.G, cell[p], w[p]);
+#pragma unroll
+    for (int p = 0; p < GRP; ++p)
+#pragma unroll
+      for (int c = 0; c < 8; ++c) v[p][c] = load_cell<V, OFF32>(k.gridA, cell[p][c]);
+  }
 #pragma unroll
   for (int p = 0; p < GRP; ++p) {
     float g[7] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
@@ -554,15 +569,6 @@ void push_ppt(const PushArgs& a, hipStream_t s) {
 }  // namespace
 
 int push_chunk_particles(int ppt) { return kBlock * ppt; }
-
-int push_sort_block_lds(int waves, int per) {
-  if (waves <= 0) return 0;
-  const int lds_per_cu = 160 * 1024;
-  const int wave_per_block = kSortBlock / per / 64;
-  const int blocks = std::max(1, waves * 4 / wave_per_block);   // blocks per CU for `waves` per SIMD
-  const int per_block = (lds_per_cu / (blocks + 1) + 256 + 255) / 256 * 256;
-  return std::max(0, per_block - (int)sizeof(uint32_t) * 10 * kSortBlock);
-}
 
 void launch_push_sort(const PushArgs& a, hipStream_t s) {
   if (a.tsc) {

@@ -115,6 +115,40 @@ __device__ __forceinline__ void stencil_u32(const uint32_t* xu, int shift, uint3
   }
 }
 
+// CIC stencil of the FP32 form as byte offsets into a mesh of CB-byte cells
+// (the same corners and weights as stencil_u32<false>): the per-axis terms
+// of the brick layout scaled by CB with 24-bit multiplies and shifts (full
+// rate), instead of a 32-bit multiplication of every corner's cell index.
+template <uint32_t CB>
+__device__ __forceinline__ void stencil_u32_bytes(const uint32_t* xu, int shift, uint32_t gmask, float finv,
+                                                  uint32_t lg, uint32_t* off, float* w) {
+#pragma clang fp contract(off)
+  const uint32_t fmask = (1u << shift) - 1u;
+  uint32_t i0[3], i1[3];
+  float t[3], u[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    i0[d] = xu[d] >> shift;
+    i1[d] = (i0[d] + 1u) & gmask;
+    t[d] = (float)(xu[d] & fmask) * finv;
+    u[d] = 1.0f - t[d];
+  }
+  // bytes of mesh_x(i) * CB, mesh_y(i) * CB, mesh_z(i) * CB
+  auto mul24 = [](uint32_t a, uint32_t b) { return (uint32_t)__umul24(a, b); };
+  auto bx = [&](uint32_t i) { return (mul24(i >> 2, CB) << (2u * lg + 2u)) + mul24(i & 3u, 16u * CB); };
+  auto by = [&](uint32_t i) { return (mul24(i >> 2, CB) << (lg + 4u)) + mul24(i & 3u, 4u * CB); };
+  auto bz = [&](uint32_t i) { return mul24(i >> 2, 64u * CB) + mul24(i & 3u, CB); };
+  const uint32_t ax[2] = {bx(i0[0]), bx(i1[0])};
+  const uint32_t ay[2] = {by(i0[1]), by(i1[1])};
+  const uint32_t az[2] = {bz(i0[2]), bz(i1[2])};
+#pragma unroll
+  for (int cc = 0; cc < 8; ++cc) {
+    const int cx = cc >> 2, cy = (cc >> 1) & 1, cz = cc & 1;
+    off[cc] = ax[cx] + ay[cy] + az[cz];
+    w[cc] = ((cx ? t[0] : u[0]) * (cy ? t[1] : u[1])) * (cz ? t[2] : u[2]);
+  }
+}
+
 // FP64 form: x in [0, L) Mpc.
 template <bool TSC, typename I>
 __device__ __forceinline__ void stencil_f64(const double* x, double ginv, int gm, I G,
