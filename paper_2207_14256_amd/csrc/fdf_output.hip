@@ -1,6 +1,7 @@
 // Outputs of the push: delta-f weights (sec. 2.2) and the energy-density
 // deposit of eq. empirical_rho, gfx950.
 #include <algorithm>
+#include <type_traits>
 
 #include "fdf_device.h"
 #include "fdf_internal.h"
@@ -96,20 +97,6 @@ __device__ __forceinline__ void deposit_cic(const OutputArgs& a, int64_t i, size
   }
 }
 
-// Binary64 deposit (FP64 form): hardware float64 atomics into the halves.
-__global__ void k_deposit_f64(OutputArgs a) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < a.seg.n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    int half;
-    const double val = deposit_value(a, i, &half);
-    size_t cell[8];
-    double wc[8];
-    deposit_cic<false>(a, i, cell, wc);
-    double* dst = (double*)a.dens[half];
-    for (int c = 0; c < 8; ++c) unsafeAtomicAdd(&dst[cell[c]], wc[c] * val);
-  }
-}
-
 // Fixed-point deposit (FP32 form).  Every contribution wc * val is rounded
 // to an integer multiple of a quantum Q = 2^(e - bits), where 2^e bounds the
 // largest |val| of the spectrum's particles and bits leaves headroom for the
@@ -136,20 +123,72 @@ __global__ void __launch_bounds__(256) k_deposit_max(OutputArgs a) {
   if ((threadIdx.x & 63) == 0 && m > 0.0f) atomicMax(a.max_bits, __float_as_uint(m));
 }
 
-__global__ void k_deposit_fixed(OutputArgs a) {
-  const double inv_q = fixed_inv_quantum(*a.max_bits, a.fixed_bits);
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < a.seg.n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    int half;
-    const double val = deposit_value(a, i, &half) * inv_q;
-    size_t cell[8];
-    double wc[8];
-    deposit_cic<true>(a, i, cell, wc);
-    unsigned long long* dst = (unsigned long long*)a.dens[half];
-    for (int c = 0; c < 8; ++c) {
-      const long long v = __double2ll_rn(wc[c] * val);
-      if (v) atomicAdd(&dst[cell[c]], (unsigned long long)v);
+// Deposit with the additions gathered first in a workgroup hash table in
+// LDS (key = 2 cell + half, linear probing), so that the sums of a block's
+// 1024 particles reach the mesh with one global atomic per distinct cell and
+// half instead of one per corner.  Global atomics are carried out past the
+// per-XCD L2 caches, one memory transaction each, and dominate the plain
+// kernels' time; sorted particles share most corners (about 8 contributions
+// per particle become 2 to 3 global atomics).  A contribution that finds no
+// slot within kProbe probes goes to the mesh directly.  V = unsigned long
+// long: the fixed-point form, whose integer sums do not depend on how the
+// additions are grouped or ordered; V = double: the FP64 form.
+template <typename V>
+__global__ void __launch_bounds__(256) k_deposit_lds(OutputArgs a) {
+  constexpr int R = 4, LOGH = 12;
+  constexpr uint32_t H = 1u << LOGH, kEmpty = 0xFFFFFFFFu;
+  constexpr int kProbe = 32;
+  constexpr bool kFixed = std::is_same<V, unsigned long long>::value;
+  __shared__ uint32_t key[H];
+  __shared__ V val[H];
+  const double scale = kFixed ? fixed_inv_quantum(*a.max_bits, a.fixed_bits) : 1.0;
+  constexpr int64_t per = 256 * R;
+  const int64_t nchunk = (a.seg.n + per - 1) / per;
+  for (int64_t ch = blockIdx.x; ch < nchunk; ch += gridDim.x) {
+    for (uint32_t s = threadIdx.x; s < H; s += 256) { key[s] = kEmpty; val[s] = (V)0; }
+    __syncthreads();
+    for (int r = 0; r < R; ++r) {
+      const int64_t i = ch * per + r * 256 + threadIdx.x;
+      if (i >= a.seg.n) break;
+      int half;
+      const double v0 = deposit_value(a, i, &half) * scale;
+      size_t cell[8];
+      double wc[8];
+      deposit_cic<kFixed>(a, i, cell, wc);
+      for (int c = 0; c < 8; ++c) {
+        V v;
+        if constexpr (kFixed) v = (V)__double2ll_rn(wc[c] * v0);
+        else v = wc[c] * v0;
+        if (v == (V)0) continue;
+        const uint32_t k = (uint32_t)(cell[c] * 2 + half);
+        uint32_t h = (k * 0x9E3779B1u) >> (32 - LOGH);
+        bool done = false;
+        for (int p = 0; p < kProbe; ++p) {
+          const uint32_t prev = atomicCAS(&key[h], kEmpty, k);
+          if (prev == kEmpty || prev == k) {
+            atomicAdd(&val[h], v);
+            done = true;
+            break;
+          }
+          h = (h + 1) & (H - 1);
+        }
+        if (!done) {
+          V* const d = (V*)a.dens[half] + cell[c];
+          if constexpr (kFixed) atomicAdd(d, v);
+          else unsafeAtomicAdd(d, v);
+        }
+      }
     }
+    __syncthreads();
+    for (uint32_t s = threadIdx.x; s < H; s += 256) {
+      const uint32_t k = key[s];
+      const V v = val[s];
+      if (k == kEmpty || v == (V)0) continue;
+      V* const d = (V*)a.dens[k & 1u] + (k >> 1);
+      if constexpr (kFixed) atomicAdd(d, v);
+      else unsafeAtomicAdd(d, v);
+    }
+    __syncthreads();
   }
 }
 
@@ -266,8 +305,11 @@ void launch_force_terms(const TermArgs& a, hipStream_t s) {
 }
 
 void launch_deposit(const OutputArgs& a, hipStream_t s) {
-  if (a.fp64) hipLaunchKernelGGL(k_deposit_f64, dim3(grid_for((size_t)a.seg.n, 256)), dim3(256), 0, s, a);
-  else hipLaunchKernelGGL(k_deposit_fixed, dim3(grid_for((size_t)a.seg.n, 256)), dim3(256), 0, s, a);
+  // grid_n <= 1024 (checked at creation): the keys 2 cell + half stay below
+  // the empty key in 32 bits
+  const int grid = grid_for((size_t)a.seg.n, 1024);
+  if (a.fp64) hipLaunchKernelGGL(k_deposit_lds<double>, dim3(grid), dim3(256), 0, s, a);
+  else hipLaunchKernelGGL(k_deposit_lds<unsigned long long>, dim3(grid), dim3(256), 0, s, a);
 }
 
 void launch_bins_finalize(const double* bins, int nbins, double* out, hipStream_t s) {
