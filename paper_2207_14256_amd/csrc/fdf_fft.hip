@@ -136,7 +136,7 @@ template <typename R, int G> struct Shape {
   static constexpr int NB0 = 65536 / (G * CS);
   static constexpr int NB = NB0 > 16 ? 16 : (NB0 < 1 ? 1 : NB0);     // columns per strided block
   static constexpr int NBC = NB > G / 2 ? G / 2 : NB;
-  static constexpr int NBX = NBC / 2 > 0 ? NBC / 2 : 1;             // X pass keeps delta_0 in registers
+  static constexpr int NBX = NBC;                                    // columns per X-pass block
   static constexpr int NT = 256;
   static constexpr int M = G / 2;
   static constexpr int NL0 = 1024 / G;
@@ -166,6 +166,9 @@ __device__ __forceinline__ void slot_multiplier(int kind, int nx, int ny, int nz
 }
 
 // ------------------------------------------------------------------ X pass --
+// delta_0 is read again for every field (from L2 after the first) rather
+// than held in registers across the fields: the multipliers' binary64
+// arithmetic then leaves room for several waves per SIMD.
 template <typename R, int G>
 __global__ void __launch_bounds__(256) k_xpass_inverse(GridBuildArgs a) {
   using S = Shape<R, G>;
@@ -178,32 +181,24 @@ __global__ void __launch_bounds__(256) k_xpass_inverse(GridBuildArgs a) {
   const cplx<R>* __restrict__ tw = (const cplx<R>*)a.twiddle;
   cplx<R>* scr = (cplx<R>*)a.scratch;
   const size_t plane = (size_t)G * G * M;
-  cplx<R> d[PER];
-#pragma unroll
-  for (int p = 0; p < PER; ++p) {
-    const int e = threadIdx.x + p * NT;
-    if ((G * NB) % NT == 0 || e < G * NB) {
-      const int ix = e / NB, b = e % NB;
-      d[p] = din[((size_t)ix * G + iy) * M + iz0 + b];
-    }
-  }
   const int ny = signed_index(iy, G);
   for (int f = 0; f < a.nfft; ++f) {
     const int kind = a.kind[f];
-#pragma unroll
+#pragma unroll 2
     for (int p = 0; p < PER; ++p) {
       const int e = threadIdx.x + p * NT;
       if ((G * NB) % NT == 0 || e < G * NB) {
         const int ix = e / NB, b = e % NB;
+        const cplx<R> d = din[((size_t)ix * G + iy) * M + iz0 + b];
         double re, im;
         slot_multiplier(kind, signed_index(ix, G), ny, iz0 + b, a.kf, a.tr, re, im);
-        const double dx = (double)d[p].x, dy = (double)d[p].y;
+        const double dx = (double)d.x, dy = (double)d.y;
         buf[ix * NB + b] = {(R)(re * dx - im * dy), (R)(re * dy + im * dx)};
       }
     }
     __syncthreads();
     fft_lines<R, G, NB, NT, true, 1>(buf, tw);
-#pragma unroll
+#pragma unroll 4
     for (int p = 0; p < PER; ++p) {
       const int e = threadIdx.x + p * NT;
       if ((G * NB) % NT == 0 || e < G * NB) {
@@ -574,6 +569,112 @@ __global__ void k_bin_sums(PkArgs a) {
   }
 }
 
+// bfloat16 meshes: one block = 2 x-values by 4 y-lines (8 z-lines), so that
+// it writes whole halves of 4^3-cell bricks (32 cells of 2 NSLOT bytes: whole
+// 128-byte lines, one vector store per cell) instead of fragments of lines
+// shared with blocks on other XCDs.  Element e of a field's 8 lines is
+// (line e % 8, frequency e / 8) throughout, so that every LDS access of the
+// half-length transform's pre-processing is conflict-free; the results are
+// staged as bfloat16 pairs (the same rounding as the per-cell stores above)
+// in per-slot rows padded to spread the 8 lines over the banks.
+template <int NSLOT> struct CellWords;
+template <> struct CellWords<8> { using T = uint4; };
+template <> struct CellWords<6> { using T = uint3; };
+template <> struct CellWords<4> { using T = uint2; };
+
+template <int G, int NSLOT>
+__global__ void __launch_bounds__(256) k_zpass_c2r_bf16(GridBuildArgs a) {
+  using R = float;
+  constexpr int M = G / 2, NT = 256, NL = 8;
+  constexpr int PER = (M * NL + NT - 1) / NT;
+  constexpr int SW = (G + 16) / 2;                  // 32-bit words per staged row (line, slot)
+  __shared__ cplx<R> buf[M * NL];
+  __shared__ uint32_t stage[NSLOT * NL * SW];
+  const int nyb = G / 4;
+  const int ix0 = (blockIdx.x / nyb) * 2, iy0 = (blockIdx.x % nyb) * 4;
+  const cplx<R>* __restrict__ tw = (const cplx<R>*)a.twiddle;
+  const cplx<R>* scr = (const cplx<R>*)a.scratch;
+  const size_t plane = (size_t)G * G * M;
+  for (int e = threadIdx.x; e < NSLOT * NL * SW; e += NT) stage[e] = 0u;
+  // line l = 4 (x offset) + (y offset); the next field's lines are loaded
+  // while this field is transformed
+  auto load = [&](int f, cplx<R>* v) {
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+      const int e = threadIdx.x + p * NT;
+      if ((M * NL) % NT == 0 || e < M * NL) {
+        const int line = e % NL, k = e / NL;
+        v[p] = scr[f * plane + ((size_t)(ix0 + (line >> 2)) * G + iy0 + (line & 3)) * M + k];
+      }
+    }
+  };
+  cplx<R> xn[PER];
+  if (a.nfft > 0) load(0, xn);
+  for (int f = 0; f < a.nfft; ++f) {
+    const int slot = a.slot[f];
+    cplx<R> x[PER];
+#pragma unroll
+    for (int p = 0; p < PER; ++p) x[p] = xn[p];
+    if (f + 1 < a.nfft) load(f + 1, xn);
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+      const int e = threadIdx.x + p * NT;
+      if ((M * NL) % NT == 0 || e < M * NL) buf[e] = x[p];
+    }
+    __syncthreads();
+    // Z[k] = (X[k] + conj X[M-k]) + i e^{2 pi i k/G} (X[k] - conj X[M-k]), X[M] = 0
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+      const int e = threadIdx.x + p * NT;
+      if ((M * NL) % NT == 0 || e < M * NL) {
+        const int line = e % NL, k = e / NL;
+        cplx<R> xk = x[p];
+        cplx<R> xm = k ? buf[(M - k) * NL + line] : cplx<R>{(R)0, (R)0};
+        cplx<R> s = {xk.x + xm.x, xk.y - xm.y};
+        cplx<R> d = {xk.x - xm.x, xk.y + xm.y};
+        cplx<R> w = tw[k];
+        cplx<R> wd = cmulc(d, w);
+        x[p] = {s.x - wd.y, s.y + wd.x};
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+      const int e = threadIdx.x + p * NT;
+      if ((M * NL) % NT == 0 || e < M * NL) buf[e] = x[p];
+    }
+    __syncthreads();
+    fft_lines<R, M, NL, NT, true, 2>(buf, tw);
+#pragma unroll 4
+    for (int e = threadIdx.x; e < M * NL; e += NT) {
+      const int line = e % NL, m = e / NL;
+      const cplx<R> z = buf[e];
+      stage[(slot * NL + line) * SW + m] = f32_to_bf16_bits(z.x) | (f32_to_bf16_bits(z.y) << 16);
+    }
+    __syncthreads();   // buf is rewritten by the next field
+  }
+  // brick j along z: cells base(j) + c, c = 16 dx + 4 dy + dz in [0, 32)
+  using W = typename CellWords<NSLOT>::T;
+  const uint16_t* st = (const uint16_t*)stage;
+  W* out = (W*)a.out;
+  const size_t base0 = (size_t)mesh_x(ix0, G) + mesh_y(iy0, G);
+#pragma unroll 2
+  for (int t = threadIdx.x; t < (G / 4) * 32; t += NT) {
+    const int j = t >> 5, c = t & 31;
+    const int line = (c >> 4) * 4 + ((c >> 2) & 3), iz = 4 * j + (c & 3);
+    uint32_t wv[NSLOT / 2];
+#pragma unroll
+    for (int q = 0; q < NSLOT / 2; ++q)
+      wv[q] = (uint32_t)st[2 * ((2 * q) * NL * SW + line * SW) + iz] |
+              ((uint32_t)st[2 * ((2 * q + 1) * NL * SW + line * SW) + iz] << 16);
+    W v;
+    if constexpr (NSLOT == 8) v = make_uint4(wv[0], wv[1], wv[2], wv[3]);
+    else if constexpr (NSLOT == 6) v = make_uint3(wv[0], wv[1], wv[2]);
+    else v = make_uint2(wv[0], wv[1]);
+    out[base0 + mesh_z(4 * j) + c] = v;
+  }
+}
+
 // --------------------------------------------------------------- dispatch --
 template <typename R, int G>
 void build_grids_g(const GridBuildArgs& a, hipStream_t s) {
@@ -585,6 +686,15 @@ void build_grids_g(const GridBuildArgs& a, hipStream_t s) {
   const int nyb = G / S::NL;
   const dim3 zg(G * nyb);
   if constexpr (std::is_same<R, float>::value) {
+    if constexpr (G <= 512) {   // the staged outputs of 8 lines fit in LDS
+      if (a.out_type == GT_BF16) {
+        const dim3 zb((G / 2) * (G / 4));
+        if (a.nslot == 8) hipLaunchKernelGGL((k_zpass_c2r_bf16<G, 8>), zb, dim3(S::NT), 0, s, a);
+        else if (a.nslot == 6) hipLaunchKernelGGL((k_zpass_c2r_bf16<G, 6>), zb, dim3(S::NT), 0, s, a);
+        else hipLaunchKernelGGL((k_zpass_c2r_bf16<G, 4>), zb, dim3(S::NT), 0, s, a);
+        return;
+      }
+    }
     if (a.out_type == GT_BF16) {
       if (a.nslot == 8) hipLaunchKernelGGL((k_zpass_c2r<R, G, 8, GT_BF16>), zg, dim3(S::NT), 0, s, a);
       else if (a.nslot == 6) hipLaunchKernelGGL((k_zpass_c2r<R, G, 6, GT_BF16>), zg, dim3(S::NT), 0, s, a);
