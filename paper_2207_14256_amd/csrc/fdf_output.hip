@@ -192,17 +192,23 @@ __global__ void __launch_bounds__(256) k_deposit_lds(OutputArgs a) {
   }
 }
 
-// Bricked fixed-point halves -> x-major binary32 meshes.
+// Bricked fixed-point halves -> x-major binary32 meshes, four cells along z
+// per thread: they are contiguous in both layouts (one 32-byte read of the
+// brick's z-run, one 16-byte write).
 __global__ void k_fixed_to_real(FixedToRealArgs a) {
   const double q = 1.0 / fixed_inv_quantum(*a.max_bits, a.fixed_bits);
   const uint32_t G = (uint32_t)a.G, lg = 31 - __clz(G);
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < a.n;
+  const size_t n4 = a.n / 4, h4 = a.n_half / 4;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n4;
        i += (size_t)gridDim.x * blockDim.x) {
-    const int h = i >= a.n_half;
-    const size_t j = i - (h ? a.n_half : 0);     // x-major cell (ix, iy, iz)
+    const int h = i >= h4;
+    const size_t j = 4 * (i - (h ? h4 : 0));     // x-major cell (ix, iy, iz), iz = 0 mod 4
     const uint32_t iz = (uint32_t)(j & (G - 1)), iy = (uint32_t)((j >> lg) & (G - 1)), ix = (uint32_t)(j >> (2 * lg));
     const size_t b = (size_t)mesh_x(ix, G) + mesh_y(iy, G) + mesh_z(iz);
-    a.dst[h][j] = (float)((double)a.src[h][b] * q);
+    const longlong2* src = (const longlong2*)(a.src[h] + b);
+    const longlong2 v0 = src[0], v1 = src[1];
+    *(float4*)(a.dst[h] + j) = make_float4((float)((double)v0.x * q), (float)((double)v0.y * q),
+                                           (float)((double)v1.x * q), (float)((double)v1.y * q));
   }
 }
 
@@ -321,7 +327,7 @@ void launch_deposit_max(const OutputArgs& a, hipStream_t s) {
 }
 
 void launch_fixed_to_real(const FixedToRealArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_fixed_to_real, dim3(grid_for(a.n, 256)), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_fixed_to_real, dim3(grid_for(a.n / 4, 256)), dim3(256), 0, s, a);
 }
 
 // Zero a 16-byte aligned buffer whose size is a multiple of 16 with a plain
