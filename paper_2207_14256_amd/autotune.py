@@ -8,8 +8,10 @@ Candidates are timed on the device through the C ABI's own HIP-event timers:
   2. sort policy -- bucket size and the drift threshold of the adaptive
      cadence -- over the full schedule, since the cost of a stale order and the
      number of re-sorts both depend on how far the particles travel;
-  3. hipGraph capture and replay of the step sequence against plain launches,
-     by wall time.
+  3. a persistent push grid (a fixed number of blocks looping over the
+     chunks) against one block per chunk, then hipGraph capture and replay of
+     the step sequence against plain launches, both by wall time over the
+     schedule.
 
 Results are cached in ``tuning_cache.json`` next to this file, keyed by the
 device architecture, mesh size, particles per cell, precision and number of
@@ -106,11 +108,19 @@ def autotune(cfg, path=CACHE_PATH, log=print, full_schedule=True):
                 if r["wall_s"] < best_wall:
                     chosen, best_wall = t, r["wall_s"]
         best = chosen
-    # 3. the launch sequence captured in a hipGraph and replayed, against
-    #    plain launches, by wall time over the schedule (two runs each: the
-    #    first replay of a graph includes its capture); graphs must win by 1 %,
-    #    since they turn the per-kernel timers off
+    # 3. a persistent push grid, then the launch sequence captured in a
+    #    hipGraph and replayed, against plain launches, by wall time over the
+    #    schedule (two runs each: the first replay of a graph includes its
+    #    capture); either must win by 1 % (graphs turn the per-kernel timers
+    #    off)
     if full_schedule:
+        walls = {}
+        for pb in (0, 1024, 2048):
+            t = dict(best, persistent_blocks=pb)
+            walls[pb] = min(_run(ctx, cfg, t, cfg["n_steps"])["wall_s"] for _ in range(2))
+            log("[autotune] persistent_blocks=%d: %.3f s" % (pb, walls[pb]))
+        pb = min(walls, key=walls.get)
+        best = dict(best, persistent_blocks=pb if walls[pb] < 0.99 * walls[0] else 0)
         walls = {}
         for g in (0, 1):
             t = dict(best, use_graph=g)
