@@ -131,7 +131,8 @@ def test_eom_split_calls_bitwise(prec):
 @pytest.mark.parametrize("n_steps", [60, 1142])
 def test_separable_vs_exact_power_spectrum(n_steps):
     """Sec. 3.3: the non-symplectic integration of the exact equations and the
-    separable scheme give density spectra that differ at the 1e-5 level.
+    separable scheme give nearly the same density spectra (the paper quotes
+    about 1e-5 for its run; here the synthetic potentials give about 1e-4).
     1142 steps from z = 1e6 to 10 is the paper's Delta log a = 0.01; 60 steps
     is Delta log a = 0.19."""
     say("separable vs exact P(k), %d steps" % n_steps)
@@ -148,7 +149,9 @@ def test_separable_vs_exact_power_spectrum(n_steps):
     rel = np.abs(pe[ok] / ps[ok] - 1)
     dloga = np.log((1 + 1e6) / (1 + 10.0)) / n_steps
     say("separable vs exact, dloga %.3f: max |dP/P| = %.3e, median %.3e" % (dloga, rel.max(), np.median(rel)))
-    assert np.median(rel) < 1e-3
+    # recorded: median 8.7e-5 / 9.9e-5 and max 6.2e-4 / 6.8e-4 (1142 / 60
+    # steps); the paper quotes about 1e-5 for its own run
+    assert np.median(rel) < 3e-4 and rel.max() < 2e-3
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
