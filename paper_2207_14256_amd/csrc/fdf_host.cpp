@@ -665,6 +665,7 @@ int sort_push_species(fdf_ctx* c, const std::vector<SortPrediction>& pred, const
     p.alt_mask = p.skip_mask = 0;
     p.nseg = 1;
     p.total_chunks = (s.n + kSortBlock - 1) / kSortBlock;
+    p.xcd_blocks = 0;
     p.persistent = 0;
     p.ppt = c->sort_push_ppt;
     p.lds_reserve = 0;   // the cap on resident waves is the plain push's; this kernel runs at full occupancy
@@ -680,6 +681,23 @@ int sort_push_species(fdf_ctx* c, const std::vector<SortPrediction>& pred, const
     s.cur ^= 1;
   }
   return launched(c, "sort + push");
+}
+
+// Grid of the segment-balanced XCD mapping of a launch over every species
+// (8 times the largest share of an XCD), or 0 for a single species.
+int64_t xcd_blocks(fdf_ctx* c) {
+  if (c->species.size() < 2) return 0;
+  const int64_t per = push_chunk_particles(c->ppt);
+  int64_t most = 0;
+  for (int64_t x = 0; x < 8; ++x) {
+    int64_t share = 0;
+    for (auto& s : c->species) {
+      const int64_t n = (s.n + per - 1) / per;
+      share += n * (x + 1) / 8 - n * x / 8;
+    }
+    most = std::max(most, share);
+  }
+  return 8 * most;
 }
 
 int64_t total_chunks(fdf_ctx* c) {
@@ -1077,6 +1095,7 @@ int enqueue_steps(fdf_ctx* c, int32_t n) {
   PushArgs pa{};
   pa.nseg = (int)c->species.size();
   pa.total_chunks = total_chunks(c);
+  pa.xcd_blocks = xcd_blocks(c);
   pa.fp64 = c->cfg.precision == FDF_PREC_FP64;
   pa.nslot = c->lay.nslot;
   pa.G = c->cfg.grid_n;

@@ -129,6 +129,7 @@ struct PushArgs {
   int32_t grid_sel;        // which set holds the earlier anchor: 0 = grid, 1 = grid2
   double blend_t;          // interpolation weight of the later anchor
   int32_t lds_reserve;     // bytes of LDS reserved per block (caps resident waves), or 0
+  int64_t xcd_blocks;      // > 0: grid of the segment-balanced XCD mapping (several segments)
   // push fused with the move of a re-sort (launch_push_sort; FP32 separable
   // form, one species: seg and dseg point at its entry in the two tables,
   // total_chunks counts its kSortBlock-particle rank blocks)

@@ -490,7 +490,11 @@ __device__ __forceinline__ void push_chunk_f64(const PushArgs& a, int64_t chunk)
 // contiguous eighth of the chunk range.
 template <int NSLOT, int PPT, bool BLEND, bool TSC, bool OFF32>
 __global__ void __launch_bounds__(kBlock) k_push_f32(PushArgs a) {
-  if (!a.persistent) { push_chunk_f32<NSLOT, PPT, BLEND, TSC, OFF32>(a, xcd_chunk(blockIdx.x, gridDim.x)); return; }
+  if (!a.persistent) {
+    const int64_t c = launch_chunk(a);
+    if (c >= 0) push_chunk_f32<NSLOT, PPT, BLEND, TSC, OFF32>(a, c);
+    return;
+  }
   const int64_t per = (a.total_chunks + 7) / 8, x = blockIdx.x % 8, stride = gridDim.x / 8;
   const int64_t end = min((x + 1) * per, a.total_chunks);
   for (int64_t c = x * per + blockIdx.x / 8; c < end; c += stride) push_chunk_f32<NSLOT, PPT, BLEND, TSC, OFF32>(a, c);
@@ -498,7 +502,11 @@ __global__ void __launch_bounds__(kBlock) k_push_f32(PushArgs a) {
 
 template <int NSLOT, int PPT, bool BLEND, bool TSC, bool OFF32>
 __global__ void __launch_bounds__(kBlock) k_push_f64(PushArgs a) {
-  if (!a.persistent) { push_chunk_f64<NSLOT, PPT, BLEND, TSC, OFF32>(a, xcd_chunk(blockIdx.x, gridDim.x)); return; }
+  if (!a.persistent) {
+    const int64_t c = launch_chunk(a);
+    if (c >= 0) push_chunk_f64<NSLOT, PPT, BLEND, TSC, OFF32>(a, c);
+    return;
+  }
   const int64_t per = (a.total_chunks + 7) / 8, x = blockIdx.x % 8, stride = gridDim.x / 8;
   const int64_t end = min((x + 1) * per, a.total_chunks);
   for (int64_t c = x * per + blockIdx.x / 8; c < end; c += stride) push_chunk_f64<NSLOT, PPT, BLEND, TSC, OFF32>(a, c);
@@ -506,7 +514,7 @@ __global__ void __launch_bounds__(kBlock) k_push_f64(PushArgs a) {
 
 template <int PPT, bool BLEND, bool TSC>
 void push_launch(const PushArgs& a, hipStream_t s) {
-  const int64_t grid_blocks = a.persistent ? a.persistent : a.total_chunks;
+  const int64_t grid_blocks = a.persistent ? a.persistent : (a.xcd_blocks > 0 ? a.xcd_blocks : a.total_chunks);
   const dim3 grid((unsigned)grid_blocks), block(kBlock);
   // byte offsets of the mesh fit 32 bits?
   const bool off32 = (uint64_t)a.G * a.G * a.G * (uint64_t)(a.nslot * (a.fp64 ? 8 : 2)) <= (1ull << 32);

@@ -19,6 +19,30 @@ __device__ __forceinline__ int64_t xcd_chunk(int64_t b, int64_t nb) {
   return (b % 8) * per + b / 8;
 }
 
+// Several segments (species) in one launch: each XCD takes the same share of
+// every segment, a contiguous eighth of its chunks, and walks its shares in
+// segment order.  A contiguous eighth of the whole chunk range would give
+// whole species to single XCDs, and species whose particles cost more (sparse
+// seeds, whose gathers share few mesh lines) would hold the launch on those
+// XCDs.  -1: a block past its XCD's share (the grid is 8 times the largest).
+__device__ __forceinline__ int64_t xcd_segment_chunk(const PushArgs& a, int64_t b) {
+  const int64_t x = b & 7;
+  int64_t l = b >> 3;
+  for (int s = 0; s < a.nseg; ++s) {
+    const int64_t cb = a.seg[s].chunk_begin;
+    const int64_t n = (s + 1 < a.nseg ? a.seg[s + 1].chunk_begin : a.total_chunks) - cb;
+    const int64_t lo = n * x / 8, hi = n * (x + 1) / 8;
+    if (l < hi - lo) return cb + lo + l;
+    l -= hi - lo;
+  }
+  return -1;
+}
+
+// The chunk of this block in a non-persistent launch, or -1.
+__device__ __forceinline__ int64_t launch_chunk(const PushArgs& a) {
+  return a.xcd_blocks > 0 ? xcd_segment_chunk(a, blockIdx.x) : xcd_chunk(blockIdx.x, gridDim.x);
+}
+
 __device__ __forceinline__ int find_segment(const Segment* seg, int nseg, int64_t chunk) {
   int s = 0;
   while (s + 1 < nseg && seg[s + 1].chunk_begin <= chunk) ++s;

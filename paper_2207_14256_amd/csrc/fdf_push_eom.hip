@@ -277,7 +277,11 @@ __device__ __forceinline__ void push_chunk_eom_f64(const PushArgs& a, int64_t ch
 
 template <int NSLOT, int PPT, bool BLEND, bool TSC>
 __global__ void __launch_bounds__(kBlock) k_push_eom_f32(PushArgs a) {
-  if (!a.persistent) { push_chunk_eom_f32<NSLOT, PPT, BLEND, TSC>(a, xcd_chunk(blockIdx.x, gridDim.x)); return; }
+  if (!a.persistent) {
+    const int64_t c = launch_chunk(a);
+    if (c >= 0) push_chunk_eom_f32<NSLOT, PPT, BLEND, TSC>(a, c);
+    return;
+  }
   const int64_t per = (a.total_chunks + 7) / 8, x = blockIdx.x % 8, stride = gridDim.x / 8;
   const int64_t end = min((x + 1) * per, a.total_chunks);
   for (int64_t c = x * per + blockIdx.x / 8; c < end; c += stride) push_chunk_eom_f32<NSLOT, PPT, BLEND, TSC>(a, c);
@@ -285,7 +289,11 @@ __global__ void __launch_bounds__(kBlock) k_push_eom_f32(PushArgs a) {
 
 template <int NSLOT, int PPT, bool BLEND, bool TSC>
 __global__ void __launch_bounds__(kBlock) k_push_eom_f64(PushArgs a) {
-  if (!a.persistent) { push_chunk_eom_f64<NSLOT, PPT, BLEND, TSC>(a, xcd_chunk(blockIdx.x, gridDim.x)); return; }
+  if (!a.persistent) {
+    const int64_t c = launch_chunk(a);
+    if (c >= 0) push_chunk_eom_f64<NSLOT, PPT, BLEND, TSC>(a, c);
+    return;
+  }
   const int64_t per = (a.total_chunks + 7) / 8, x = blockIdx.x % 8, stride = gridDim.x / 8;
   const int64_t end = min((x + 1) * per, a.total_chunks);
   for (int64_t c = x * per + blockIdx.x / 8; c < end; c += stride) push_chunk_eom_f64<NSLOT, PPT, BLEND, TSC>(a, c);
@@ -293,7 +301,7 @@ __global__ void __launch_bounds__(kBlock) k_push_eom_f64(PushArgs a) {
 
 template <int PPT, bool BLEND, bool TSC>
 void eom_launch(const PushArgs& a, hipStream_t s) {
-  const int64_t grid_blocks = a.persistent ? a.persistent : a.total_chunks;
+  const int64_t grid_blocks = a.persistent ? a.persistent : (a.xcd_blocks > 0 ? a.xcd_blocks : a.total_chunks);
   const dim3 grid((unsigned)grid_blocks), block(kBlock);
   if (a.fp64) {
     if (a.nslot == 8) hipLaunchKernelGGL((k_push_eom_f64<8, PPT, BLEND, TSC>), grid, block, a.lds_reserve, s, a);
