@@ -644,27 +644,59 @@ int sort_species(fdf_ctx* c, const std::vector<SortPrediction>& pred, const std:
   return launched(c, "sort");
 }
 
-// A re-sort carried out by the push of the step: per species, the rank pass
-// and scan, then the push that writes the updated state in sorted order into
-// the other copy (pa describes the step's push; its segment tables are
-// indexed per species here).  The rank passes are timed as sorting, the
+// A re-sort carried out by the push of the step: the due species in batches
+// of up to kMaxSortJobs (as many as the bucket-count buffer holds), each
+// batch ranked by one launch and scanned together, then pushed by one launch
+// that writes the updated state in sorted order into the other copy (pa
+// describes the step's push).  The rank passes are timed as sorting, the
 // pushes on their own.
 int sort_push_species(fdf_ctx* c, const std::vector<SortPrediction>& pred, const std::vector<char>& due,
                       const PushArgs& pa, size_t table) {
-  for (size_t i = 0; i < c->species.size(); ++i) {
-    if (!due[i]) continue;
-    SpeciesRec& s = c->species[i];
-    const SortArgs a = sort_args(c, s, pred[i].tau, pred[i].a_mid);
+  const size_t ns = c->species.size();
+  const int tiles = sort_tiles_of(c);
+  const int64_t nkeys = (int64_t)tiles * tiles * tiles;
+  const int64_t max_jobs = std::min<int64_t>(kMaxSortJobs, std::max<int64_t>(1, c->lay.sort_keys_max / nkeys));
+  const Segment* tables[2] = {(const Segment*)(c->ws + c->lay.seg), (const Segment*)(c->ws + c->lay.seg + table)};
+  size_t i = 0;
+  while (true) {
+    while (i < ns && !due[i]) ++i;
+    if (i >= ns) break;
+    SpeciesRec& s0 = c->species[i];
+    SortArgs a = sort_args(c, s0, pred[i].tau, pred[i].a_mid);
+    SortBatch& b = a.batch;
+    b = SortBatch{};
+    b.tables[0] = tables[0];
+    b.tables[1] = tables[1];
+    int64_t blocks = 0, base = 0;
+    std::vector<size_t> members;
+    std::vector<char> mesh(c->fields.size(), 0);
+    for (; i < ns && b.njobs < max_jobs; ++i) {
+      if (!due[i]) continue;
+      const SpeciesRec& s = c->species[i];
+      const int j = b.njobs++;
+      b.job_species[j] = (int32_t)i;
+      b.job_cur[j] = s.cur;
+      b.job_block[j] = blocks;
+      b.job_base[j] = base;
+      b.job_tau[j] = pred[i].tau;
+      b.job_ma[j] = s.m * pred[i].a_mid;
+      blocks += (s.n + kSortBlock - 1) / kSortBlock;
+      base += s.n;
+      members.push_back(i);
+      mesh[s.field] = 1;
+    }
+    b.job_block[b.njobs] = blocks;
     std::pair<hipEvent_t, hipEvent_t> ev;
     timing_begin(c, FDF_KERNEL_SORT, &ev);
-    launch_sort_rank(a, stream_of(c));
+    launch_sort_rank_batch(a, stream_of(c));
     timing_end(c, FDF_KERNEL_SORT, ev);
     PushArgs p = pa;
-    p.seg = (const Segment*)(c->ws + c->lay.seg + s.cur * table) + i;
-    p.dseg = (const Segment*)(c->ws + c->lay.seg + (s.cur ^ 1) * table) + i;
+    p.seg = tables[0];
+    p.seg_alt = tables[1];
+    p.dseg = nullptr;
     p.alt_mask = p.skip_mask = 0;
     p.nseg = 1;
-    p.total_chunks = (s.n + kSortBlock - 1) / kSortBlock;
+    p.total_chunks = blocks;
     p.xcd_blocks = 0;
     p.persistent = 0;
     p.ppt = c->sort_push_ppt;
@@ -673,14 +705,20 @@ int sort_push_species(fdf_ctx* c, const std::vector<SortPrediction>& pred, const
     p.sort_rank = a.rank;
     p.sort_bucket = a.bucket;
     p.sort_start = a.count;
+    p.sort_nkeys = nkeys;
+    p.sort_batch = b;
     timing_begin(c, FDF_KERNEL_PUSH_SORT, &ev);
     launch_push_sort(p, stream_of(c));
     timing_end(c, FDF_KERNEL_PUSH_SORT, ev);
-    timing_work(c, FDF_KERNEL_PUSH_SORT, s.n, 0, (int64_t)c->cfg.grid_n * c->cfg.grid_n * c->cfg.grid_n *
-                                                 (pa.blend ? 2 : 1));
-    s.cur ^= 1;
+    int64_t meshes = 0;
+    for (char r : mesh) meshes += r;
+    timing_work(c, FDF_KERNEL_PUSH_SORT, base, 0,
+                meshes * (int64_t)c->cfg.grid_n * c->cfg.grid_n * c->cfg.grid_n * (pa.blend ? 2 : 1));
+    for (size_t m : members) c->species[m].cur ^= 1;
+    const int rc = launched(c, "sort + push");
+    if (rc) return rc;
   }
-  return launched(c, "sort + push");
+  return FDF_OK;
 }
 
 // Grid of the segment-balanced XCD mapping of a launch over every species

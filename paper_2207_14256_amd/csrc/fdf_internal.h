@@ -103,6 +103,58 @@ struct Segment {
   int64_t chunk_begin;     // first chunk of this segment in the launch
 };
 
+// Particles per block of the sort's rank pass.
+constexpr int kSortBlock = 1024;
+
+// A batched re-sort (FP32 separable form): the species due at one step are
+// ranked by one launch, scanned together and moved by one fused push launch.
+// Job j is species job_species[j], whose current state is in copy
+// job_cur[j] of the segment tables; its rank blocks (kSortBlock particles
+// each) are [job_block[j], job_block[j + 1]); its bucket counts are
+// count + j nkeys, scanned together with the other jobs' so that its bucket
+// starts are offset by job_base[j] (the particles of the jobs before it), and
+// its rank-pass outputs are rank, bucket and src + job_base[j].
+constexpr int kMaxSortJobs = 16;
+struct SortBatch {
+  int32_t njobs;           // 0: not batched (SortArgs.seg, one species)
+  int32_t job_species[kMaxSortJobs];
+  int32_t job_cur[kMaxSortJobs];
+  int64_t job_block[kMaxSortJobs + 1];
+  int64_t job_base[kMaxSortJobs];
+  double job_tau[kMaxSortJobs];   // predict_tau of the job's species
+  double job_ma[kMaxSortJobs];    // m a of the job's species
+  const Segment* tables[2];       // device segment tables, copies 0 and 1
+};
+
+// Block b of a batched launch: each XCD (b mod 8) takes a contiguous eighth
+// of every job's blocks.  Returns the job and (*local) the block inside it,
+// or -1 for a block past its XCD's share (the grid is 8 times the largest).
+__device__ inline int batch_block(const SortBatch& sb, int64_t b, int64_t* local) {
+  const int64_t x = b & 7;
+  int64_t l = b >> 3;
+  for (int j = 0; j < sb.njobs; ++j) {
+    const int64_t n = sb.job_block[j + 1] - sb.job_block[j];
+    const int64_t lo = n * x / 8, hi = n * (x + 1) / 8;
+    if (l < hi - lo) { *local = lo + l; return j; }
+    l -= hi - lo;
+  }
+  return -1;
+}
+
+// Grid of a batched launch (host).
+inline int64_t batch_grid(const SortBatch& sb) {
+  int64_t most = 0;
+  for (int64_t x = 0; x < 8; ++x) {
+    int64_t share = 0;
+    for (int j = 0; j < sb.njobs; ++j) {
+      const int64_t n = sb.job_block[j + 1] - sb.job_block[j];
+      share += n * (x + 1) / 8 - n * x / 8;
+    }
+    most = most > share ? most : share;
+  }
+  return 8 * most;
+}
+
 struct PushArgs {
   const Segment* seg;      // device array: each species' segment in copy 0 of its state
   const Segment* seg_alt;  // the same in copy 1 (the other buffer of a sorting species)
@@ -138,10 +190,9 @@ struct PushArgs {
   const uint32_t* sort_rank;
   const uint32_t* sort_bucket;
   const uint32_t* sort_start;   // bucket starts (the scanned counts)
+  int64_t sort_nkeys;           // buckets per job (batched re-sort)
+  SortBatch sort_batch;         // batched re-sort: njobs > 0 (seg / seg_alt are the two tables)
 };
-
-// Particles per block of the sort's rank pass.
-constexpr int kSortBlock = 1024;
 
 struct SortArgs {
   Segment seg;             // source copy
@@ -160,6 +211,7 @@ struct SortArgs {
   uint32_t* bucket;        // [n] per sorted element: bucket
   uint32_t* src;           // [n] per sorted element: source slot inside the block
   int32_t id_only;         // move pass: move the ids alone (the caller re-samples the state by id)
+  SortBatch batch;         // rank pass over several species (batch.njobs > 0; seg, dst unused)
 };
 
 struct SampleArgs {
@@ -249,6 +301,7 @@ void launch_fill_zero(void* ptr, size_t bytes, hipStream_t s);
 int push_chunk_particles(int ppt);
 void launch_sort(const SortArgs& a, hipStream_t s);
 void launch_sort_rank(const SortArgs& a, hipStream_t s);   // counts, rank pass and scan, no move
+void launch_sort_rank_batch(const SortArgs& a, hipStream_t s);   // the same over a SortBatch
 void launch_push_sort(const PushArgs& a, hipStream_t s);
 size_t sort_scan_scratch_words(int64_t nkeys);
 

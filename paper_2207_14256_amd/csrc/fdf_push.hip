@@ -294,9 +294,28 @@ __global__ void __launch_bounds__(kSortBlock / PER) k_push_sort_f32(PushArgs a) 
   constexpr int kPer = PER;
   constexpr int kFusedThreads = kSortBlock / PER;
   __shared__ uint32_t st[10][kSortBlock];
-  const Segment& sg = a.seg[0];
-  const Segment& ds = a.dseg[0];
-  const int64_t i0 = xcd_chunk(blockIdx.x, gridDim.x) * (int64_t)kSortBlock;
+  // one species (sort_batch.njobs == 0: seg and dseg point at its entries),
+  // or one job of a batched re-sort (seg and seg_alt are the two tables)
+  const SortBatch& sb = a.sort_batch;
+  int64_t blk = xcd_chunk(blockIdx.x, gridDim.x), base = 0;
+  const Segment* sgp = a.seg;
+  const Segment* dsp = a.dseg;
+  const uint32_t* start = a.sort_start;
+  if (sb.njobs > 0) {
+    const int j = batch_block(sb, blockIdx.x, &blk);
+    if (j < 0) return;
+    const int cur = sb.job_cur[j], sp = sb.job_species[j];
+    sgp = (cur ? a.seg_alt : a.seg) + sp;
+    dsp = (cur ? a.seg : a.seg_alt) + sp;
+    base = sb.job_base[j];
+    start = a.sort_start + j * a.sort_nkeys;
+  }
+  const Segment& sg = *sgp;
+  const Segment& ds = *dsp;
+  const uint32_t* sort_src = a.sort_src + base;
+  const uint32_t* sort_bucket = a.sort_bucket + base;
+  const uint32_t* sort_rank = a.sort_rank + base;
+  const int64_t i0 = blk * (int64_t)kSortBlock;
   const int cnt = (int)min<int64_t>(kSortBlock, sg.n - i0);
   // the sort outputs and ids first: their latency (bucket, then its start)
   // overlaps the state loads and the gathers.  Elements past the end of the
@@ -307,9 +326,9 @@ __global__ void __launch_bounds__(kSortBlock / PER) k_push_sort_f32(PushArgs a) 
   for (int r = 0; r < kPer; ++r) {
     const int e = min((int)threadIdx.x + r * kFusedThreads, cnt - 1);
     const int64_t o = i0 + e;                  // element e of the sorted order; slot e of the block
-    src[r] = ldnt(&a.sort_src[o]);
-    bucket[r] = ldnt(&a.sort_bucket[o]);
-    rank[r] = ldnt(&a.sort_rank[o]);
+    src[r] = ldnt(&sort_src[o]);
+    bucket[r] = ldnt(&sort_bucket[o]);
+    rank[r] = ldnt(&sort_rank[o]);
     id[r] = ldnt(&sg.id[o]);
   }
   uint32_t xu[kPer][3];
@@ -326,7 +345,7 @@ __global__ void __launch_bounds__(kSortBlock / PER) k_push_sort_f32(PushArgs a) 
   }
   int64_t dst[kPer];
 #pragma unroll
-  for (int r = 0; r < kPer; ++r) dst[r] = (int64_t)a.sort_start[bucket[r]] + rank[r];
+  for (int r = 0; r < kPer; ++r) dst[r] = (int64_t)start[bucket[r]] - base + rank[r];
   const ConstF32 k = const_f32<BLEND>(a, sg);
   if constexpr (!BLEND && !TSC) {
     update_group_f32<NSLOT, kPer, OFF32>(k, true, xu, q0, dq);
@@ -543,7 +562,8 @@ void push_launch(const PushArgs& a, hipStream_t s) {
 
 template <bool BLEND, bool TSC, int PER>
 void push_sort_launch_per(const PushArgs& a, hipStream_t s) {
-  const dim3 grid((unsigned)a.total_chunks), block(kSortBlock / PER);
+  const dim3 grid((unsigned)(a.sort_batch.njobs > 0 ? batch_grid(a.sort_batch) : a.total_chunks)),
+      block(kSortBlock / PER);
   const bool off32 = (uint64_t)a.G * a.G * a.G * (uint64_t)(a.nslot * 2) <= (1ull << 32);
   if (off32) {
     if (a.nslot == 8) hipLaunchKernelGGL((k_push_sort_f32<8, BLEND, TSC, true, PER>), grid, block, a.lds_reserve, s, a);

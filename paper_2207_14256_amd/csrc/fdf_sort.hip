@@ -26,31 +26,63 @@ __device__ __forceinline__ uint32_t part1by2(uint32_t v) {   // spread 10 bits t
   return v;
 }
 
+// The species a rank block belongs to: its state arrays, prediction and
+// outputs (one species, or one job of a batched re-sort).
+struct RankView {
+  const uint32_t* xu[3];
+  const float* q0f[3];
+  const float* dqf[3];
+  const double* xd[3];
+  const double* qd[3];
+  int64_t n;
+  double tau, ma;
+  uint32_t* count;
+  uint32_t* rank;
+  uint32_t* bucket;
+  uint32_t* src;
+};
+
+__device__ __forceinline__ RankView view_of(const Segment& g, double tau, double ma, uint32_t* count,
+                                            uint32_t* rank, uint32_t* bucket, uint32_t* src) {
+  RankView v;
+  for (int d = 0; d < 3; ++d) {
+    v.xu[d] = g.xu[d]; v.q0f[d] = g.q0f[d]; v.dqf[d] = g.dqf[d]; v.xd[d] = g.xd[d]; v.qd[d] = g.qd[d];
+  }
+  v.n = g.n;
+  v.tau = tau;
+  v.ma = ma;
+  v.count = count;
+  v.rank = rank;
+  v.bucket = bucket;
+  v.src = src;
+  return v;
+}
+
 // Full key of particle i: Morton index of its coarse tile (the counting-sort
 // bucket) above the Morton index of its cell inside the tile.  The position
 // is extrapolated along the particle's current velocity to the middle of the
 // interval until the next re-sort: neighbours in that order stay within half
 // an interval's drift of each other over the whole interval, instead of a
 // whole interval's drift by its end.
-__device__ __forceinline__ uint32_t full_key(const SortArgs& a, int64_t i) {
+__device__ __forceinline__ uint32_t full_key(const SortArgs& a, const RankView& g, int64_t i) {
   uint32_t c[3];
   if (a.fp64) {
     const double s = (double)a.grid_n / a.box;
     double v[3] = {0.0, 0.0, 0.0};
-    if (a.predict_tau != 0.0) {
-      const double q[3] = {a.seg.qd[0][i], a.seg.qd[1][i], a.seg.qd[2][i]};
-      const double f = a.predict_tau / sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + a.ma * a.ma);
+    if (g.tau != 0.0) {
+      const double q[3] = {g.qd[0][i], g.qd[1][i], g.qd[2][i]};
+      const double f = g.tau / sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + g.ma * g.ma);
       for (int d = 0; d < 3; ++d) v[d] = q[d] * f;
     }
     for (int d = 0; d < 3; ++d)
-      c[d] = (uint32_t)(int64_t)floor((a.seg.xd[d][i] + v[d]) * s) & (uint32_t)(a.grid_n - 1);
+      c[d] = (uint32_t)(int64_t)floor((g.xd[d][i] + v[d]) * s) & (uint32_t)(a.grid_n - 1);
   } else {
-    uint32_t x[3] = {a.seg.xu[0][i], a.seg.xu[1][i], a.seg.xu[2][i]};
-    if (a.predict_tau != 0.0) {
+    uint32_t x[3] = {g.xu[0][i], g.xu[1][i], g.xu[2][i]};
+    if (g.tau != 0.0) {
       float q[3];
-      for (int d = 0; d < 3; ++d) q[d] = a.seg.q0f[d][i] + a.seg.dqf[d][i];
-      const float ma = (float)a.ma;
-      const float f = (float)(a.predict_tau * 4294967296.0 / a.box) /
+      for (int d = 0; d < 3; ++d) q[d] = g.q0f[d][i] + g.dqf[d][i];
+      const float ma = (float)g.ma;
+      const float f = (float)(g.tau * 4294967296.0 / a.box) /
                       sqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + ma * ma);
       for (int d = 0; d < 3; ++d) x[d] += (uint32_t)__float2int_rn(q[d] * f);   // wraps with the box
     }
@@ -151,16 +183,15 @@ __device__ __forceinline__ void bitonic_block(W (&v)[4], W* lds, int tid) {
 // When the block's keys span less than 2^22 (spatially compact blocks, the
 // common case once sorted), the network runs on 32-bit words of (key - the
 // block's smallest key, slot), half the work of the 64-bit words.
-__global__ void __launch_bounds__(kRankThreads) k_sort_rank(SortArgs a) {
+__device__ __forceinline__ void rank_block(const SortArgs& a, const RankView& g, int64_t blk) {
   static_assert(kRankBlock == 4 * kRankThreads, "four elements per thread");
   __shared__ uint64_t kv[kRankBlock];
   __shared__ uint32_t seg_start[kRankBlock];
   __shared__ uint32_t seg_base[kRankBlock];
   __shared__ uint32_t wave_max[kRankThreads / 64];
   __shared__ uint64_t wave_kmin[kRankThreads / 64], wave_kmax[kRankThreads / 64];
-  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
   const int64_t i0 = blk * kRankBlock;
-  const int cnt = (int)min<int64_t>(kRankBlock, a.seg.n - i0);
+  const int cnt = (int)min<int64_t>(kRankBlock, g.n - i0);
   const int tid = threadIdx.x;
   const int lane = tid & 63, wid = tid >> 6;
   // keys read coalesced (element tid + 256 r)
@@ -169,7 +200,7 @@ __global__ void __launch_bounds__(kRankThreads) k_sort_rank(SortArgs a) {
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int e = tid + kRankThreads * r;
-    key[r] = e < cnt ? (uint64_t)full_key(a, i0 + e) : kNoKey;
+    key[r] = e < cnt ? (uint64_t)full_key(a, g, i0 + e) : kNoKey;
     if (e < cnt) { kmin = min(kmin, key[r]); kmax = max(kmax, key[r]); }
   }
 #pragma unroll
@@ -252,7 +283,7 @@ __global__ void __launch_bounds__(kRankThreads) k_sort_rank(SortArgs a) {
     const bool last = e == kRankBlock - 1 || (kv[e + 1] >> sh) != (kv[e] >> sh);
     if (last && key != kNoKey) {
       const uint32_t st = seg_start[e];
-      seg_base[st] = atomicAdd(&a.count[(uint32_t)(key >> (3 * a.fine_bits))], (uint32_t)(e - st + 1));
+      seg_base[st] = atomicAdd(&g.count[(uint32_t)(key >> (3 * a.fine_bits))], (uint32_t)(e - st + 1));
     }
   }
   __syncthreads();
@@ -261,12 +292,29 @@ __global__ void __launch_bounds__(kRankThreads) k_sort_rank(SortArgs a) {
     const int e = 4 * tid + r;
     const uint64_t key = kv[e] >> 10;
     const int64_t o = i0 + e;
-    if (o >= a.seg.n) continue;   // sentinels sort last: e < n - i0 holds real particles
+    if (o >= g.n) continue;   // sentinels sort last: e < n - i0 holds real particles
     const uint32_t st = seg_start[e];
-    a.src[o] = (uint32_t)(kv[e] & kIdxMask);
-    a.rank[o] = seg_base[st] + (uint32_t)(e - st);
-    a.bucket[o] = (uint32_t)(key >> (3 * a.fine_bits));
+    g.src[o] = (uint32_t)(kv[e] & kIdxMask);
+    g.rank[o] = seg_base[st] + (uint32_t)(e - st);
+    g.bucket[o] = (uint32_t)(key >> (3 * a.fine_bits));
   }
+}
+
+// One species (batch.njobs == 0), or one block of a batched re-sort.
+__global__ void __launch_bounds__(kRankThreads) k_sort_rank(SortArgs a) {
+  if (a.batch.njobs == 0) {
+    rank_block(a, view_of(a.seg, a.predict_tau, a.ma, a.count, a.rank, a.bucket, a.src),
+               xcd_block(blockIdx.x, gridDim.x));
+    return;
+  }
+  int64_t local;
+  const int j = batch_block(a.batch, blockIdx.x, &local);
+  if (j < 0) return;
+  const SortBatch& b = a.batch;
+  const Segment& g = b.tables[b.job_cur[j]][b.job_species[j]];
+  const int64_t base = b.job_base[j];
+  rank_block(a, view_of(g, b.job_tau[j], b.job_ma[j], a.count + j * a.nkeys, a.rank + base, a.bucket + base,
+                        a.src + base), local);
 }
 
 // Move pass, one 1024-block at a time and one state array at a time: the
@@ -419,6 +467,14 @@ void launch_sort_rank(const SortArgs& a, hipStream_t s) {
   launch_fill_zero(a.count, ((size_t)a.nkeys * 4 + 15) / 16 * 16, s);
   hipLaunchKernelGGL(k_sort_rank, dim3((unsigned)((n + kRankBlock - 1) / kRankBlock)), dim3(kRankThreads), 0, s, a);
   scan_exclusive(a.count, a.nkeys, a.scan_scratch, s);   // bucket counts -> bucket starts
+}
+
+// Batched rank pass: counts of every job cleared, ranked, scanned together.
+void launch_sort_rank_batch(const SortArgs& a, hipStream_t s) {
+  const int64_t keys = a.nkeys * a.batch.njobs;
+  launch_fill_zero(a.count, ((size_t)keys * 4 + 15) / 16 * 16, s);
+  hipLaunchKernelGGL(k_sort_rank, dim3((unsigned)batch_grid(a.batch)), dim3(kRankThreads), 0, s, a);
+  scan_exclusive(a.count, keys, a.scan_scratch, s);
 }
 
 void launch_sort(const SortArgs& a, hipStream_t s) {
