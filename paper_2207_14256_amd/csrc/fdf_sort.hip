@@ -117,10 +117,31 @@ __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int mask) {
   return ((uint64_t)hi << 32) | lo;
 }
 
+// Value of lane (this lane xor mask).  The network's masks are compile-time
+// constants after unrolling: 1 and 2 are quad permutations and 4 and 8 two row
+// shifts and a select, all DPP moves on the vector ALU; 16 is a swizzle inside
+// 32 lanes; only 32 goes through the LDS crossbar (bpermute).  Row shifts: lane
+// i of row_shl:n reads lane i + n of its row of 16, row_shr:n lane i - n.
 __device__ __forceinline__ uint32_t shfl_xor_word(uint32_t v, int mask) {
-  return (uint32_t)__shfl_xor((int)v, mask, 64);
+  const int x = (int)v;
+  if (mask == 1) return (uint32_t)__builtin_amdgcn_mov_dpp(x, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+  if (mask == 2) return (uint32_t)__builtin_amdgcn_mov_dpp(x, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+  if (mask == 4) {
+    const int up = __builtin_amdgcn_mov_dpp(x, 0x104, 0xF, 0xF, false);   // row_shl:4
+    const int dn = __builtin_amdgcn_mov_dpp(x, 0x114, 0xF, 0xF, false);   // row_shr:4
+    return (uint32_t)((__lane_id() & 4) ? dn : up);
+  }
+  if (mask == 8) {
+    const int up = __builtin_amdgcn_mov_dpp(x, 0x108, 0xF, 0xF, false);   // row_shl:8
+    const int dn = __builtin_amdgcn_mov_dpp(x, 0x118, 0xF, 0xF, false);   // row_shr:8
+    return (uint32_t)((__lane_id() & 8) ? dn : up);
+  }
+  if (mask == 16) return (uint32_t)__builtin_amdgcn_ds_swizzle(x, 0x401F);   // and 0x1f, xor 0x10
+  return (uint32_t)__shfl_xor(x, mask, 64);
 }
-__device__ __forceinline__ uint64_t shfl_xor_word(uint64_t v, int mask) { return shfl_xor_u64(v, mask); }
+__device__ __forceinline__ uint64_t shfl_xor_word(uint64_t v, int mask) {
+  return ((uint64_t)shfl_xor_word((uint32_t)(v >> 32), mask) << 32) | shfl_xor_word((uint32_t)v, mask);
+}
 
 // Bitonic sort of the block's 1024 words, thread t holding sorted positions
 // 4t .. 4t + 3 in registers.  Element e = 4 tid + r keeps the smaller of its
