@@ -199,6 +199,13 @@ typedef struct fdf_tuning {
   int32_t sort_push_ppt;         /* push that carries out a re-sort: particles per
                                     thread (1, 2 or 4; 0 selects 4) of its
                                     1024-particle blocks */
+  int32_t sort_keys_push;        /* 1 (the default): with one species, CIC, no
+                                    super-steps and no graph, the plain push of the
+                                    step before a re-sort in the same fdf_step call
+                                    also writes the particles' sort keys, which the
+                                    rank pass then reads instead of the state (4
+                                    instead of 36 bytes per particle; results
+                                    bit-identical); 0: the rank pass computes them */
 } fdf_tuning;
 
 /* ---- lifetime -------------------------------------------------------------- */

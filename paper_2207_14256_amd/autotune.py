@@ -71,7 +71,7 @@ def autotune(cfg, path=CACHE_PATH, log=print, full_schedule=True):
     sorting = cfg.get("sort_every", 0) > 0
     base = dict(particles_per_thread=4, sort_tiles=0, sort_every=cfg.get("sort_every", 0),
                 sort_cells=3.0 if sorting else 0.0, persistent_blocks=0, use_graph=0, sort_predict=1,
-                sort_fused=1, push_waves=0, sort_push_ppt=1)
+                sort_fused=1, push_waves=0, sort_push_ppt=1, sort_keys_push=1)
     # 1. launch shape: particles per thread and the cap on resident waves,
     #    timed over the whole schedule (the mesh locality of the gathers, and
     #    with it the best shape, changes as the particles disperse), scored

@@ -352,6 +352,7 @@ struct fdf_ctx {
   bool sort_fused = true;   // FP32 separable: re-sorts after the first ride on the push
   int push_waves = 0;       // cap on resident push waves per SIMD (0: none)
   int sort_push_ppt = 4;    // particles per thread of the fused re-sort push
+  bool sort_keys_push = true;   // the push before a re-sort writes the sort keys
   hipStream_t cap_stream = nullptr;   // private stream used only for graph capture
   hipStream_t launch_stream = nullptr;  // stream kernels are enqueued on right now
   std::vector<GraphRec> graphs;       // captured step sequences
@@ -649,9 +650,10 @@ int sort_species(fdf_ctx* c, const std::vector<SortPrediction>& pred, const std:
 // batch ranked by one launch and scanned together, then pushed by one launch
 // that writes the updated state in sorted order into the other copy (pa
 // describes the step's push).  The rank passes are timed as sorting, the
-// pushes on their own.
+// pushes on their own.  keyed: the push of the previous step has written the
+// (single) due species' sort keys.
 int sort_push_species(fdf_ctx* c, const std::vector<SortPrediction>& pred, const std::vector<char>& due,
-                      const PushArgs& pa, size_t table) {
+                      const PushArgs& pa, size_t table, bool keyed) {
   const size_t ns = c->species.size();
   const int tiles = sort_tiles_of(c);
   const int64_t nkeys = (int64_t)tiles * tiles * tiles;
@@ -686,6 +688,9 @@ int sort_push_species(fdf_ctx* c, const std::vector<SortPrediction>& pred, const
       mesh[s.field] = 1;
     }
     b.job_block[b.njobs] = blocks;
+    // keys written by the previous push (one species) sit in the rank array
+    // itself: each rank block reads its keys before it writes its ranks
+    if (keyed && b.njobs == 1) a.keys = a.rank;
     std::pair<hipEvent_t, hipEvent_t> ev;
     timing_begin(c, FDF_KERNEL_SORT, &ev);
     launch_sort_rank_batch(a, stream_of(c));
@@ -1199,8 +1204,12 @@ int enqueue_steps(fdf_ctx* c, int32_t n) {
     p.tau = c->sort_predict ? 0.5 * span : 0.0;
     return p;
   };
-  std::vector<char> due(ns, 0);
+  std::vector<char> due(ns, 0), due_next(ns, 0);
   std::vector<SortPrediction> pred(ns);
+  // the plain push before a re-sort may write the sort keys (one species)
+  const bool key_fusable = c->sort_keys_push && c->sort_fused && !pa.fp64 && pa.eom == FDF_EOM_SEPARABLE &&
+                           !pa.tsc && c->anchors.empty() && !c->use_graph && ns == 1 && n > 0;
+  bool keyed = false;           // this step's re-sort reads keys written by the previous push
   for (int j = 0; j <= nabs; ++j) {
     int t;            // integer time of this launch's kick
     double kclose = 0, kopen = 0, drift = 0, a_drift = 0;   // half-kicks ending / starting at t
@@ -1295,9 +1304,24 @@ int enqueue_steps(fdf_ctx* c, int32_t n) {
     int64_t pushed = 0;           // particles of the plain launch, and the meshes it reads
     std::vector<char> mesh_read(c->fields.size(), 0);
     if (fused_sort) {
-      rc = sort_push_species(c, pred, due, pa, table);
+      rc = sort_push_species(c, pred, due, pa, table, keyed && due[0]);
       if (rc) return rc;
       for (size_t i = 0; i < ns; ++i) if (due[i]) pa.skip_mask |= 1ull << i;   // pushed already
+    }
+    keyed = false;
+    // write the sort keys in this push when the next launch of this call
+    // re-sorts the species and this launch pushes it (the keys are those of
+    // the state the rank pass would read)
+    pa.key_out = nullptr;
+    if (key_fusable && c->sorted_once && j + 1 < nabs && !(fused_sort && due[0]) &&
+        sorts_due(t + 1, &due_next) && due_next[0]) {
+      const SortPrediction pn = sort_prediction(t + 1, cadence_mass(0));
+      const SortArgs sa = sort_args(c, c->species[0], pn.tau, pn.a_mid);
+      pa.key_out = sa.rank;
+      pa.key_fine_bits = sa.fine_bits;
+      pa.key_tau = pn.tau;
+      pa.key_ma = sa.ma;
+      keyed = true;
     }
     for (size_t i = 0; i < ns; ++i) {
       if (fused_sort && due[i]) continue;
@@ -1316,6 +1340,7 @@ int enqueue_steps(fdf_ctx* c, int32_t n) {
       rc = launched(c, "push");
       if (rc) return rc;
     }
+    pa.key_out = nullptr;
     for (auto& s : c->species) s.pristine = false;
   }
   c->step_index = k0 + n;
@@ -1842,6 +1867,7 @@ int fdf_get_tuning(const fdf_ctx* c, fdf_tuning* t) {
   t->sort_fused = c->sort_fused ? 1 : 0;
   t->push_waves = c->push_waves;
   t->sort_push_ppt = c->sort_push_ppt;
+  t->sort_keys_push = c->sort_keys_push ? 1 : 0;
   return FDF_OK;
 }
 
@@ -1865,6 +1891,7 @@ int fdf_set_tuning(fdf_ctx* c, const fdf_tuning* t) {
     return fail(c, FDF_ERR_ARG, "push_waves must be 0 or in [2, 8]");
   if (t->sort_push_ppt != 0 && t->sort_push_ppt != 1 && t->sort_push_ppt != 2 && t->sort_push_ppt != 4)
     return fail(c, FDF_ERR_ARG, "sort_push_ppt must be 0, 1, 2 or 4");
+  if (t->sort_keys_push != 0 && t->sort_keys_push != 1) return fail(c, FDF_ERR_ARG, "sort_keys_push must be 0 or 1");
   if (p != c->ppt) c->seg_dirty = true;   // chunk boundaries depend on the block size
   clear_graphs(c);
   c->persistent = t->persistent_blocks;
@@ -1877,6 +1904,7 @@ int fdf_set_tuning(fdf_ctx* c, const fdf_tuning* t) {
   c->sort_fused = t->sort_fused != 0;
   c->push_waves = t->push_waves;
   c->sort_push_ppt = t->sort_push_ppt ? t->sort_push_ppt : 4;
+  c->sort_keys_push = t->sort_keys_push != 0;
   return FDF_OK;
 }
 

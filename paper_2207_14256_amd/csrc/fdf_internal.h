@@ -192,6 +192,12 @@ struct PushArgs {
   const uint32_t* sort_start;   // bucket starts (the scanned counts)
   int64_t sort_nkeys;           // buckets per job (batched re-sort)
   SortBatch sort_batch;         // batched re-sort: njobs > 0 (seg / seg_alt are the two tables)
+  // sort keys of the next step's re-sort, written by this (plain, FP32,
+  // one-species) push from the state it leaves: key_out[i] for particle slot i
+  uint32_t* key_out;            // or null
+  int32_t key_fine_bits;        // log2 of the bucket tile side in cells
+  double key_tau;               // predict_tau of the next re-sort
+  double key_ma;                // m a at the middle of its interval
 };
 
 struct SortArgs {
@@ -212,6 +218,7 @@ struct SortArgs {
   uint32_t* src;           // [n] per sorted element: source slot inside the block
   int32_t id_only;         // move pass: move the ids alone (the caller re-samples the state by id)
   SortBatch batch;         // rank pass over several species (batch.njobs > 0; seg, dst unused)
+  const uint32_t* keys;    // rank pass: keys written by the previous push (one species), or null
 };
 
 struct SampleArgs {

@@ -27,6 +27,7 @@
 // The separable form is the one implemented here; the other equations of
 // motion (fdf_push_eom.hip) take over when PushArgs::eom is set.
 #include "fdf_push_common.h"
+#include "fdf_key.h"
 
 namespace fdf {
 namespace {
@@ -225,7 +226,7 @@ __device__ __forceinline__ void update_group_f32(const ConstF32& k, bool drift, 
 // Particles per gather group of a PPT-particle thread.
 template <int PPT> struct GatherGroup { static constexpr int N = PPT < 4 ? PPT : 4; };
 
-template <int NSLOT, int PPT, bool BLEND, bool TSC, bool OFF32>
+template <int NSLOT, int PPT, bool BLEND, bool TSC, bool OFF32, bool KEY>
 __device__ __forceinline__ void push_chunk_f32(const PushArgs& a, int64_t chunk) {
   bool skip;
   const Segment& sg = chunk_segment(a, chunk, &skip);
@@ -277,6 +278,17 @@ __device__ __forceinline__ void push_chunk_f32(const PushArgs& a, int64_t chunk)
     }
 #pragma unroll
     for (int d = 0; d < 3; ++d) stnt(dq[p][d], &DQ[d][i]);
+  }
+  if constexpr (KEY) {   // sort keys of the next step's re-sort, from the state just stored
+    const float ma = (float)a.key_ma, ts = (float)(a.key_tau * 4294967296.0 / a.box);
+    uint32_t* K = a.key_out + c0;
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+      const uint32_t i = threadIdx.x + (uint32_t)(p * kBlock);
+      if ((int64_t)i >= left) break;
+      const float q[3] = {q0[p][0] + dq[p][0], q0[p][1] + dq[p][1], q0[p][2] + dq[p][2]};
+      K[i] = sort_key::key_f32(xu[p], q, ma, ts, a.key_tau != 0.0, k.shift, a.key_fine_bits);
+    }
   }
 }
 
@@ -507,16 +519,17 @@ __device__ __forceinline__ void push_chunk_f64(const PushArgs& a, int64_t chunk)
 // Chunk loop.  One block per chunk, or (persistent) a fixed grid whose
 // blocks stride over the chunks; either way each XCD (block id mod 8) walks a
 // contiguous eighth of the chunk range.
-template <int NSLOT, int PPT, bool BLEND, bool TSC, bool OFF32>
+template <int NSLOT, int PPT, bool BLEND, bool TSC, bool OFF32, bool KEY = false>
 __global__ void __launch_bounds__(kBlock) k_push_f32(PushArgs a) {
   if (!a.persistent) {
     const int64_t c = launch_chunk(a);
-    if (c >= 0) push_chunk_f32<NSLOT, PPT, BLEND, TSC, OFF32>(a, c);
+    if (c >= 0) push_chunk_f32<NSLOT, PPT, BLEND, TSC, OFF32, KEY>(a, c);
     return;
   }
   const int64_t per = (a.total_chunks + 7) / 8, x = blockIdx.x % 8, stride = gridDim.x / 8;
   const int64_t end = min((x + 1) * per, a.total_chunks);
-  for (int64_t c = x * per + blockIdx.x / 8; c < end; c += stride) push_chunk_f32<NSLOT, PPT, BLEND, TSC, OFF32>(a, c);
+  for (int64_t c = x * per + blockIdx.x / 8; c < end; c += stride)
+    push_chunk_f32<NSLOT, PPT, BLEND, TSC, OFF32, KEY>(a, c);
 }
 
 template <int NSLOT, int PPT, bool BLEND, bool TSC, bool OFF32>
@@ -548,6 +561,20 @@ void push_launch(const PushArgs& a, hipStream_t s) {
       else hipLaunchKernelGGL((k_push_f64<4, PPT, BLEND, TSC, false>), grid, block, a.lds_reserve, s, a);
     }
   } else {
+    if constexpr (!BLEND && !TSC) {
+      if (a.key_out) {   // this push also writes the sort keys of the next step's re-sort
+        if (off32) {
+          if (a.nslot == 8) hipLaunchKernelGGL((k_push_f32<8, PPT, false, false, true, true>), grid, block, a.lds_reserve, s, a);
+          else if (a.nslot == 6) hipLaunchKernelGGL((k_push_f32<6, PPT, false, false, true, true>), grid, block, a.lds_reserve, s, a);
+          else hipLaunchKernelGGL((k_push_f32<4, PPT, false, false, true, true>), grid, block, a.lds_reserve, s, a);
+        } else {
+          if (a.nslot == 8) hipLaunchKernelGGL((k_push_f32<8, PPT, false, false, false, true>), grid, block, a.lds_reserve, s, a);
+          else if (a.nslot == 6) hipLaunchKernelGGL((k_push_f32<6, PPT, false, false, false, true>), grid, block, a.lds_reserve, s, a);
+          else hipLaunchKernelGGL((k_push_f32<4, PPT, false, false, false, true>), grid, block, a.lds_reserve, s, a);
+        }
+        return;
+      }
+    }
     if (off32) {
       if (a.nslot == 8) hipLaunchKernelGGL((k_push_f32<8, PPT, BLEND, TSC, true>), grid, block, a.lds_reserve, s, a);
       else if (a.nslot == 6) hipLaunchKernelGGL((k_push_f32<6, PPT, BLEND, TSC, true>), grid, block, a.lds_reserve, s, a);

@@ -13,18 +13,12 @@
 // depend on the order.  Particles keep their id.
 #include "fdf_device.h"
 #include "fdf_internal.h"
+#include "fdf_key.h"
 
 namespace fdf {
 namespace {
 
-__device__ __forceinline__ uint32_t part1by2(uint32_t v) {   // spread 10 bits to every third bit
-  v &= 0x3FFu;
-  v = (v | (v << 16)) & 0x030000FFu;
-  v = (v | (v << 8)) & 0x0300F00Fu;
-  v = (v | (v << 4)) & 0x030C30C3u;
-  v = (v | (v << 2)) & 0x09249249u;
-  return v;
-}
+using namespace sort_key;
 
 // The species a rank block belongs to: its state arrays, prediction and
 // outputs (one species, or one job of a batched re-sort).
@@ -36,15 +30,17 @@ struct RankView {
   const double* qd[3];
   int64_t n;
   double tau, ma;
+  const uint32_t* keys;    // precomputed keys of the species' particles, or null
   uint32_t* count;
   uint32_t* rank;
   uint32_t* bucket;
   uint32_t* src;
 };
 
-__device__ __forceinline__ RankView view_of(const Segment& g, double tau, double ma, uint32_t* count,
-                                            uint32_t* rank, uint32_t* bucket, uint32_t* src) {
+__device__ __forceinline__ RankView view_of(const Segment& g, double tau, double ma, const uint32_t* keys,
+                                            uint32_t* count, uint32_t* rank, uint32_t* bucket, uint32_t* src) {
   RankView v;
+  v.keys = keys;
   for (int d = 0; d < 3; ++d) {
     v.xu[d] = g.xu[d]; v.q0f[d] = g.q0f[d]; v.dqf[d] = g.dqf[d]; v.xd[d] = g.xd[d]; v.qd[d] = g.qd[d];
   }
@@ -65,8 +61,9 @@ __device__ __forceinline__ RankView view_of(const Segment& g, double tau, double
 // an interval's drift of each other over the whole interval, instead of a
 // whole interval's drift by its end.
 __device__ __forceinline__ uint32_t full_key(const SortArgs& a, const RankView& g, int64_t i) {
-  uint32_t c[3];
+  if (g.keys) return g.keys[i];   // written by the push before this re-sort
   if (a.fp64) {
+    uint32_t c[3];
     const double s = (double)a.grid_n / a.box;
     double v[3] = {0.0, 0.0, 0.0};
     if (g.tau != 0.0) {
@@ -76,23 +73,14 @@ __device__ __forceinline__ uint32_t full_key(const SortArgs& a, const RankView& 
     }
     for (int d = 0; d < 3; ++d)
       c[d] = (uint32_t)(int64_t)floor((g.xd[d][i] + v[d]) * s) & (uint32_t)(a.grid_n - 1);
-  } else {
-    uint32_t x[3] = {g.xu[0][i], g.xu[1][i], g.xu[2][i]};
-    if (g.tau != 0.0) {
-      float q[3];
-      for (int d = 0; d < 3; ++d) q[d] = g.q0f[d][i] + g.dqf[d][i];
-      const float ma = (float)g.ma;
-      const float f = (float)(g.tau * 4294967296.0 / a.box) /
-                      sqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + ma * ma);
-      for (int d = 0; d < 3; ++d) x[d] += (uint32_t)__float2int_rn(q[d] * f);   // wraps with the box
-    }
-    for (int d = 0; d < 3; ++d) c[d] = x[d] >> a.cell_shift;
+    return morton_key(c, a.fine_bits);
   }
-  const int fb = a.fine_bits;                       // log2 of the tile side in cells
-  const uint32_t fm = (1u << fb) - 1u;
-  const uint32_t coarse = (part1by2(c[0] >> fb) << 2) | (part1by2(c[1] >> fb) << 1) | part1by2(c[2] >> fb);
-  const uint32_t fine = (part1by2(c[0] & fm) << 2) | (part1by2(c[1] & fm) << 1) | part1by2(c[2] & fm);
-  return (coarse << (3 * fb)) | fine;
+  const uint32_t x[3] = {g.xu[0][i], g.xu[1][i], g.xu[2][i]};
+  float q[3] = {0.0f, 0.0f, 0.0f};
+  if (g.tau != 0.0)
+    for (int d = 0; d < 3; ++d) q[d] = g.q0f[d][i] + g.dqf[d][i];
+  return key_f32(x, q, (float)g.ma, (float)(g.tau * 4294967296.0 / a.box), g.tau != 0.0, a.cell_shift,
+                 a.fine_bits);
 }
 
 // Blocks are dispatched round-robin over the 8 XCDs; remap so each XCD (own
@@ -324,7 +312,7 @@ __device__ __forceinline__ void rank_block(const SortArgs& a, const RankView& g,
 // One species (batch.njobs == 0), or one block of a batched re-sort.
 __global__ void __launch_bounds__(kRankThreads) k_sort_rank(SortArgs a) {
   if (a.batch.njobs == 0) {
-    rank_block(a, view_of(a.seg, a.predict_tau, a.ma, a.count, a.rank, a.bucket, a.src),
+    rank_block(a, view_of(a.seg, a.predict_tau, a.ma, a.keys, a.count, a.rank, a.bucket, a.src),
                xcd_block(blockIdx.x, gridDim.x));
     return;
   }
@@ -334,8 +322,8 @@ __global__ void __launch_bounds__(kRankThreads) k_sort_rank(SortArgs a) {
   const SortBatch& b = a.batch;
   const Segment& g = b.tables[b.job_cur[j]][b.job_species[j]];
   const int64_t base = b.job_base[j];
-  rank_block(a, view_of(g, b.job_tau[j], b.job_ma[j], a.count + j * a.nkeys, a.rank + base, a.bucket + base,
-                        a.src + base), local);
+  rank_block(a, view_of(g, b.job_tau[j], b.job_ma[j], a.keys ? a.keys + base : nullptr, a.count + j * a.nkeys,
+                        a.rank + base, a.bucket + base, a.src + base), local);
 }
 
 // Move pass, one 1024-block at a time and one state array at a time: the

@@ -69,7 +69,8 @@ class Tuning(ctypes.Structure):
                 ("persistent_blocks", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("sort_predict", ctypes.c_int32),
                 ("sort_fused", ctypes.c_int32),
-                ("push_waves", ctypes.c_int32), ("sort_push_ppt", ctypes.c_int32)]
+                ("push_waves", ctypes.c_int32), ("sort_push_ppt", ctypes.c_int32),
+                ("sort_keys_push", ctypes.c_int32)]
 
 
 class FastDFError(RuntimeError):
@@ -370,7 +371,7 @@ class Context:
                     sort_every=t.sort_every, sort_cells=t.sort_cells,
                     persistent_blocks=t.persistent_blocks, use_graph=t.use_graph,
                     sort_predict=t.sort_predict, sort_fused=t.sort_fused, push_waves=t.push_waves,
-                    sort_push_ppt=t.sort_push_ppt)
+                    sort_push_ppt=t.sort_push_ppt, sort_keys_push=t.sort_keys_push)
 
     def set_tuning(self, **kw):
         cur = self.get_tuning()
@@ -378,7 +379,7 @@ class Context:
         t = Tuning(cur["particles_per_thread"], cur["sort_tiles"], cur["sort_every"],
                    float(cur["sort_cells"]), int(cur["persistent_blocks"]), int(cur["use_graph"]),
                    int(cur["sort_predict"]), int(cur["sort_fused"]), int(cur["push_waves"]),
-                   int(cur.get("sort_push_ppt", 4)))
+                   int(cur.get("sort_push_ppt", 4)), int(cur.get("sort_keys_push", 1)))
         self._check(self.lib.fdf_set_tuning(self.ctx, ctypes.byref(t)), "fdf_set_tuning")
 
     def sync(self):

@@ -218,3 +218,33 @@ def test_padded_mesh_bit_identical(order):
         out.append((x, q, w, g, p))
     for a, b in zip(*out):
         assert np.array_equal(a, b, equal_nan=True)
+
+
+@pytest.mark.parametrize("ppt", [4, 8])
+def test_sort_keys_from_push_bit_identical(ppt):
+    """With one species, the push before each re-sort writes the sort keys
+    (sort_keys_push): every result by id equals the run whose rank passes
+    compute the keys and the never-sorted run, for a particle count that is
+    not a multiple of the rank block, in one call and in split calls (the
+    first re-sort of a call computes its keys itself)."""
+    print("[gpu-case] sort keys from push ppt=%d" % ppt, flush=True)
+    cfg = workloads.small("c3", grid_n=32, n_side=37, n_steps=200, z_begin=1e9, z_end=3.0)
+    ref = _state_by_id(dict(cfg, sort_every=0), dict(sort_every=0))
+    base = dict(sort_every=1, sort_cells=0.7, particles_per_thread=ppt)
+    for keys in (1, 0):
+        got = _state_by_id(cfg, dict(base, sort_keys_push=keys))
+        for a, b in zip(got, ref):
+            assert np.array_equal(a, b), keys
+    # split calls (each call applies its closing half-kick on its own, so the
+    # reference is the never-sorted run split the same way)
+    split = {}
+    for key, c, t in (("ref", dict(cfg, sort_every=0), dict(sort_every=0)),
+                      ("keys", cfg, dict(base, sort_keys_push=1))):
+        ctx, fields, species = fastdf.setup_workload(c, tuning=t)
+        for k in (37, 63, 100):
+            ctx.step(k)
+        x, q = ctx.read_state(species[0])
+        split[key] = (x, q, ctx.weights(species[0]).cpu().numpy())
+        ctx.close()
+    for a, b in zip(split["keys"], split["ref"]):
+        assert np.array_equal(a, b)
