@@ -283,7 +283,10 @@ int fdf_weights(struct fdf_ctx* ctx, int32_t species_id, double* d_w);
  * the weight <eps>_s(a) / sum_s <eps>_s.  The species must share one field and
  * appear once each (FDF_ERR_ARG otherwise).  Host outputs of n_bins doubles:
  * mean |k| [1/Mpc], P(k) [Mpc^3] (NaN for an empty bin) and the number of
- * modes. */
+ * modes.  The bin sums are exact fixed-point sums in both forms, and the FP32
+ * form also deposits in fixed point, so its spectrum is the same bit for bit
+ * from run to run, whatever the launch shape, sort cadence or particle
+ * order. */
 int fdf_density_power_spectrum(struct fdf_ctx* ctx, const int32_t* species, int32_t n_species,
                                int32_t n_bins, int32_t mode,
                                double* h_k, double* h_p, double* h_nmodes);
