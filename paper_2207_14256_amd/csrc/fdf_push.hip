@@ -20,9 +20,11 @@
 // CIC corner.
 // FP64 form: everything binary64; 8 slots = four 16-byte loads per corner.
 //
-// Blocks take contiguous chunks of one species, in an XCD-aware order.  On a
-// step that begins with a re-sort, k_push_sort_f32 pushes one species and
-// writes the updated state straight to its sorted slots.
+// Blocks take contiguous chunks of one species, in an XCD-aware order (with
+// several species, every XCD takes an eighth of each).  On a step that begins
+// with a re-sort, k_push_sort_f32 pushes the species due (one launch for all
+// of them) and writes their updated state straight to their sorted slots; the
+// plain push of the step before can also write their sort keys.
 //
 // The separable form is the one implemented here; the other equations of
 // motion (fdf_push_eom.hip) take over when PushArgs::eom is set.
@@ -292,8 +294,9 @@ __device__ __forceinline__ void push_chunk_f32(const PushArgs& a, int64_t chunk)
   }
 }
 
-// A push that also performs a re-sort of one species whose rank pass has run:
-// one block per rank block of kSortBlock particles.  The block reads its
+// A push that also performs the re-sort of the species whose rank pass has
+// run (one, or the jobs of a batch): one block per rank block of kSortBlock
+// particles.  The block reads its
 // particles in place (coalesced), updates them, stages the whole new state in
 // LDS and writes it out in sorted order, element e of the sorted run to
 // start[bucket[e]] + rank[e] of the other buffer copy, so consecutive threads
