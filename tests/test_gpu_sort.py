@@ -73,6 +73,12 @@ FUSED_CASES = {
                   model="radmat", omega_m=0.9999, omega_r=1e-4, slip_amp=0.0,
                   superstep_tol=0.01, interp_order=2),
         second=0, tuning=dict(sort_every=1, sort_cells=0.3)),
+    # super-steps with CIC: the grouped two-set gathers of both push kernels
+    "radmat-superstep-cic": dict(
+        base=dict(grid_n=16, n_side=21, n_steps=60, box_mpc=600.0, z_begin=1e6, z_end=10.0,
+                  model="radmat", omega_m=0.9999, omega_r=1e-4, slip_amp=0.01,
+                  superstep_tol=0.01, interp_order=1),
+        second=0, tuning=dict(sort_every=1, sort_cells=0.3, particles_per_thread=8)),
     # graph capture and replay of the fused launches
     "graph": dict(
         base=dict(grid_n=32, n_side=21, n_steps=60, box_mpc=600.0, z_begin=1e6, z_end=10.0),
